@@ -1,0 +1,482 @@
+/*
+ * FP64 CPU oracle of the immersed-boundary lattice Boltzmann (IB-LB) wetting
+ * model.  TEST INFRASTRUCTURE ONLY: nothing in the product path links,
+ * loads or calls this file; only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark do.  It shares no code, header, table or
+ * helper with the HIP library.
+ *
+ * Everything is plain loops in double precision, written to be checked by
+ * eye against the paper ("Immersed boundary - lattice Boltzmann method for
+ * wetting problems"):
+ *
+ *   velocity set            Table I (D3Q19); D2Q9 is its 2D analogue
+ *   LB update               eq. (LBE): stream + BGK collision + Guo source
+ *   equilibrium             second-order Maxwell-Boltzmann expansion
+ *   Guo source term         S_i(U, F) with the (1 - dt/2tau) prefactor
+ *   moments                 eqs. (hydro_var1), (hydro_var2) (half-force U)
+ *   delta kernel            Peskin 4-point Psi, Delta = Psi Psi Psi / dx^3
+ *   spreading               eq. (force_spread)
+ *   interpolation           eq. (vel_interpolation)
+ *   advection               forward Euler q <- q + qdot dt
+ *   surface tension         phi_sigma = -dW/dq with W = sigma e^a summed
+ *                           over the reference area (Sec. "Modelling surface
+ *                           tension forces"); e^a is the area ratio, so W is
+ *                           sigma times the current area (perimeter in 2D)
+ *   wetting                 eq. (disjoin-p) for Pi(h); nodal force
+ *                           -(chi_j/3) Pi n_j; strength A from eq. (A_choice)
+ *   boundaries              periodic sides, bounce-back walls (Sec. "Numerical
+ *                           results", set-up paragraph)
+ *
+ * Conventions shared with every other implementation of the model (an
+ * interface, not code): populations are stored [i][z][y][x] with x fastest;
+ * cell (x,y,z) is centred at (x+1/2, y+1/2, z+1/2); walls sit at coordinate 0
+ * and n of a wall axis; velocities are ordered rest, then opposite pairs
+ * adjacent, so opp(i) = i+1 for odd i and i-1 for even i > 0.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PERIODIC 0
+#define ORC_WALL 1
+
+/* ------------------------------------------------------------------------ */
+/* Velocity sets                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* D2Q9: rest; +x,-x; +y,-y; (+1,+1),(-1,-1); (-1,+1),(+1,-1) */
+static const int C2[9][3] = {
+    {0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+    {1, 1, 0}, {-1, -1, 0}, {-1, 1, 0}, {1, -1, 0}};
+static const double W2[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+/* D3Q19 (Table I): rest w = 1/3; six axis velocities w = 1/18; twelve
+ * face diagonals w = 1/36 */
+static const int C3[19][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+static const double W3[19] = {
+    1.0 / 3.0,
+    1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+static const double CS2 = 1.0 / 3.0; /* c_s^2 = dx^2 / (3 dt^2) */
+
+static int nq(int dim) { return dim == 2 ? 9 : 19; }
+static const int *cvec(int dim, int i) { return dim == 2 ? C2[i] : C3[i]; }
+static double wgt(int dim, int i) { return dim == 2 ? W2[i] : W3[i]; }
+
+/* index of -c_i, found by search so it does not rely on the ordering */
+static int opposite(int dim, int i)
+{
+    const int *c = cvec(dim, i);
+    for (int k = 0; k < nq(dim); ++k) {
+        const int *d = cvec(dim, k);
+        if (d[0] == -c[0] && d[1] == -c[1] && d[2] == -c[2]) return k;
+    }
+    return -1;
+}
+
+void orc_lattice(int dim, int *c_out /* Q*3 */, double *w_out /* Q */)
+{
+    for (int i = 0; i < nq(dim); ++i) {
+        for (int a = 0; a < 3; ++a) c_out[3 * i + a] = cvec(dim, i)[a];
+        w_out[i] = wgt(dim, i);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Collision ingredients                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* second-order equilibrium f_i^eq(rho, U) */
+void orc_equilibrium(int dim, double rho, const double *U, double *feq)
+{
+    double uu = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+    for (int i = 0; i < nq(dim); ++i) {
+        const int *c = cvec(dim, i);
+        double cu = c[0] * U[0] + c[1] * U[1] + c[2] * U[2];
+        feq[i] = wgt(dim, i) * rho *
+                 (1.0 + cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+    }
+}
+
+/* Guo source S_i(U, F) = (1 - dt/(2 tau)) w_i [ (c_i - U)/cs^2
+ *                                             + (c_i.U) c_i / cs^4 ] . F  */
+void orc_guo_source(int dim, double tau, const double *U, const double *F, double *S)
+{
+    double pre = 1.0 - 1.0 / (2.0 * tau);
+    for (int i = 0; i < nq(dim); ++i) {
+        const int *c = cvec(dim, i);
+        double cu = c[0] * U[0] + c[1] * U[1] + c[2] * U[2];
+        double s = 0.0;
+        for (int a = 0; a < 3; ++a)
+            s += ((c[a] - U[a]) / CS2 + cu * c[a] / (CS2 * CS2)) * F[a];
+        S[i] = pre * wgt(dim, i) * s;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* One LB time step, pull form:                                              */
+/*   f_i(x, t)   = f*_i(x - c_i, t - 1)  (streaming, left side of eq. LBE)   */
+/*   rho, U      from eqs. (hydro_var1), (hydro_var2) with F(x, t)           */
+/*   f*_i(x, t)  = f_i - (f_i - f_i^eq)/tau + S_i   (right side of eq. LBE)  */
+/* A population whose source cell lies beyond a wall was reflected there     */
+/* half a step earlier: it is the opposite population of the same cell       */
+/* (half-way bounce-back, resting wall).                                     */
+/* fin, fout: [Q][ncell]; F, U: [3][ncell] (unused components zero);        */
+/* rho: [ncell].  F may be NULL (no force).                                  */
+/* ------------------------------------------------------------------------ */
+void orc_lb_step(int dim, int nx, int ny, int nz, const int *bc, double tau,
+                 const double *fin, const double *F, double *fout,
+                 double *rho_out, double *U_out)
+{
+    const int Q = nq(dim);
+    const long ncell = (long)nx * ny * nz;
+    const int n[3] = {nx, ny, nz};
+    double f[19], feq[19], S[19];
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const long cell = ((long)z * ny + y) * nx + x;
+                const int pos[3] = {x, y, z};
+                for (int i = 0; i < Q; ++i) {
+                    const int *c = cvec(dim, i);
+                    int src[3];
+                    int bounced = 0;
+                    for (int a = 0; a < 3; ++a) {
+                        src[a] = pos[a] - c[a];
+                        if (src[a] < 0 || src[a] >= n[a]) {
+                            if (bc[a] == ORC_PERIODIC)
+                                src[a] = (src[a] + n[a]) % n[a];
+                            else
+                                bounced = 1;
+                        }
+                    }
+                    if (bounced) {
+                        f[i] = fin[(long)opposite(dim, i) * ncell + cell];
+                    } else {
+                        long sc = ((long)src[2] * ny + src[1]) * nx + src[0];
+                        f[i] = fin[(long)i * ncell + sc];
+                    }
+                }
+                double Fx[3] = {0.0, 0.0, 0.0};
+                if (F)
+                    for (int a = 0; a < dim; ++a) Fx[a] = F[(long)a * ncell + cell];
+                double rho = 0.0, mom[3] = {0.0, 0.0, 0.0};
+                for (int i = 0; i < Q; ++i) {
+                    rho += f[i];
+                    for (int a = 0; a < 3; ++a) mom[a] += cvec(dim, i)[a] * f[i];
+                }
+                double U[3];
+                for (int a = 0; a < 3; ++a) U[a] = (mom[a] + 0.5 * Fx[a]) / rho;
+                orc_equilibrium(dim, rho, U, feq);
+                orc_guo_source(dim, tau, U, Fx, S);
+                for (int i = 0; i < Q; ++i)
+                    fout[(long)i * ncell + cell] = f[i] - (f[i] - feq[i]) / tau + S[i];
+                if (rho_out) rho_out[cell] = rho;
+                if (U_out)
+                    for (int a = 0; a < 3; ++a) U_out[(long)a * ncell + cell] = U[a];
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Peskin 4-point kernel Psi(x) (dx = 1), evaluated from its piecewise      */
+/* definition.                                                               */
+/* ------------------------------------------------------------------------ */
+double orc_psi(double x)
+{
+    double r = fabs(x);
+    if (r <= 1.0) return 3.0 / 8.0 - r / 4.0 + sqrt(r - r * r + 0.25) / 4.0;
+    if (r <= 2.0) return 5.0 / 8.0 - r / 4.0 - sqrt(3.0 * r - r * r - 1.75) / 4.0;
+    return 0.0;
+}
+
+/* Visit every lattice cell within the support of Delta(q - x): cells whose
+ * centre lies within 2 of q along every axis.  Along a periodic axis the
+ * cell index wraps; along a wall axis a cell beyond the wall is reported as
+ * solid (index -1). */
+typedef void (*tap_fn)(void *ctx, long cell, double weight);
+
+static void for_each_tap(int dim, const int *n, const int *bc, const double *q,
+                         tap_fn fn, void *ctx)
+{
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        if (a < dim) {
+            lo[a] = (int)floor(q[a]) - 3;
+            hi[a] = (int)floor(q[a]) + 3;
+        } else {
+            lo[a] = hi[a] = 0;
+        }
+    }
+    for (int k = lo[2]; k <= hi[2]; ++k)
+        for (int j = lo[1]; j <= hi[1]; ++j)
+            for (int i = lo[0]; i <= hi[0]; ++i) {
+                const int idx[3] = {i, j, k};
+                double wgt_ = 1.0;
+                for (int a = 0; a < dim; ++a) wgt_ *= orc_psi(idx[a] + 0.5 - q[a]);
+                if (wgt_ == 0.0) continue;
+                int w[3];
+                int solid = 0;
+                for (int a = 0; a < 3; ++a) {
+                    w[a] = idx[a];
+                    if (a >= dim) { w[a] = 0; continue; }
+                    if (w[a] < 0 || w[a] >= n[a]) {
+                        if (bc[a] == ORC_PERIODIC)
+                            w[a] = ((w[a] % n[a]) + n[a]) % n[a];
+                        else
+                            solid = 1;
+                    }
+                }
+                long cell = solid ? -1 : ((long)w[2] * n[1] + w[1]) * n[0] + w[0];
+                fn(ctx, cell, wgt_);
+            }
+}
+
+struct spread_ctx {
+    int dim;
+    long ncell;
+    const double *phi; /* this node's force */
+    double *F;
+    double *dropped;
+};
+
+static void spread_tap(void *vctx, long cell, double weight)
+{
+    struct spread_ctx *s = (struct spread_ctx *)vctx;
+    for (int a = 0; a < s->dim; ++a) {
+        if (cell >= 0)
+            s->F[(long)a * s->ncell + cell] += s->phi[a] * weight;
+        else
+            s->dropped[a] += s->phi[a] * weight;
+    }
+}
+
+/* eq. (force_spread): F(x) = sum_j phi_j Delta(q_j - x), dx = 1.
+ * q, phi: [dim][N].  F: [3][ncell], overwritten.  dropped[3]: the part of
+ * the nodal forces whose taps fall beyond a wall (not spread). */
+void orc_spread(int dim, int nx, int ny, int nz, const int *bc, int N,
+                const double *q, const double *phi, double *F, double *dropped)
+{
+    const int n[3] = {nx, ny, nz};
+    const long ncell = (long)nx * ny * nz;
+    memset(F, 0, sizeof(double) * 3 * ncell);
+    dropped[0] = dropped[1] = dropped[2] = 0.0;
+    for (int j = 0; j < N; ++j) {
+        double qj[3] = {0, 0, 0}, pj[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a) {
+            qj[a] = q[(long)a * N + j];
+            pj[a] = phi[(long)a * N + j];
+        }
+        struct spread_ctx s = {dim, ncell, pj, F, dropped};
+        for_each_tap(dim, n, bc, qj, spread_tap, &s);
+    }
+}
+
+struct interp_ctx {
+    int dim;
+    long ncell;
+    const double *U;
+    double acc[3];
+};
+
+static void interp_tap(void *vctx, long cell, double weight)
+{
+    struct interp_ctx *s = (struct interp_ctx *)vctx;
+    if (cell < 0) return; /* wall: the fluid velocity there is zero */
+    for (int a = 0; a < s->dim; ++a) s->acc[a] += s->U[(long)a * s->ncell + cell] * weight;
+}
+
+/* eq. (vel_interpolation): qdot_j = sum_x U(x) Delta(q_j - x) dx^3 */
+void orc_interp(int dim, int nx, int ny, int nz, const int *bc, const double *U,
+                int N, const double *q, double *qdot)
+{
+    const int n[3] = {nx, ny, nz};
+    const long ncell = (long)nx * ny * nz;
+    for (int j = 0; j < N; ++j) {
+        double qj[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a) qj[a] = q[(long)a * N + j];
+        struct interp_ctx s = {dim, ncell, U, {0, 0, 0}};
+        for_each_tap(dim, n, bc, qj, interp_tap, &s);
+        for (int a = 0; a < dim; ++a) qdot[(long)a * N + j] = s.acc[a];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Interface forces                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* eq. (A_choice) */
+double orc_wetting_strength(double sigma, double theta, double xi, int n, int m)
+{
+    return sigma * (double)((m - 1) * (n - 1)) / ((double)(n - m) * xi) * (1.0 + cos(theta));
+}
+
+/* eq. (disjoin-p) */
+double orc_pi(double h, double A, double xi, int n, int m)
+{
+    return A * (pow(xi / h, n) - pow(xi / h, m));
+}
+
+/* 2D closed polygon, nodes counter-clockwise.  The membrane energy is sigma
+ * times the perimeter (line tension), so the nodal surface-tension force is
+ *   phi_sigma_j = -sigma d|Gamma|/dq_j = sigma (t_j - t_{j-1}),
+ * t_j the unit tangent of edge j -> j+1.  The wetting force uses the node
+ * normal (mean of the two adjacent edge normals, renormalised), the length
+ * associated with the node chi_j = l_{j-1} + l_j, shared by the two nodes of
+ * each edge (factor 1/2, the 2D counterpart of 1/3), and h_j = q_j,y.
+ * q, phi: [2][N].  Outputs: phi (total), and optional normals [2][N]. */
+void orc_forces_2d(int N, const double *q, double sigma, double A, double xi,
+                   int n, int m, int wetting, double *phi, double *normal_out)
+{
+    const double *x = q, *y = q + N;
+    for (int j = 0; j < N; ++j) {
+        int jp = (j + 1) % N, jm = (j - 1 + N) % N;
+        double ex = x[jp] - x[j], ey = y[jp] - y[j];           /* edge j */
+        double fx = x[j] - x[jm], fy = y[j] - y[jm];           /* edge j-1 */
+        double le = sqrt(ex * ex + ey * ey), lf = sqrt(fx * fx + fy * fy);
+        double px = sigma * (ex / le - fx / lf);
+        double py = sigma * (ey / le - fy / lf);
+        /* outward unit normals of the two edges */
+        double nex = ey / le, ney = -ex / le;
+        double nfx = fy / lf, nfy = -fx / lf;
+        double nx_ = nex + nfx, ny_ = ney + nfy;
+        double nn = sqrt(nx_ * nx_ + ny_ * ny_);
+        nx_ /= nn;
+        ny_ /= nn;
+        if (wetting) {
+            double chi = le + lf;
+            double P = orc_pi(y[j], A, xi, n, m);
+            px += -(chi / 2.0) * P * nx_;
+            py += -(chi / 2.0) * P * ny_;
+        }
+        phi[j] = px;
+        phi[N + j] = py;
+        if (normal_out) {
+            normal_out[j] = nx_;
+            normal_out[N + j] = ny_;
+        }
+    }
+}
+
+static void cross3(const double *a, const double *b, double *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* 3D closed triangle mesh, triangles counter-clockwise seen from outside.
+ * The membrane energy is sigma times the total area, so for triangle
+ * (a, b, c) with unit normal n_t
+ *   phi_sigma_a += -sigma d(area)/dq_a = -(sigma/2) n_t x (q_c - q_b)
+ * and cyclically for b and c.  Wetting: n_j is the mean of the unit normals
+ * of the faces sharing node j (renormalised), chi_j the sum of their areas,
+ * phi_Pi_j = -(chi_j / 3) Pi(h_j) n_j with h_j = q_j,z.
+ * q, phi: [3][N]; tri: [T][3]. */
+void orc_forces_3d(int N, const double *q, int T, const int *tri, double sigma,
+                   double A, double xi, int n, int m, int wetting, double *phi,
+                   double *normal_out)
+{
+    double *nsum = (double *)calloc((size_t)3 * N, sizeof(double));
+    double *chi = (double *)calloc((size_t)N, sizeof(double));
+    for (long k = 0; k < 3L * N; ++k) phi[k] = 0.0;
+    for (int t = 0; t < T; ++t) {
+        int v[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
+        double P[3][3];
+        for (int s = 0; s < 3; ++s)
+            for (int a = 0; a < 3; ++a) P[s][a] = q[(long)a * N + v[s]];
+        double e1[3], e2[3], nt[3];
+        for (int a = 0; a < 3; ++a) {
+            e1[a] = P[1][a] - P[0][a];
+            e2[a] = P[2][a] - P[0][a];
+        }
+        cross3(e1, e2, nt);
+        double len = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+        double area = 0.5 * len;
+        for (int a = 0; a < 3; ++a) nt[a] /= len;
+        for (int s = 0; s < 3; ++s) {
+            int sb = (s + 1) % 3, sc = (s + 2) % 3;
+            double d[3], g[3];
+            for (int a = 0; a < 3; ++a) d[a] = P[sc][a] - P[sb][a];
+            cross3(nt, d, g);
+            for (int a = 0; a < 3; ++a) {
+                phi[(long)a * N + v[s]] += -0.5 * sigma * g[a];
+                nsum[(long)a * N + v[s]] += nt[a];
+            }
+            chi[v[s]] += area;
+        }
+    }
+    for (int j = 0; j < N; ++j) {
+        double nv[3];
+        for (int a = 0; a < 3; ++a) nv[a] = nsum[(long)a * N + j];
+        double nn = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+        for (int a = 0; a < 3; ++a) nv[a] /= nn;
+        if (wetting) {
+            double Pi = orc_pi(q[2L * N + j], A, xi, n, m);
+            for (int a = 0; a < 3; ++a) phi[(long)a * N + j] += -(chi[j] / 3.0) * Pi * nv[a];
+        }
+        if (normal_out)
+            for (int a = 0; a < 3; ++a) normal_out[(long)a * N + j] = nv[a];
+    }
+    free(nsum);
+    free(chi);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time loop                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Run nsteps of the coupled method.  Order inside a step: nodal forces at
+ * q(t) -> spread to F(t) -> LB step with F(t) (in the Guo source and the
+ * half-force velocity alike) -> interpolate U(t) at q(t) -> q(t+1).
+ *
+ * f: [Q][ncell] post-collision populations, updated in place.
+ * q: [dim][N] node positions, updated in place.
+ * rho, U, F: outputs of the last step ([ncell], [3][ncell], [3][ncell]).
+ * phi, qdot: outputs of the last step ([dim][N]).  dropped: [3].
+ * N = 0 runs the fluid alone with the prescribed force field F_fixed
+ * (may be NULL).  Returns 0, or -4 if a node reached h <= 0 (wetting on). */
+int orc_run(int dim, int nx, int ny, int nz, const int *bc, double tau,
+            double sigma, double theta, double xi, int n_exp, int m_exp, int wetting,
+            int N, double *q, int T, const int *tri, int nsteps,
+            double *f, double *rho, double *U, double *F, const double *F_fixed,
+            double *phi, double *qdot, double *dropped)
+{
+    const int Q = nq(dim);
+    const long ncell = (long)nx * ny * nz;
+    double *g = (double *)malloc(sizeof(double) * Q * ncell);
+    double A = orc_wetting_strength(sigma, theta, xi, n_exp, m_exp);
+    int status = 0;
+    for (int t = 0; t < nsteps; ++t) {
+        if (N > 0) {
+            if (wetting)
+                for (int j = 0; j < N; ++j)
+                    if (q[(long)(dim - 1) * N + j] <= 0.0) status = -4;
+            if (status) break;
+            if (dim == 2)
+                orc_forces_2d(N, q, sigma, A, xi, n_exp, m_exp, wetting, phi, NULL);
+            else
+                orc_forces_3d(N, q, T, tri, sigma, A, xi, n_exp, m_exp, wetting, phi, NULL);
+            orc_spread(dim, nx, ny, nz, bc, N, q, phi, F, dropped);
+        } else if (F_fixed) {
+            memcpy(F, F_fixed, sizeof(double) * 3 * ncell);
+        } else {
+            memset(F, 0, sizeof(double) * 3 * ncell);
+        }
+        orc_lb_step(dim, nx, ny, nz, bc, tau, f, F, g, rho, U);
+        memcpy(f, g, sizeof(double) * Q * ncell);
+        if (N > 0) {
+            orc_interp(dim, nx, ny, nz, bc, U, N, q, qdot);
+            for (long k = 0; k < (long)dim * N; ++k) q[k] += qdot[k];
+        }
+    }
+    free(g);
+    return status;
+}
