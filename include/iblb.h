@@ -1,0 +1,206 @@
+/*
+ * iblb.h -- C ABI of the MI355X (gfx950) immersed-boundary lattice Boltzmann
+ * wetting solver.
+ *
+ * The model is the hybrid IB-LB method of "Immersed boundary - lattice
+ * Boltzmann method for wetting problems":
+ *   - fluid: lattice Boltzmann equation (eq. LBE) with the BGK collision, the
+ *     second-order equilibrium and Guo's source term; density and
+ *     half-force velocity from eqs. (hydro_var1)-(hydro_var2); D3Q19 velocity
+ *     set of Table I, or its 2D analogue D2Q9 (w = 4/9, 1/9, 1/36);
+ *   - coupling: nodal forces spread to the lattice (eq. force_spread), lattice
+ *     velocity interpolated to the nodes (eq. vel_interpolation) with the
+ *     Peskin 4-point kernel, nodes advanced by forward Euler;
+ *   - interface forces: surface tension from the strain energy w = sigma e^a
+ *     (Sec. "Modelling surface tension forces"), evaluated as minus sigma
+ *     times the gradient of the interface area (perimeter in 2D), plus the
+ *     wetting force -(chi_j/3) Pi(h_j) n_j of Sec. "Modelling wetting
+ *     properties" with Pi(h) of eq. (disjoin-p) and A of eq. (A_choice);
+ *   - boundaries: periodic sides, half-way bounce-back walls (Sec.
+ *     "Numerical results", set-up paragraph).
+ *
+ * Conventions
+ *   - Lattice units, dx = dt = 1.  Cell (i, j, k) is centred at
+ *     (i + 1/2, j + 1/2, k + 1/2).  A wall axis has walls at coordinate 0
+ *     and n; the substrate is the wall at 0 of the last axis (y in 2D, z in
+ *     3D), so a node's height above it is its last coordinate.
+ *   - Velocity order: rest, then opposite pairs adjacent
+ *       D2Q9 : 0 | +x -x | +y -y | (+1,+1) (-1,-1) | (-1,+1) (+1,-1)
+ *       D3Q19: 0 | +x -x | +y -y | +z -z | (1,1,0) (-1,-1,0) | (1,-1,0)
+ *              (-1,1,0) | (1,0,1) (-1,0,-1) | (1,0,-1) (-1,0,1) | (0,1,1)
+ *              (0,-1,-1) | (0,1,-1) (0,-1,1)
+ *   - Cell arrays are [component][z][y][x], x fastest.  Node arrays are
+ *     structure-of-arrays [component][node].
+ *   - A population is exchanged as its deviation from its weight, f_i - w_i.
+ *
+ * Memory and streams
+ *   - The caller owns all device memory.  iblb_workspace_bytes() gives the
+ *     size of one device buffer that the caller allocates and hands to
+ *     iblb_create(); the library carves every device array from it and
+ *     allocates no device memory of its own.  Host memory for the handle
+ *     and a private capture stream are created in iblb_create().
+ *   - Every call is ordered on the stream given to iblb_create() (a
+ *     hipStream_t passed as void*; NULL is the default stream).  Calls that
+ *     return host data synchronise that stream.
+ *   - A handle is not thread-safe; any number of handles may coexist.
+ *
+ * Errors
+ *   Every call returns an iblb_status.  Nothing throws across the ABI.
+ *   iblb_last_error() gives a message for the handle's last failure.
+ */
+#ifndef IBLB_H
+#define IBLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IBLB_OK = 0,
+    IBLB_EINVAL = -1,     /* bad argument: see iblb_last_error()            */
+    IBLB_ENOMEM = -2,     /* workspace smaller than iblb_workspace_bytes()  */
+    IBLB_EDEVICE = -3,    /* a HIP runtime call failed                      */
+    IBLB_EUNSTABLE = -4   /* a node reached h <= 0 with wetting on, or a
+                             node speed became non-finite or above 0.3      */
+} iblb_status;
+
+typedef enum { IBLB_PERIODIC = 0, IBLB_WALL = 1 } iblb_bc;
+
+/* Storage format of the populations.  Arithmetic is fp32 in every case.
+ * The shifted formats store the deviation f_i - w_i rounded to nearest even
+ * (fp32, fp16 or bf16), which keeps the small deviations from the rest
+ * state at full relative precision. */
+typedef enum { IBLB_F32 = 0, IBLB_F16 = 1, IBLB_BF16 = 2 } iblb_storage;
+
+/* Parameters of one droplet simulation (one fluid box + one interface). */
+typedef struct {
+    int dim;            /* 2 (D2Q9) or 3 (D3Q19)                              */
+    int nx, ny, nz;     /* lattice size; nz = 1 in 2D; each >= 1              */
+    int bc[3];          /* iblb_bc per axis                                   */
+    double tau;         /* BGK relaxation time, > 1/2; INFINITY gives pure
+                           streaming (no relaxation, no force)               */
+    double sigma;       /* surface tension                                    */
+    double theta_eq;    /* equilibrium contact angle in radians               */
+    double xi;          /* regularising length of Pi(h), > 0                  */
+    int n_exp, m_exp;   /* exponents of Pi(h), n > m (the paper uses 6, 3)    */
+    int wetting;        /* 1: Pi(h) acts from the substrate; 0: free droplet  */
+} iblb_params;
+
+/* FP64 diagnostics of one droplet after the last completed step. */
+typedef struct {
+    int64_t step;             /* steps completed                              */
+    double mass;              /* sum over cells of rho                        */
+    double momentum[3];       /* sum over cells of rho U (last step)          */
+    double sum_phi[3];        /* sum of nodal forces (last step)              */
+    double sum_F[3];          /* sum of the spread force density (last step)  */
+    double dropped_F[3];      /* nodal force falling on wall taps (not spread)*/
+    double volume;            /* enclosed area (2D) or volume (3D)            */
+    double area;              /* perimeter (2D) or surface area (3D)          */
+    double contact_radius;    /* protocol (i): crossing of the interface with
+                                 the plane at z_cut = xi (n/m)^(1/(n-m))      */
+    double height;            /* max minus min node height                   */
+    double theta_meas;        /* angle from the half-height (eq. angleh; 2D:
+                                 the circular-cap counterpart), radians       */
+    double max_normal_speed;  /* max over nodes of |qdot . n|                 */
+    double max_speed;         /* max over nodes of |qdot|                     */
+    double min_h;             /* lowest node height                           */
+    double edge_min, edge_max;/* shortest / longest mesh edge                 */
+    int32_t status;           /* iblb_status of the droplet                   */
+} iblb_diag;
+
+typedef struct iblb_ctx iblb_ctx;
+
+/* Size in bytes of the device workspace for n_droplets droplets with the
+ * given parameters, node counts and triangle counts (n_tris may be NULL in
+ * 2D, where the interface is a closed polygon).  Returns 0 on bad input. */
+size_t iblb_workspace_bytes(int n_droplets, const iblb_params *params,
+                            const int *n_nodes, const int *n_tris, int storage);
+
+/* Create a handle for n_droplets independent droplets that are stepped
+ * together (one launch per kernel for the whole batch).  All droplets share
+ * dim and storage.  d_workspace: caller-owned device buffer of ws_bytes >=
+ * iblb_workspace_bytes(...).  stream: hipStream_t or NULL.  On success the
+ * populations are at rest (f = w) and every node sits at the origin until
+ * iblb_set_interface() is called.  *out receives the handle (NULL on error). */
+int iblb_create(int n_droplets, const iblb_params *params, const int *n_nodes,
+                const int *n_tris, int storage, void *d_workspace, size_t ws_bytes,
+                void *stream, iblb_ctx **out);
+
+int iblb_destroy(iblb_ctx *ctx);
+
+/* Message for the handle's last failure ("" if none).  Valid until the next
+ * call on the handle.  ctx may be NULL for failures of iblb_create(). */
+const char *iblb_last_error(const iblb_ctx *ctx);
+
+/* Upload droplet d's interface: h_pos [dim][N] node positions (host,
+ * float64, N as given to iblb_create).  2D: the nodes form a closed polygon
+ * in the given order, counter-clockwise.  3D: h_tris [T][3] vertex indices
+ * (host, int32), counter-clockwise seen from outside; every vertex must
+ * belong to at least one triangle.  Copies are made; EINVAL on a bad index. */
+int iblb_set_interface(iblb_ctx *ctx, int droplet, const double *h_pos,
+                       const int32_t *h_tris);
+
+/* Reset droplet d (or every droplet for d = -1) to rest: f_i = w_i. */
+int iblb_init_rest(iblb_ctx *ctx, int droplet);
+
+/* Overwrite / read droplet d's post-collision populations, exchanged as
+ * deviations f_i - w_i in a device float64 array [Q][nz][ny][nx].  Writing
+ * narrows through fp32 to the storage format, nearest even at each step. */
+int iblb_write_populations(iblb_ctx *ctx, int droplet, const double *d_fdev);
+int iblb_read_populations(iblb_ctx *ctx, int droplet, double *d_fdev);
+
+/* Replace droplet d's immersed boundary by a prescribed, constant force
+ * density d_F [dim][nz][ny][nx] (device float32, copied), or give back the
+ * immersed boundary with d_F = NULL.  Used for closed-form flows. */
+int iblb_set_force_field(iblb_ctx *ctx, int droplet, const float *d_F);
+
+/* Advance every droplet by n_steps time steps.  Each step: nodal forces at
+ * q(t) -> spread to F(t) -> fused pull-stream + collide with F(t) -> velocity
+ * U(t) interpolated at q(t) -> q(t+1) = q(t) + qdot(t).  Asynchronous except
+ * for a final status check (synchronises the stream, reads one int per
+ * droplet).  Long runs replay a captured graph of a fixed number of steps.
+ * The last step of every call also stores rho, U and F of every cell for
+ * iblb_read_fields(). */
+int iblb_step(iblb_ctx *ctx, int n_steps);
+
+/* Copy the last step's fields of droplet d into device float32 arrays:
+ * d_rho [nz][ny][nx], d_u [dim][nz][ny][nx], d_F [dim][nz][ny][nx]; any of
+ * them may be NULL.  Before the first step, rho = 1 and U = F = 0. */
+int iblb_read_fields(iblb_ctx *ctx, int droplet, float *d_rho, float *d_u, float *d_F);
+
+/* Copy droplet d's nodes to host arrays [dim][N]: positions q(t+1)
+ * (float64), velocities qdot(t) and nodal forces phi(t) (float32) of the
+ * last step; any pointer may be NULL.  Synchronises the stream. */
+int iblb_read_nodes(iblb_ctx *ctx, int droplet, double *h_pos, float *h_vel, float *h_force);
+
+/* FP64 diagnostics of droplet d into *out (host), or of every droplet into
+ * out[0..n_droplets-1] for d = -1.  Reads all populations once.
+ * Synchronises. */
+int iblb_diagnostics(iblb_ctx *ctx, int droplet, iblb_diag *out);
+
+/* Tile shape of the lattice kernel: index into the shape list (0: 256x1
+ * cells per block, 1: 128x2, 2: 64x4), or -1 to keep the current one.
+ * Returns the shape in use via *shape_out (may be NULL). */
+int iblb_set_tile_shape(iblb_ctx *ctx, int shape, int *shape_out);
+
+/* Number of steps captured in one replayed graph (>= 2, even); default 64.
+ * 0 disables graphs (every step launched directly). */
+int iblb_set_graph_steps(iblb_ctx *ctx, int steps);
+
+/* Mark droplet d active (1) or frozen (0).  Frozen droplets are skipped by
+ * every kernel until re-activated; their state is kept. */
+int iblb_set_active(iblb_ctx *ctx, int droplet, int active);
+
+/* Measured device time (milliseconds, hipEvent based) of the lattice kernel
+ * and of the whole step, averaged over the steps of the last iblb_step()
+ * call made with timing on (see iblb_set_timing). */
+int iblb_set_timing(iblb_ctx *ctx, int on);
+int iblb_last_timing(const iblb_ctx *ctx, double *lb_ms_per_step, double *step_ms_per_step);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBLB_H */

@@ -1,0 +1,207 @@
+"""MI355X-native immersed-boundary lattice Boltzmann wetting solver.
+
+The compute path is the HIP library libiblb.so (C ABI in include/iblb.h).
+This package only marshals arguments: PyTorch provides the device
+workspace and the stream, numpy holds host-side node arrays.
+
+    from paper_2503_20605_amd import Solver, make_params
+    p = make_params(dim=2, nx=128, ny=64, tau=1.0, sigma=0.01,
+                    theta_eq_deg=60.0, xi=2.0)
+    s = Solver([p], [nodes])          # nodes: (N, 2) float64, CCW polygon
+    s.step(1000)
+    rho, U, F = s.read_fields(0)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+
+from . import _lib
+from ._lib import (IBLB_BF16, IBLB_F16, IBLB_F32, IBLB_PERIODIC, IBLB_WALL, IblbError,
+                   iblb_diag, iblb_params)
+
+__all__ = ["Solver", "make_params", "IblbError", "IBLB_F32", "IBLB_F16", "IBLB_BF16",
+           "IBLB_PERIODIC", "IBLB_WALL", "STORAGE"]
+
+STORAGE = {"f32": IBLB_F32, "f16": IBLB_F16, "bf16": IBLB_BF16}
+
+
+def make_params(dim=2, nx=128, ny=64, nz=1, bc=None, tau=1.0, sigma=0.01, theta_eq_deg=90.0,
+                xi=2.0, n_exp=6, m_exp=3, wetting=True) -> iblb_params:
+    """Build an iblb_params record (angle given in degrees)."""
+    if bc is None:
+        bc = (IBLB_PERIODIC, IBLB_WALL, IBLB_PERIODIC) if dim == 2 else \
+             (IBLB_PERIODIC, IBLB_PERIODIC, IBLB_WALL)
+    p = iblb_params()
+    p.dim, p.nx, p.ny, p.nz = dim, nx, ny, (nz if dim == 3 else 1)
+    for a in range(3):
+        p.bc[a] = int(bc[a])
+    p.tau, p.sigma = float(tau), float(sigma)
+    p.theta_eq = math.radians(theta_eq_deg)
+    p.xi, p.n_exp, p.m_exp, p.wetting = float(xi), int(n_exp), int(m_exp), int(bool(wetting))
+    return p
+
+
+def params_from(obj) -> iblb_params:
+    """iblb_params from any object with the attributes of make_params."""
+    return make_params(dim=obj.dim, nx=obj.nx, ny=obj.ny, nz=getattr(obj, "nz", 1),
+                       bc=obj.bc, tau=obj.tau, sigma=obj.sigma,
+                       theta_eq_deg=obj.theta_eq_deg, xi=obj.xi, n_exp=obj.n_exp,
+                       m_exp=obj.m_exp, wetting=obj.wetting)
+
+
+class Solver:
+    """One handle on a batch of droplets.
+
+    params: list of iblb_params; nodes: list of (N, dim) float64 arrays (or
+    None for a fluid-only droplet); tris: list of (T, 3) int32 arrays in 3D.
+    The device workspace is one torch uint8 tensor; every call runs on
+    `stream` (default: torch's current stream)."""
+
+    def __init__(self, params, nodes, tris=None, storage=IBLB_F32, device="cuda", stream=None):
+        import torch
+        self._torch = torch
+        lib = _lib.load()
+        self.lib = lib
+        n = len(params)
+        self.n = n
+        self.dim = params[0].dim
+        self.Q = 9 if self.dim == 2 else 19
+        self.params = list(params)
+        self.storage = storage
+        self.device = torch.device(device)
+        nodes = [None] * n if nodes is None else list(nodes)
+        tris = [None] * n if tris is None else list(tris)
+        self.n_nodes = [0 if q is None else int(np.asarray(q).shape[0]) for q in nodes]
+        self.n_tris = [0 if t is None else int(np.asarray(t).shape[0]) for t in tris]
+        P = (iblb_params * n)(*params)
+        NN = (ctypes.c_int * n)(*self.n_nodes)
+        NT = (ctypes.c_int * n)(*self.n_tris)
+        self._P, self._NN, self._NT = P, NN, NT
+        nbytes = lib.iblb_workspace_bytes(n, P, NN, NT, storage)
+        if nbytes == 0:
+            # let create() produce the message
+            nbytes = 256
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        ctx = ctypes.c_void_p()
+        code = lib.iblb_create(n, P, NN, NT, storage, ctypes.c_void_p(self.ws.data_ptr()),
+                               ctypes.c_size_t(nbytes), ctypes.c_void_p(self.stream.cuda_stream),
+                               ctypes.byref(ctx))
+        _lib.check(code, None)
+        self.ctx = ctx
+        for d in range(n):
+            if nodes[d] is not None and self.n_nodes[d] > 0:
+                self.set_interface(d, nodes[d], tris[d])
+
+    # -- lifetime ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.iblb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, code):
+        return _lib.check(code, self.ctx)
+
+    # -- set-up ------------------------------------------------------------
+    def set_interface(self, d, q, tris=None):
+        q = np.ascontiguousarray(np.asarray(q, dtype=np.float64).T)
+        t = None if tris is None else np.ascontiguousarray(np.asarray(tris, dtype=np.int32))
+        self._chk(self.lib.iblb_set_interface(
+            self.ctx, d, q.ctypes.data_as(ctypes.c_void_p),
+            None if t is None else t.ctypes.data_as(ctypes.c_void_p)))
+
+    def init_rest(self, d=-1):
+        self._chk(self.lib.iblb_init_rest(self.ctx, d))
+
+    def cells(self, d):
+        p = self.params[d]
+        return (p.nz if self.dim == 3 else 1, p.ny, p.nx)
+
+    def write_populations(self, d, fdev):
+        """fdev: deviations f - w, shape (Q, nz, ny, nx), any float dtype."""
+        t = self._torch.as_tensor(np.asarray(fdev) if not self._torch.is_tensor(fdev) else fdev)
+        t = t.to(device=self.device, dtype=self._torch.float64).contiguous()
+        assert t.numel() == self.Q * int(np.prod(self.cells(d)))
+        self._chk(self.lib.iblb_write_populations(self.ctx, d, ctypes.c_void_p(t.data_ptr())))
+        self.stream.synchronize()
+
+    def read_populations(self, d):
+        """Deviations f - w of the current post-collision populations."""
+        t = self._torch.empty((self.Q,) + self.cells(d), dtype=self._torch.float64,
+                              device=self.device)
+        self._chk(self.lib.iblb_read_populations(self.ctx, d, ctypes.c_void_p(t.data_ptr())))
+        self.stream.synchronize()
+        return t
+
+    def set_force_field(self, d, F):
+        if F is None:
+            self._chk(self.lib.iblb_set_force_field(self.ctx, d, None))
+            return
+        t = self._torch.as_tensor(F).to(device=self.device, dtype=self._torch.float32)
+        t = t[: self.dim].contiguous()
+        self._chk(self.lib.iblb_set_force_field(self.ctx, d, ctypes.c_void_p(t.data_ptr())))
+        self.stream.synchronize()
+
+    # -- stepping ----------------------------------------------------------
+    def step(self, n):
+        self._chk(self.lib.iblb_step(self.ctx, int(n)))
+
+    def set_tile_shape(self, shape):
+        out = ctypes.c_int()
+        self._chk(self.lib.iblb_set_tile_shape(self.ctx, int(shape), ctypes.byref(out)))
+        return out.value
+
+    def set_graph_steps(self, k):
+        self._chk(self.lib.iblb_set_graph_steps(self.ctx, int(k)))
+
+    def set_active(self, d, on):
+        self._chk(self.lib.iblb_set_active(self.ctx, d, int(bool(on))))
+
+    def set_timing(self, on):
+        self._chk(self.lib.iblb_set_timing(self.ctx, int(bool(on))))
+
+    def last_timing(self):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self._chk(self.lib.iblb_last_timing(self.ctx, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    # -- outputs -----------------------------------------------------------
+    def read_fields(self, d):
+        torch = self._torch
+        sh = self.cells(d)
+        rho = torch.empty(sh, dtype=torch.float32, device=self.device)
+        U = torch.empty((self.dim,) + sh, dtype=torch.float32, device=self.device)
+        F = torch.empty((self.dim,) + sh, dtype=torch.float32, device=self.device)
+        self._chk(self.lib.iblb_read_fields(self.ctx, d, ctypes.c_void_p(rho.data_ptr()),
+                                            ctypes.c_void_p(U.data_ptr()),
+                                            ctypes.c_void_p(F.data_ptr())))
+        self.stream.synchronize()
+        return rho, U, F
+
+    def read_nodes(self, d):
+        N = self.n_nodes[d]
+        pos = np.zeros((self.dim, N), dtype=np.float64)
+        vel = np.zeros((self.dim, N), dtype=np.float32)
+        frc = np.zeros((self.dim, N), dtype=np.float32)
+        self._chk(self.lib.iblb_read_nodes(self.ctx, d, pos.ctypes.data_as(ctypes.c_void_p),
+                                           vel.ctypes.data_as(ctypes.c_void_p),
+                                           frc.ctypes.data_as(ctypes.c_void_p)))
+        return pos.T.copy(), vel.T.copy(), frc.T.copy()
+
+    def diagnostics(self, d=0):
+        if d == -1:
+            arr = (iblb_diag * self.n)()
+            self._chk(self.lib.iblb_diagnostics(self.ctx, -1, arr))
+            return [a.to_dict(self.dim) for a in arr]
+        out = iblb_diag()
+        self._chk(self.lib.iblb_diagnostics(self.ctx, d, ctypes.byref(out)))
+        return out.to_dict(self.dim)

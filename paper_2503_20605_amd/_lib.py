@@ -1,0 +1,120 @@
+"""ctypes binding of libiblb.so (the C ABI declared in include/iblb.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+library.  Importing this module fails loudly when the library has not been
+built; there is no fallback of any kind."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libiblb.so")
+
+IBLB_OK = 0
+IBLB_EINVAL = -1
+IBLB_ENOMEM = -2
+IBLB_EDEVICE = -3
+IBLB_EUNSTABLE = -4
+IBLB_PERIODIC = 0
+IBLB_WALL = 1
+IBLB_F32 = 0
+IBLB_F16 = 1
+IBLB_BF16 = 2
+
+STATUS_NAMES = {0: "IBLB_OK", -1: "IBLB_EINVAL", -2: "IBLB_ENOMEM", -3: "IBLB_EDEVICE",
+                -4: "IBLB_EUNSTABLE"}
+
+EXPORTED = (
+    "iblb_workspace_bytes", "iblb_create", "iblb_destroy", "iblb_last_error",
+    "iblb_set_interface", "iblb_init_rest", "iblb_write_populations",
+    "iblb_read_populations", "iblb_set_force_field", "iblb_step", "iblb_read_fields",
+    "iblb_read_nodes", "iblb_diagnostics", "iblb_set_tile_shape", "iblb_set_graph_steps",
+    "iblb_set_active", "iblb_set_timing", "iblb_last_timing",
+)
+
+
+class iblb_params(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("nz", ctypes.c_int), ("bc", ctypes.c_int * 3), ("tau", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("theta_eq", ctypes.c_double),
+                ("xi", ctypes.c_double), ("n_exp", ctypes.c_int), ("m_exp", ctypes.c_int),
+                ("wetting", ctypes.c_int)]
+
+
+class iblb_diag(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("mass", ctypes.c_double),
+                ("momentum", ctypes.c_double * 3), ("sum_phi", ctypes.c_double * 3),
+                ("sum_F", ctypes.c_double * 3), ("dropped_F", ctypes.c_double * 3),
+                ("volume", ctypes.c_double), ("area", ctypes.c_double),
+                ("contact_radius", ctypes.c_double), ("height", ctypes.c_double),
+                ("theta_meas", ctypes.c_double), ("max_normal_speed", ctypes.c_double),
+                ("max_speed", ctypes.c_double), ("min_h", ctypes.c_double),
+                ("edge_min", ctypes.c_double), ("edge_max", ctypes.c_double),
+                ("status", ctypes.c_int32)]
+
+    def to_dict(self, dim=3):
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            if isinstance(v, ctypes.Array):
+                v = list(v)[:dim]
+            out[name] = v
+        return out
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libiblb.so; raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"HIP library not built: {LIB_PATH} is missing "
+            "(run `python -m paper_2503_20605_amd.build` or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    c_int, c_void_p, c_size_t, c_double = ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_double
+    ip = P(c_int)
+    lib.iblb_workspace_bytes.argtypes = [c_int, P(iblb_params), ip, ip, c_int]
+    lib.iblb_workspace_bytes.restype = c_size_t
+    lib.iblb_create.argtypes = [c_int, P(iblb_params), ip, ip, c_int, c_void_p, c_size_t,
+                                c_void_p, P(c_void_p)]
+    lib.iblb_destroy.argtypes = [c_void_p]
+    lib.iblb_last_error.argtypes = [c_void_p]
+    lib.iblb_last_error.restype = ctypes.c_char_p
+    lib.iblb_set_interface.argtypes = [c_void_p, c_int, c_void_p, c_void_p]
+    lib.iblb_init_rest.argtypes = [c_void_p, c_int]
+    lib.iblb_write_populations.argtypes = [c_void_p, c_int, c_void_p]
+    lib.iblb_read_populations.argtypes = [c_void_p, c_int, c_void_p]
+    lib.iblb_set_force_field.argtypes = [c_void_p, c_int, c_void_p]
+    lib.iblb_step.argtypes = [c_void_p, c_int]
+    lib.iblb_read_fields.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_void_p]
+    lib.iblb_read_nodes.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_void_p]
+    lib.iblb_diagnostics.argtypes = [c_void_p, c_int, P(iblb_diag)]
+    lib.iblb_set_tile_shape.argtypes = [c_void_p, c_int, ip]
+    lib.iblb_set_graph_steps.argtypes = [c_void_p, c_int]
+    lib.iblb_set_active.argtypes = [c_void_p, c_int, c_int]
+    lib.iblb_set_timing.argtypes = [c_void_p, c_int]
+    lib.iblb_last_timing.argtypes = [c_void_p, P(c_double), P(c_double)]
+    for name in EXPORTED:
+        if name not in ("iblb_workspace_bytes", "iblb_last_error"):
+            getattr(lib, name).restype = c_int
+    _lib = lib
+    return lib
+
+
+class IblbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(code, ctx=None):
+    if code != IBLB_OK:
+        msg = load().iblb_last_error(ctx)
+        raise IblbError(code, msg.decode() if msg else "")
+    return code

@@ -1,0 +1,899 @@
+// Host runtime and C ABI of the gfx950 IB-LB wetting solver (see iblb.h).
+//
+// One handle owns a batch of droplets.  All device arrays are carved from
+// the caller's workspace.  A time step is three launches on the caller's
+// stream: k_force_spread (nodes), k_lb (cells, over a tile list that
+// concatenates every active droplet's tiles), k_interp_advect (nodes).
+// Long runs replay a hipGraph that holds a fixed, even number of steps, so
+// the ping-pong buffers are back in place after every replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+// the ABI entry points are the only exported symbols
+#pragma GCC visibility push(default)
+#include "iblb.h"
+#pragma GCC visibility pop
+#include "kernels.hpp"
+
+using namespace iblb;
+
+namespace {
+
+constexpr int kShapes = 3;
+constexpr int kShapeBX[kShapes] = {256, 128, 64};
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+struct Layout {
+    // byte offsets into the workspace
+    size_t drops, tiles_lb, tiles_all, f0, f1, F, U, Fout, rho, flags, pos, phi, qdot, dropped,
+        node_drop, tri, inc, inc_beg, inc_end, status, partials, diag, total;
+    long long cells;       // sum of cells
+    long long flag_bytes;  // sum of band flags
+    int ntot, ttot, max_tiles;
+    std::vector<long long> c_off, flag_off;
+    std::vector<int> node_off, tri_off;
+};
+
+int tiles_of(const iblb_params& p, int shape) {
+    const int bx = kShapeBX[shape], by = kBlock / bx;
+    return ceil_div(p.nx, bx) * ceil_div(p.ny, by) * (p.dim == 3 ? p.nz : 1);
+}
+
+bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage, Layout& L,
+          std::string& err) {
+    if (n < 1) { err = "n_droplets must be >= 1"; return false; }
+    if (!P || !nn) { err = "params and n_nodes must not be NULL"; return false; }
+    if (storage < 0 || storage > 2) { err = "storage must be IBLB_F32, IBLB_F16 or IBLB_BF16"; return false; }
+    const int dim = P[0].dim;
+    if (dim != 2 && dim != 3) { err = "dim must be 2 or 3"; return false; }
+    const int Q = dim == 2 ? 9 : 19;
+    const int sb = storage == 0 ? 4 : 2;
+    L.cells = 0;
+    L.flag_bytes = 0;
+    L.ntot = 0;
+    L.ttot = 0;
+    L.max_tiles = 0;
+    L.c_off.assign(n, 0);
+    L.flag_off.assign(n, 0);
+    L.node_off.assign(n, 0);
+    L.tri_off.assign(n, 0);
+    int tiles[kShapes] = {0, 0, 0};
+    for (int d = 0; d < n; ++d) {
+        const iblb_params& p = P[d];
+        char buf[256];
+        if (p.dim != dim) { err = "all droplets must share dim"; return false; }
+        const int nz = dim == 3 ? p.nz : 1;
+        if (p.nx < 1 || p.ny < 1 || nz < 1) {
+            snprintf(buf, sizeof buf, "droplet %d: lattice sizes must be >= 1", d);
+            err = buf;
+            return false;
+        }
+        const long long cells = (long long)p.nx * p.ny * nz;
+        if (cells * Q >= (1LL << 31)) {
+            snprintf(buf, sizeof buf, "droplet %d: Q * cells must stay below 2^31", d);
+            err = buf;
+            return false;
+        }
+        if (!(p.tau > 0.5)) {
+            snprintf(buf, sizeof buf, "droplet %d: tau must exceed 1/2", d);
+            err = buf;
+            return false;
+        }
+        for (int a = 0; a < 3; ++a)
+            if (p.bc[a] != IBLB_PERIODIC && p.bc[a] != IBLB_WALL) {
+                snprintf(buf, sizeof buf, "droplet %d: bad boundary code", d);
+                err = buf;
+                return false;
+            }
+        if (nn[d] < 0 || (nn[d] > 0 && nn[d] < 3)) {
+            snprintf(buf, sizeof buf, "droplet %d: an interface needs at least 3 nodes", d);
+            err = buf;
+            return false;
+        }
+        if (nn[d] > 0 && p.wetting && !(p.xi > 0.0 && p.n_exp > p.m_exp && p.m_exp >= 1)) {
+            snprintf(buf, sizeof buf, "droplet %d: wetting needs xi > 0 and n > m >= 1", d);
+            err = buf;
+            return false;
+        }
+        const int T = (dim == 3 && nt) ? nt[d] : 0;
+        if (dim == 3 && nn[d] > 0 && T < 4) {
+            snprintf(buf, sizeof buf, "droplet %d: a closed 3D mesh needs >= 4 triangles", d);
+            err = buf;
+            return false;
+        }
+        L.c_off[d] = L.cells;
+        L.cells += cells;
+        L.flag_off[d] = L.flag_bytes;
+        L.flag_bytes += (long long)nz * p.ny * ceil_div(p.nx, kStrip);
+        L.node_off[d] = L.ntot;
+        L.ntot += nn[d];
+        L.tri_off[d] = L.ttot;
+        L.ttot += T;
+        for (int s = 0; s < kShapes; ++s) tiles[s] += tiles_of(p, s);
+    }
+    for (int s = 0; s < kShapes; ++s) L.max_tiles = std::max(L.max_tiles, tiles[s]);
+    const long long C = L.cells;
+    const int N = std::max(L.ntot, 1), T = std::max(L.ttot, 1);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    L.drops = take(sizeof(DropDev) * n);
+    L.tiles_lb = take(sizeof(int4) * L.max_tiles);
+    L.tiles_all = take(sizeof(int4) * L.max_tiles);
+    L.f0 = take((size_t)Q * C * sb);
+    L.f1 = take((size_t)Q * C * sb);
+    L.F = take(sizeof(float) * dim * C);
+    L.U = take(sizeof(float) * dim * C);
+    L.Fout = take(sizeof(float) * dim * C);
+    L.rho = take(sizeof(float) * C);
+    L.flags = take((size_t)L.flag_bytes);
+    L.pos = take(sizeof(double) * 3 * N);
+    L.phi = take(sizeof(float) * 3 * N);
+    L.qdot = take(sizeof(float) * 3 * N);
+    L.dropped = take(sizeof(float) * 3 * N);
+    L.node_drop = take(sizeof(int) * N);
+    L.tri = take(sizeof(int) * 3 * T);
+    L.inc = take(sizeof(int) * 3 * T);
+    L.inc_beg = take(sizeof(int) * N);
+    L.inc_end = take(sizeof(int) * N);
+    L.status = take(sizeof(int) * n);
+    L.partials = take(sizeof(double) * 8 * L.max_tiles);
+    L.diag = take(sizeof(DiagDev) * n);
+    L.total = o;
+    return true;
+}
+
+}  // namespace
+
+struct iblb_ctx {
+    int n = 0, dim = 2, Q = 9, storage = 0;
+    std::vector<iblb_params> params;
+    std::vector<int> n_nodes, n_tris;
+    std::vector<DropDev> drops;
+    Layout L;
+    char* ws = nullptr;
+    hipStream_t stream = nullptr, cap_stream = nullptr;
+    int cur = 0;  // buffer holding the current post-collision populations
+    int shape = 0;
+    int ntiles_lb = 0, ntiles_all = 0;
+    bool tiles_dirty = true;
+    std::vector<int4> tiles_h;
+    int graph_steps = 64;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    bool timing = false;
+    double t_lb = 0.0, t_step = 0.0;
+    std::vector<hipEvent_t> events;
+    long long step = 0;
+    std::vector<int> status_h;
+    std::vector<char> iface_set;
+    std::string err;
+
+    template <typename T>
+    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(iblb_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg; else g_create_err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(ctx, IBLB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+NodeArrays node_arrays(const iblb_ctx* c) {
+    NodeArrays A;
+    A.pos = c->at<double>(c->L.pos);
+    A.pos_w = c->at<double>(c->L.pos);
+    A.phi = c->at<float>(c->L.phi);
+    A.qdot = c->at<float>(c->L.qdot);
+    A.dropped = c->at<float>(c->L.dropped);
+    A.node_drop = c->at<int>(c->L.node_drop);
+    A.tri = c->at<int>(c->L.tri);
+    A.inc = c->at<int>(c->L.inc);
+    A.inc_beg = c->at<int>(c->L.inc_beg);
+    A.inc_end = c->at<int>(c->L.inc_end);
+    A.stride = std::max(c->L.ntot, 1);
+    A.tstride = std::max(c->L.ttot, 1);
+    A.ntot = c->L.ntot;
+    return A;
+}
+
+void drop_graphs(iblb_ctx* c) {
+    for (int k = 0; k < 2; ++k)
+        if (c->exec[k]) {
+            (void)hipGraphExecDestroy(c->exec[k]);
+            c->exec[k] = nullptr;
+        }
+}
+
+int upload_drops(iblb_ctx* c) {
+    HIPCHK(c, hipMemcpyAsync(c->at<DropDev>(c->L.drops), c->drops.data(),
+                             sizeof(DropDev) * c->n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return IBLB_OK;
+}
+
+// Tiles of droplet d, x fastest, then y, then z.
+void push_tiles(const iblb_ctx* c, int d, std::vector<int4>& v) {
+    const iblb_params& p = c->params[d];
+    const int bx = kShapeBX[c->shape], by = kBlock / bx;
+    const int ntx = ceil_div(p.nx, bx), nty = ceil_div(p.ny, by);
+    const int nz = c->dim == 3 ? p.nz : 1;
+    for (int z = 0; z < nz; ++z)
+        for (int ty = 0; ty < nty; ++ty)
+            for (int tx = 0; tx < ntx; ++tx) v.push_back(make_int4(d, tx, ty, z));
+}
+
+int rebuild_tiles(iblb_ctx* c) {
+    std::vector<int4> all, lb;
+    for (int d = 0; d < c->n; ++d) {
+        c->drops[d].tile_off = (int)all.size();
+        push_tiles(c, d, all);
+        c->drops[d].n_tiles = (int)all.size() - c->drops[d].tile_off;
+        if (c->drops[d].active) push_tiles(c, d, lb);
+    }
+    c->ntiles_all = (int)all.size();
+    c->ntiles_lb = (int)lb.size();
+    HIPCHK(c, hipMemcpyAsync(c->at<int4>(c->L.tiles_all), all.data(), sizeof(int4) * all.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    if (!lb.empty())
+        HIPCHK(c, hipMemcpyAsync(c->at<int4>(c->L.tiles_lb), lb.data(), sizeof(int4) * lb.size(),
+                                 hipMemcpyHostToDevice, c->stream));
+    int rc = upload_drops(c);  // synchronises: the host vectors may go
+    if (rc) return rc;
+    drop_graphs(c);
+    c->tiles_dirty = false;
+    return IBLB_OK;
+}
+
+// ---- kernel dispatch -------------------------------------------------------
+
+template <int DIM, int S>
+void launch_lb_t(const iblb_ctx* c, hipStream_t s, int src, int full) {
+    using T = typename Codec<S>::T;
+    T* f[2] = {c->at<T>(c->L.f0), c->at<T>(c->L.f1)};
+    const dim3 grid(c->ntiles_lb), block(kBlock);
+    auto args = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, block, 0, s, c->at<DropDev>(c->L.drops),
+                           c->at<int4>(c->L.tiles_lb), f[src], f[src ^ 1], c->at<float>(c->L.F),
+                           c->at<float>(c->L.U), c->at<float>(c->L.rho), c->at<float>(c->L.Fout),
+                           c->at<uint8_t>(c->L.flags), full);
+    };
+    switch (c->shape) {
+        case 0: args(k_lb<DIM, S, 256>); break;
+        case 1: args(k_lb<DIM, S, 128>); break;
+        default: args(k_lb<DIM, S, 64>); break;
+    }
+}
+
+template <int DIM>
+void launch_lb_d(const iblb_ctx* c, hipStream_t s, int src, int full) {
+    switch (c->storage) {
+        case ST_F32: launch_lb_t<DIM, ST_F32>(c, s, src, full); break;
+        case ST_F16: launch_lb_t<DIM, ST_F16>(c, s, src, full); break;
+        default: launch_lb_t<DIM, ST_BF16>(c, s, src, full); break;
+    }
+}
+
+void launch_lb(const iblb_ctx* c, hipStream_t s, int src, int full) {
+    if (c->ntiles_lb == 0) return;
+    if (c->dim == 2) launch_lb_d<2>(c, s, src, full);
+    else launch_lb_d<3>(c, s, src, full);
+}
+
+void launch_nodes(const iblb_ctx* c, hipStream_t s, int phase, int full) {
+    if (c->L.ntot == 0) return;
+    const NodeArrays A = node_arrays(c);
+    const dim3 grid(ceil_div(c->L.ntot, kBlock)), block(kBlock);
+    const DropDev* D = c->at<DropDev>(c->L.drops);
+    if (phase == 0) {
+        if (c->dim == 2)
+            hipLaunchKernelGGL(k_force_spread<2>, grid, block, 0, s, D, A, c->at<float>(c->L.F),
+                               c->at<uint8_t>(c->L.flags), full);
+        else
+            hipLaunchKernelGGL(k_force_spread<3>, grid, block, 0, s, D, A, c->at<float>(c->L.F),
+                               c->at<uint8_t>(c->L.flags), full);
+    } else {
+        if (c->dim == 2)
+            hipLaunchKernelGGL(k_interp_advect<2>, grid, block, 0, s, D, A, c->at<float>(c->L.U),
+                               c->at<int>(c->L.status));
+        else
+            hipLaunchKernelGGL(k_interp_advect<3>, grid, block, 0, s, D, A, c->at<float>(c->L.U),
+                               c->at<int>(c->L.status));
+    }
+}
+
+// One time step from buffer `src`; events (may be null) bracket the lattice
+// kernel.
+void launch_step(const iblb_ctx* c, hipStream_t s, int src, int full, hipEvent_t e0 = nullptr,
+                 hipEvent_t e1 = nullptr) {
+    launch_nodes(c, s, 0, full);
+    if (e0) (void)hipEventRecord(e0, s);
+    launch_lb(c, s, src, full);
+    if (e1) (void)hipEventRecord(e1, s);
+    launch_nodes(c, s, 1, full);
+}
+
+int ensure_graph(iblb_ctx* c, int parity) {
+    if (c->exec[parity]) return IBLB_OK;
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int src = parity;
+    for (int k = 0; k < c->graph_steps; ++k) {
+        launch_step(c, c->cap_stream, src, 0);
+        src ^= 1;
+    }
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (e != hipSuccess) return fail(c, IBLB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->exec[parity], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->exec[parity] = nullptr;
+        return fail(c, IBLB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return IBLB_OK;
+}
+
+int check_droplet(const iblb_ctx* c, int d) {
+    return c && d >= 0 && d < c->n;
+}
+
+template <int S>
+void launch_pop_io(iblb_ctx* c, int d, const double* in, double* out) {
+    using T = typename Codec<S>::T;
+    T* f = c->at<T>(c->cur ? c->L.f1 : c->L.f0) + c->drops[d].f_off;
+    const long long n = (long long)c->Q * c->drops[d].ncell;
+    if (in)
+        hipLaunchKernelGGL(k_pop_write<S>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, c->stream, f,
+                           n, in);
+    else
+        hipLaunchKernelGGL(k_pop_read<S>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, c->stream,
+                           (const T*)f, n, out);
+}
+
+int pop_io(iblb_ctx* c, int d, const double* in, double* out) {
+    if (!check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
+    if (!in && !out) return fail(c, IBLB_EINVAL, "NULL population array");
+    switch (c->storage) {
+        case ST_F32: launch_pop_io<ST_F32>(c, d, in, out); break;
+        case ST_F16: launch_pop_io<ST_F16>(c, d, in, out); break;
+        default: launch_pop_io<ST_BF16>(c, d, in, out); break;
+    }
+    HIPCHK(c, hipGetLastError());
+    return IBLB_OK;
+}
+
+int reset_droplet(iblb_ctx* c, int d) {
+    const DropDev& D = c->drops[d];
+    const size_t sb = c->storage == ST_F32 ? 4 : 2;
+    // zero deviation = rest state, in both buffers
+    HIPCHK(c, hipMemsetAsync(c->ws + c->L.f0 + D.f_off * sb, 0, (size_t)c->Q * D.ncell * sb, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->ws + c->L.f1 + D.f_off * sb, 0, (size_t)c->Q * D.ncell * sb, c->stream));
+    const size_t vb = sizeof(float) * c->dim * D.ncell, vo = sizeof(float) * c->dim * D.c_off;
+    HIPCHK(c, hipMemsetAsync(c->ws + c->L.F + vo, 0, vb, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->ws + c->L.U + vo, 0, vb, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->ws + c->L.Fout + vo, 0, vb, c->stream));
+    const iblb_params& p = c->params[d];
+    const size_t fb = (size_t)(c->dim == 3 ? p.nz : 1) * p.ny * ceil_div(p.nx, kStrip);
+    HIPCHK(c, hipMemsetAsync(c->ws + c->L.flags + D.flag_off, 0, fb, c->stream));
+    hipLaunchKernelGGL(k_fill_f32, dim3(ceil_div(D.ncell, kBlock)), dim3(kBlock), 0, c->stream,
+                       c->at<float>(c->L.rho) + D.c_off, (long long)D.ncell, 1.0f);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemsetAsync(c->at<int>(c->L.status) + d, 0, sizeof(int), c->stream));
+    return IBLB_OK;
+}
+
+double angle_from_height(int dim, double volume, double height) {
+    const double ell = 0.5 * height;
+    if (!(ell > 0.0) || !(volume > 0.0)) return NAN;
+    if (dim == 3) {
+        // tan^2(theta/2) = 3 l^3 / (R0^3 - l^3), R0 of the equal-volume sphere
+        const double R03 = 3.0 * volume / (4.0 * M_PI);
+        const double l3 = ell * ell * ell;
+        if (l3 >= R03) return M_PI;
+        return 2.0 * atan(sqrt(3.0 * l3 / (R03 - l3)));
+    }
+    // circular cap of angle theta: area / l^2 = (theta - sin cos) / sin^4(theta/2),
+    // decreasing on (0, pi)
+    const double target = volume / (ell * ell);
+    auto g = [](double th) {
+        const double s = sin(0.5 * th);
+        return (th - sin(th) * cos(th)) / (s * s * s * s);
+    };
+    double lo = 1e-6, hi = M_PI;
+    if (target <= g(hi)) return M_PI;
+    for (int k = 0; k < 200; ++k) {
+        const double mid = 0.5 * (lo + hi);
+        if (g(mid) > target) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+template <int DIM, int S>
+void launch_cell_sums(iblb_ctx* c) {
+    using T = typename Codec<S>::T;
+    const T* f = c->at<T>(c->cur ? c->L.f1 : c->L.f0);
+    const dim3 grid(c->ntiles_all), block(kBlock);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, block, 0, c->stream, c->at<DropDev>(c->L.drops),
+                           c->at<int4>(c->L.tiles_all), f, c->at<float>(c->L.U), c->at<float>(c->L.rho),
+                           c->at<float>(c->L.Fout), c->at<double>(c->L.partials));
+    };
+    switch (c->shape) {
+        case 0: go(k_cell_sums<DIM, S, 256>); break;
+        case 1: go(k_cell_sums<DIM, S, 128>); break;
+        default: go(k_cell_sums<DIM, S, 64>); break;
+    }
+}
+
+template <int DIM>
+void launch_diag_d(iblb_ctx* c) {
+    switch (c->storage) {
+        case ST_F32: launch_cell_sums<DIM, ST_F32>(c); break;
+        case ST_F16: launch_cell_sums<DIM, ST_F16>(c); break;
+        default: launch_cell_sums<DIM, ST_BF16>(c); break;
+    }
+    hipLaunchKernelGGL(k_diag<DIM>, dim3(c->n), dim3(kBlock), 0, c->stream, c->at<DropDev>(c->L.drops),
+                       node_arrays(c), c->at<double>(c->L.partials), c->at<DiagDev>(c->L.diag));
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+extern "C" {
+
+size_t iblb_workspace_bytes(int n_droplets, const iblb_params* params, const int* n_nodes,
+                            const int* n_tris, int storage) {
+    Layout L;
+    std::string err;
+    if (!plan(n_droplets, params, n_nodes, n_tris, storage, L, err)) return 0;
+    return L.total;
+}
+
+int iblb_create(int n, const iblb_params* P, const int* nn, const int* nt, int storage,
+                void* d_ws, size_t ws_bytes, void* stream, iblb_ctx** out) {
+    if (!out) return fail(nullptr, IBLB_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    Layout L;
+    std::string err;
+    if (!plan(n, P, nn, nt, storage, L, err)) return fail(nullptr, IBLB_EINVAL, err);
+    if (!d_ws) return fail(nullptr, IBLB_EINVAL, "NULL workspace");
+    if (ws_bytes < L.total) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
+                 L.total);
+        return fail(nullptr, IBLB_ENOMEM, buf);
+    }
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign)
+        return fail(nullptr, IBLB_EINVAL, "workspace must be 256-byte aligned");
+    iblb_ctx* c = new iblb_ctx();
+    c->n = n;
+    c->dim = P[0].dim;
+    c->Q = c->dim == 2 ? 9 : 19;
+    c->storage = storage;
+    c->params.assign(P, P + n);
+    c->n_nodes.assign(nn, nn + n);
+    c->n_tris.assign(n, 0);
+    if (c->dim == 3 && nt) c->n_tris.assign(nt, nt + n);
+    c->L = L;
+    c->ws = static_cast<char*>(d_ws);
+    c->stream = static_cast<hipStream_t>(stream);
+    c->status_h.assign(n, 0);
+    c->iface_set.assign(n, 0);
+    c->drops.resize(n);
+    for (int d = 0; d < n; ++d) {
+        const iblb_params& p = P[d];
+        DropDev& D = c->drops[d];
+        memset(&D, 0, sizeof D);
+        D.nx = p.nx;
+        D.ny = p.ny;
+        D.nz = c->dim == 3 ? p.nz : 1;
+        D.nstrip = ceil_div(p.nx, kStrip);
+        D.bcx = p.bc[0];
+        D.bcy = p.bc[1];
+        D.bcz = c->dim == 3 ? p.bc[2] : 0;
+        D.ncell = p.nx * p.ny * D.nz;
+        D.f_off = (long long)c->Q * L.c_off[d];
+        D.c_off = L.c_off[d];
+        D.flag_off = L.flag_off[d];
+        D.omega = (float)(1.0 / p.tau);
+        D.guo = (float)(1.0 - 0.5 / p.tau);
+        D.force_mode = 0;
+        D.active = 1;
+        D.node_off = L.node_off[d];
+        D.n_nodes = nn[d];
+        D.tri_off = L.tri_off[d];
+        D.n_tris = c->n_tris[d];
+        D.wetting = p.wetting ? 1 : 0;
+        D.n_exp = p.n_exp;
+        D.m_exp = p.m_exp;
+        D.sigma = p.sigma;
+        D.xi = p.xi;
+        // eq. (A_choice)
+        D.A = p.wetting ? p.sigma * (double)((p.m_exp - 1) * (p.n_exp - 1)) /
+                              ((double)(p.n_exp - p.m_exp) * p.xi) * (1.0 + cos(p.theta_eq))
+                        : 0.0;
+        // minimum of Pi(h): h* = xi (n/m)^(1/(n-m))
+        D.zcut = p.wetting ? p.xi * pow((double)p.n_exp / p.m_exp, 1.0 / (p.n_exp - p.m_exp))
+                           : p.xi;
+    }
+    hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        g_create_err = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+        delete c;
+        return IBLB_EDEVICE;
+    }
+    // node -> droplet table; positions zero until set
+    std::vector<int> nd(std::max(L.ntot, 1), 0);
+    for (int d = 0; d < n; ++d)
+        for (int k = 0; k < nn[d]; ++k) nd[L.node_off[d] + k] = d;
+    int rc = IBLB_OK;
+    auto chk = [&](hipError_t ee, const char* what) {
+        if (ee != hipSuccess && rc == IBLB_OK) {
+            g_create_err = std::string(what) + ": " + hipGetErrorString(ee);
+            rc = IBLB_EDEVICE;
+        }
+    };
+    chk(hipMemsetAsync(c->ws, 0, L.total, c->stream), "hipMemsetAsync");
+    chk(hipMemcpyAsync(c->at<int>(L.node_drop), nd.data(), sizeof(int) * nd.size(),
+                       hipMemcpyHostToDevice, c->stream), "hipMemcpyAsync");
+    chk(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (rc == IBLB_OK) {
+        for (int d = 0; d < n && rc == IBLB_OK; ++d) {
+            int r = reset_droplet(c, d);
+            if (r) { g_create_err = c->err; rc = r; }
+        }
+    }
+    if (rc == IBLB_OK) {
+        int r = rebuild_tiles(c);
+        if (r) { g_create_err = c->err; rc = r; }
+    }
+    if (rc != IBLB_OK) {
+        (void)hipStreamDestroy(c->cap_stream);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return IBLB_OK;
+}
+
+int iblb_destroy(iblb_ctx* c) {
+    if (!c) return IBLB_OK;
+    drop_graphs(c);
+    for (auto ev : c->events) (void)hipEventDestroy(ev);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+    return IBLB_OK;
+}
+
+const char* iblb_last_error(const iblb_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+int iblb_set_interface(iblb_ctx* c, int d, const double* h_pos, const int32_t* h_tris) {
+    if (!check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
+    const int N = c->n_nodes[d];
+    if (N == 0) return IBLB_OK;
+    if (!h_pos) return fail(c, IBLB_EINVAL, "NULL positions");
+    const DropDev& D = c->drops[d];
+    const int st = std::max(c->L.ntot, 1);
+    for (int a = 0; a < c->dim; ++a)
+        for (int k = 0; k < N; ++k)
+            if (!std::isfinite(h_pos[(size_t)a * N + k]))
+                return fail(c, IBLB_EINVAL, "non-finite node position");
+    if (c->params[d].wetting)
+        for (int k = 0; k < N; ++k)
+            if (!(h_pos[(size_t)(c->dim - 1) * N + k] > 0.0))
+                return fail(c, IBLB_EINVAL, "a node lies at or below the substrate (h <= 0)");
+    std::vector<double> pos(h_pos, h_pos + (size_t)c->dim * N);
+    for (int a = 0; a < c->dim; ++a)
+        HIPCHK(c, hipMemcpyAsync(c->at<double>(c->L.pos) + (size_t)a * st + D.node_off,
+                                 pos.data() + (size_t)a * N, sizeof(double) * N,
+                                 hipMemcpyHostToDevice, c->stream));
+    std::vector<int> tri, inc, beg, end;
+    if (c->dim == 3) {
+        const int T = c->n_tris[d];
+        if (!h_tris) return fail(c, IBLB_EINVAL, "NULL triangle list");
+        const int ts = std::max(c->L.ttot, 1);
+        std::vector<int> cnt(N, 0);
+        for (int t = 0; t < T; ++t)
+            for (int s = 0; s < 3; ++s) {
+                const int v = h_tris[3 * t + s];
+                if (v < 0 || v >= N) return fail(c, IBLB_EINVAL, "triangle vertex index out of range");
+                cnt[v]++;
+            }
+        for (int k = 0; k < N; ++k)
+            if (cnt[k] == 0) return fail(c, IBLB_EINVAL, "a vertex belongs to no triangle");
+        // incidence list (CSR by vertex), global triangle and node ids
+        beg.resize(N);
+        end.resize(N);
+        int acc = 3 * D.tri_off;
+        for (int k = 0; k < N; ++k) {
+            beg[k] = acc;
+            acc += cnt[k];
+            end[k] = beg[k];
+        }
+        inc.assign(3 * T, 0);
+        tri.assign(3 * T, 0);
+        for (int t = 0; t < T; ++t)
+            for (int s = 0; s < 3; ++s) {
+                const int v = h_tris[3 * t + s];
+                tri[(size_t)s * T + t] = D.node_off + v;
+                inc[end[v] - 3 * D.tri_off] = ((D.tri_off + t) << 2) | s;
+                end[v]++;
+            }
+        for (int s = 0; s < 3; ++s)
+            HIPCHK(c, hipMemcpyAsync(c->at<int>(c->L.tri) + (size_t)s * ts + D.tri_off,
+                                     tri.data() + (size_t)s * T, sizeof(int) * T,
+                                     hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->at<int>(c->L.inc) + 3 * D.tri_off, inc.data(), sizeof(int) * 3 * T,
+                                 hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->at<int>(c->L.inc_beg) + D.node_off, beg.data(), sizeof(int) * N,
+                                 hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->at<int>(c->L.inc_end) + D.node_off, end.data(), sizeof(int) * N,
+                                 hipMemcpyHostToDevice, c->stream));
+    }
+    HIPCHK(c, hipMemsetAsync(c->at<int>(c->L.status) + d, 0, sizeof(int), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // host staging vectors go out of scope
+    c->iface_set[d] = 1;
+    return IBLB_OK;
+}
+
+int iblb_init_rest(iblb_ctx* c, int d) {
+    if (!c) return IBLB_EINVAL;
+    if (d == -1) {
+        for (int k = 0; k < c->n; ++k) {
+            int rc = reset_droplet(c, k);
+            if (rc) return rc;
+        }
+        return IBLB_OK;
+    }
+    if (!check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
+    return reset_droplet(c, d);
+}
+
+int iblb_write_populations(iblb_ctx* c, int d, const double* d_fdev) {
+    return pop_io(c, d, d_fdev, nullptr);
+}
+
+int iblb_read_populations(iblb_ctx* c, int d, double* d_fdev) { return pop_io(c, d, nullptr, d_fdev); }
+
+int iblb_set_force_field(iblb_ctx* c, int d, const float* d_F) {
+    if (!check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
+    DropDev& D = c->drops[d];
+    const size_t vb = sizeof(float) * c->dim * D.ncell, vo = sizeof(float) * c->dim * D.c_off;
+    if (d_F) {
+        HIPCHK(c, hipMemcpyAsync(c->ws + c->L.F + vo, d_F, vb, hipMemcpyDeviceToDevice, c->stream));
+        D.force_mode = 1;
+    } else {
+        HIPCHK(c, hipMemsetAsync(c->ws + c->L.F + vo, 0, vb, c->stream));
+        D.force_mode = 0;
+    }
+    return upload_drops(c);
+}
+
+int iblb_step(iblb_ctx* c, int n_steps) {
+    if (!c) return IBLB_EINVAL;
+    if (n_steps < 0) return fail(c, IBLB_EINVAL, "n_steps must be >= 0");
+    if (n_steps == 0) return IBLB_OK;
+    for (int d = 0; d < c->n; ++d)
+        if (c->n_nodes[d] > 0 && !c->iface_set[d] && c->drops[d].force_mode == 0) {
+            char buf[96];
+            snprintf(buf, sizeof buf, "droplet %d: interface not set", d);
+            return fail(c, IBLB_EINVAL, buf);
+        }
+    if (c->tiles_dirty) {
+        int rc = rebuild_tiles(c);
+        if (rc) return rc;
+    }
+    if (c->timing) {
+        // direct launches with events around every lattice kernel
+        const int need = 2 * n_steps + 2;
+        while ((int)c->events.size() < need) {
+            hipEvent_t ev;
+            HIPCHK(c, hipEventCreate(&ev));
+            c->events.push_back(ev);
+        }
+        HIPCHK(c, hipEventRecord(c->events[0], c->stream));
+        for (int k = 0; k < n_steps; ++k) {
+            launch_step(c, c->stream, c->cur, k == n_steps - 1, c->events[2 + 2 * k],
+                        c->events[3 + 2 * k]);
+            c->cur ^= 1;
+        }
+        HIPCHK(c, hipEventRecord(c->events[1], c->stream));
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipEventSynchronize(c->events[1]));
+        float ms = 0.f;
+        double lb = 0.0;
+        const int nlb = n_steps > 1 ? n_steps - 1 : 1;  // the last step also stores fields
+        for (int k = 0; k < nlb; ++k) {
+            HIPCHK(c, hipEventElapsedTime(&ms, c->events[2 + 2 * k], c->events[3 + 2 * k]));
+            lb += ms;
+        }
+        c->t_lb = lb / nlb;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->events[0], c->events[1]));
+        c->t_step = ms / n_steps;
+        c->step += n_steps;
+    } else {
+        int rem = n_steps;
+        while (rem > 1) {
+            if (c->graph_steps > 0 && rem - 1 >= c->graph_steps) {
+                int rc = ensure_graph(c, c->cur);
+                if (rc) return rc;
+                HIPCHK(c, hipGraphLaunch(c->exec[c->cur], c->stream));
+                rem -= c->graph_steps;
+                c->step += c->graph_steps;
+            } else {
+                launch_step(c, c->stream, c->cur, 0);
+                c->cur ^= 1;
+                rem--;
+                c->step++;
+            }
+        }
+        launch_step(c, c->stream, c->cur, 1);
+        c->cur ^= 1;
+        c->step++;
+        HIPCHK(c, hipGetLastError());
+    }
+    HIPCHK(c, hipMemcpyAsync(c->status_h.data(), c->at<int>(c->L.status), sizeof(int) * c->n,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int d = 0; d < c->n; ++d)
+        if (c->status_h[d] && c->drops[d].active) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "droplet %d unstable (code %d: %s) by step %lld", d,
+                     c->status_h[d],
+                     (c->status_h[d] & 1) ? "node at or below the substrate" : "node speed",
+                     (long long)c->step);
+            return fail(c, IBLB_EUNSTABLE, buf);
+        }
+    return IBLB_OK;
+}
+
+int iblb_read_fields(iblb_ctx* c, int d, float* d_rho, float* d_u, float* d_F) {
+    if (!check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
+    const DropDev& D = c->drops[d];
+    const size_t vb = sizeof(float) * c->dim * D.ncell, vo = sizeof(float) * c->dim * D.c_off;
+    if (d_rho)
+        HIPCHK(c, hipMemcpyAsync(d_rho, c->at<float>(c->L.rho) + D.c_off, sizeof(float) * D.ncell,
+                                 hipMemcpyDeviceToDevice, c->stream));
+    if (d_u) HIPCHK(c, hipMemcpyAsync(d_u, c->ws + c->L.U + vo, vb, hipMemcpyDeviceToDevice, c->stream));
+    if (d_F) HIPCHK(c, hipMemcpyAsync(d_F, c->ws + c->L.Fout + vo, vb, hipMemcpyDeviceToDevice, c->stream));
+    return IBLB_OK;
+}
+
+int iblb_read_nodes(iblb_ctx* c, int d, double* h_pos, float* h_vel, float* h_force) {
+    if (!check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
+    const int N = c->n_nodes[d];
+    const int st = std::max(c->L.ntot, 1);
+    const int o = c->drops[d].node_off;
+    for (int a = 0; a < c->dim && N > 0; ++a) {
+        if (h_pos)
+            HIPCHK(c, hipMemcpyAsync(h_pos + (size_t)a * N, c->at<double>(c->L.pos) + (size_t)a * st + o,
+                                     sizeof(double) * N, hipMemcpyDeviceToHost, c->stream));
+        if (h_vel)
+            HIPCHK(c, hipMemcpyAsync(h_vel + (size_t)a * N, c->at<float>(c->L.qdot) + (size_t)a * st + o,
+                                     sizeof(float) * N, hipMemcpyDeviceToHost, c->stream));
+        if (h_force)
+            HIPCHK(c, hipMemcpyAsync(h_force + (size_t)a * N, c->at<float>(c->L.phi) + (size_t)a * st + o,
+                                     sizeof(float) * N, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return IBLB_OK;
+}
+
+static void fill_diag(const iblb_ctx* c, int d, const DiagDev& r, int st, iblb_diag* out) {
+    memset(out, 0, sizeof *out);
+    out->step = c->step;
+    out->mass = (double)c->drops[d].ncell + r.mass_dev;
+    for (int a = 0; a < 3; ++a) {
+        out->momentum[a] = r.mom[a];
+        out->sum_phi[a] = r.sum_phi[a];
+        out->sum_F[a] = r.sum_F[a];
+        out->dropped_F[a] = r.dropped[a];
+    }
+    const bool has_iface = c->n_nodes[d] > 0;
+    out->volume = has_iface ? r.volume : 0.0;
+    out->area = has_iface ? r.area : 0.0;
+    out->height = has_iface ? r.max_h - r.min_h : 0.0;
+    out->min_h = has_iface ? r.min_h : NAN;
+    out->max_normal_speed = r.max_un;
+    out->max_speed = r.max_u;
+    out->edge_min = has_iface ? r.edge_min : NAN;
+    out->edge_max = has_iface ? r.edge_max : NAN;
+    if (c->dim == 2)
+        out->contact_radius = (has_iface && r.cross_hi > r.cross_lo) ? 0.5 * (r.cross_hi - r.cross_lo) : NAN;
+    else
+        out->contact_radius = (has_iface && r.cross_n > 0) ? r.cross_r : NAN;
+    out->theta_meas = has_iface ? angle_from_height(c->dim, r.volume, out->height) : NAN;
+    out->status = st ? IBLB_EUNSTABLE : IBLB_OK;
+}
+
+int iblb_diagnostics(iblb_ctx* c, int d, iblb_diag* out) {
+    if (!c) return IBLB_EINVAL;
+    if (d != -1 && !check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
+    if (!out) return fail(c, IBLB_EINVAL, "NULL output");
+    if (c->tiles_dirty) {
+        int rc = rebuild_tiles(c);
+        if (rc) return rc;
+    }
+    if (c->dim == 2) launch_diag_d<2>(c);
+    else launch_diag_d<3>(c);
+    HIPCHK(c, hipGetLastError());
+    std::vector<DiagDev> r(c->n);
+    std::vector<int> st(c->n);
+    HIPCHK(c, hipMemcpyAsync(r.data(), c->at<DiagDev>(c->L.diag), sizeof(DiagDev) * c->n,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(st.data(), c->at<int>(c->L.status), sizeof(int) * c->n,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (d >= 0) {
+        fill_diag(c, d, r[d], st[d], out);
+    } else {
+        for (int k = 0; k < c->n; ++k) fill_diag(c, k, r[k], st[k], out + k);
+    }
+    return IBLB_OK;
+}
+
+int iblb_set_tile_shape(iblb_ctx* c, int shape, int* shape_out) {
+    if (!c) return IBLB_EINVAL;
+    if (shape >= kShapes || shape < -1) return fail(c, IBLB_EINVAL, "tile shape must be -1, 0, 1 or 2");
+    if (shape >= 0 && shape != c->shape) {
+        c->shape = shape;
+        c->tiles_dirty = true;
+    }
+    if (shape_out) *shape_out = c->shape;
+    return IBLB_OK;
+}
+
+int iblb_set_graph_steps(iblb_ctx* c, int steps) {
+    if (!c) return IBLB_EINVAL;
+    if (steps < 0 || steps == 1 || (steps & 1)) return fail(c, IBLB_EINVAL, "graph steps must be 0 or an even number >= 2");
+    if (steps != c->graph_steps) {
+        drop_graphs(c);
+        c->graph_steps = steps;
+    }
+    return IBLB_OK;
+}
+
+int iblb_set_active(iblb_ctx* c, int d, int active) {
+    if (!check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
+    const int a = active ? 1 : 0;
+    if (c->drops[d].active != a) {
+        c->drops[d].active = a;
+        c->tiles_dirty = true;
+    }
+    return IBLB_OK;
+}
+
+int iblb_set_timing(iblb_ctx* c, int on) {
+    if (!c) return IBLB_EINVAL;
+    c->timing = on != 0;
+    return IBLB_OK;
+}
+
+int iblb_last_timing(const iblb_ctx* c, double* lb_ms, double* step_ms) {
+    if (!c) return IBLB_EINVAL;
+    if (lb_ms) *lb_ms = c->t_lb;
+    if (step_ms) *step_ms = c->t_step;
+    return IBLB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,696 @@
+// gfx950 kernels of the IB-LB wetting solver.
+//
+// Every kernel works on a batch of independent droplets described by a
+// device table of DropDev records; a single droplet is a batch of one.
+//
+//   k_lb              fused pull-stream + BGK collide + Guo source for every
+//                     fluid cell (eq. LBE, equilibrium, S_i, moments of eqs.
+//                     hydro_var1/hydro_var2); HBM bound, one cell per lane
+//   k_force_spread    nodal surface-tension + wetting forces, spread to the
+//                     lattice with the Peskin 4-point kernel (eq. force_spread)
+//   k_interp_advect   lattice velocity interpolated at the nodes (eq.
+//                     vel_interpolation) and forward-Euler advection
+//   k_cell_sums,
+//   k_diag            FP64 reductions for the diagnostics
+//
+// Populations are stored as deviations f_i - w_i (see lattice.hpp), in two
+// ping-pong buffers laid out [i][z][y][x] per droplet, x fastest.
+//
+// The force density F and the velocity U are dense per-cell arrays, but the
+// lattice kernel touches them only inside the interface band: the spreading
+// kernel raises a one-byte flag for every 64-cell x strip (one wavefront of
+// the lattice kernel) that receives a tap, and only flagged wavefronts read
+// F, write U for the interpolation, clear F and clear the flag.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lattice.hpp"
+
+namespace iblb {
+
+constexpr int kBlock = 256;   // threads per block of every kernel
+constexpr int kStrip = 64;    // cells per band flag (one wavefront)
+
+struct DropDev {
+    int nx, ny, nz, nstrip;
+    int bcx, bcy, bcz, ncell;
+    long long f_off;      // element offset of the populations (Q * ncell each)
+    long long c_off;      // cell offset; vector arrays start at dim * c_off
+    long long flag_off;   // byte offset of the band flags
+    float omega, guo;     // 1/tau and 1 - 1/(2 tau)
+    int force_mode;       // 0: immersed boundary, 1: prescribed field
+    int active;
+    int node_off, n_nodes;
+    int tri_off, n_tris;
+    int tile_off, n_tiles;  // this droplet's run in the list of all tiles
+    int wetting, n_exp, m_exp, pad_;
+    double sigma, A, xi, zcut;
+};
+
+struct DiagDev {
+    double mass_dev;            // sum over cells of rho - 1
+    double mom[3];
+    double sum_F[3];
+    double sum_phi[3];
+    double dropped[3];
+    double volume, area;
+    double min_h, max_h;
+    double max_un, max_u;
+    double edge_min, edge_max;
+    double cross_lo, cross_hi;  // 2D: outermost crossings of y = zcut
+    double cross_r;             // 3D: mean distance of crossings to their centre
+    double cross_n;
+};
+
+// Blocks are dealt round-robin to the eight XCDs.  Remap the block index so
+// that each XCD works through one contiguous run of tiles: x-neighbouring
+// strips and y-neighbouring rows then meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7, l = b >> 3;
+    return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
+// ---------------------------------------------------------------------------
+// Lattice kernel
+// ---------------------------------------------------------------------------
+template <int DIM, int S, int BX>
+__global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops,
+                                               const int4* __restrict__ tiles,
+                                               const typename Codec<S>::T* __restrict__ fsrc_all,
+                                               typename Codec<S>::T* __restrict__ fdst_all,
+                                               float* __restrict__ F_all, float* __restrict__ U_all,
+                                               float* __restrict__ rho_all,
+                                               float* __restrict__ Fout_all,
+                                               uint8_t* __restrict__ flags_all, int full) {
+    using L = Lattice<DIM>;
+    using C = Codec<S>;
+    constexpr int Q = L::Q;
+    constexpr int BY = kBlock / BX;
+    const int4 tile = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const DropDev& D = drops[tile.x];
+    const int nx = D.nx, ny = D.ny, nz = D.nz;
+    const int x = tile.y * BX + (int)(threadIdx.x % BX);
+    const int y = tile.z * BY + (int)(threadIdx.x / BX);
+    const int z = tile.w;
+    if (x >= nx || y >= ny) return;
+    const int ncell = D.ncell;
+    const int cell = (z * ny + y) * nx + x;
+    const typename C::T* __restrict__ fsrc = fsrc_all + D.f_off;
+    typename C::T* __restrict__ fdst = fdst_all + D.f_off;
+
+    // source coordinates for c = +1 (xm) and c = -1 (xp); -1 marks a wall
+    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1, zm = z - 1, zp = z + 1;
+    if (xm < 0) xm = D.bcx ? -1 : nx - 1;
+    if (xp >= nx) xp = D.bcx ? -1 : 0;
+    if (ym < 0) ym = D.bcy ? -1 : ny - 1;
+    if (yp >= ny) yp = D.bcy ? -1 : 0;
+    if (DIM == 3) {
+        if (zm < 0) zm = D.bcz ? -1 : nz - 1;
+        if (zp >= nz) zp = D.bcz ? -1 : 0;
+    }
+
+    float f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+        const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
+        const int sy = cy > 0 ? ym : (cy < 0 ? yp : y);
+        const int sz = DIM == 3 ? (cz > 0 ? zm : (cz < 0 ? zp : z)) : 0;
+        // a source beyond a wall means the population was reflected there:
+        // take the opposite population of this cell (half-way bounce-back)
+        const bool wall = (sx | sy | sz) < 0;
+        const int idx = wall ? opp(i) * ncell + cell : i * ncell + (sz * ny + sy) * nx + sx;
+        f[i] = C::load(fsrc, idx);
+    }
+
+    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        drho += f[i];
+        if (L::c[i][0] > 0) jx += f[i]; else if (L::c[i][0] < 0) jx -= f[i];
+        if (L::c[i][1] > 0) jy += f[i]; else if (L::c[i][1] < 0) jy -= f[i];
+        if (DIM == 3) { if (L::c[i][2] > 0) jz += f[i]; else if (L::c[i][2] < 0) jz -= f[i]; }
+    }
+
+    float* __restrict__ F = F_all + (long long)DIM * D.c_off;
+    float* __restrict__ U = U_all + (long long)DIM * D.c_off;
+    bool forced;
+    float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+    uint8_t* flag = nullptr;
+    if (D.force_mode == 1) {
+        forced = true;
+    } else {
+        flag = flags_all + D.flag_off + (z * ny + y) * D.nstrip + (x >> 6);
+        // every lane of a wavefront lies in the same strip
+        forced = __builtin_amdgcn_readfirstlane((int)*flag) != 0;
+    }
+    if (forced) {
+        Fx = F[cell];
+        Fy = F[ncell + cell];
+        if (DIM == 3) Fz = F[2 * ncell + cell];
+    }
+    const float rho = 1.f + drho;
+    const float inv = 1.f / rho;
+    const float ux = (jx + 0.5f * Fx) * inv;
+    const float uy = (jy + 0.5f * Fy) * inv;
+    const float uz = DIM == 3 ? (jz + 0.5f * Fz) * inv : 0.f;
+    const float usq = ux * ux + uy * uy + uz * uz;
+    const float om = D.omega;
+    const float uF = ux * Fx + uy * Fy + uz * Fz;
+    const float g = D.guo;
+
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+        const float cu = cx * ux + cy * uy + (DIM == 3 ? cz * uz : 0.f);
+        // f_eq - w = w (rho - 1) + w rho (3 cu + 4.5 cu^2 - 1.5 u^2)
+        const float feq = L::w[i] * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * usq));
+        float fn = f[i] - om * (f[i] - feq);
+        if (forced) {
+            const float cF = cx * Fx + cy * Fy + (DIM == 3 ? cz * Fz : 0.f);
+            // S_i = (1 - 1/2tau) w_i [3 (c - U).F + 9 (c.U)(c.F)]
+            fn += g * L::w[i] * (3.f * (cF - uF) + 9.f * cu * cF);
+        }
+        C::store(fdst, i * ncell + cell, fn);
+    }
+
+    if (forced && D.force_mode == 0) {
+        // interface band: keep U for the interpolation, hand back a clean F
+        U[cell] = ux;
+        U[ncell + cell] = uy;
+        if (DIM == 3) U[2 * ncell + cell] = uz;
+        F[cell] = 0.f;
+        F[ncell + cell] = 0.f;
+        if (DIM == 3) F[2 * ncell + cell] = 0.f;
+        *flag = 0;
+    }
+    if (full) {
+        float* __restrict__ Fo = Fout_all + (long long)DIM * D.c_off;
+        rho_all[D.c_off + cell] = rho;
+        U[cell] = ux;
+        U[ncell + cell] = uy;
+        Fo[cell] = Fx;
+        Fo[ncell + cell] = Fy;
+        if (DIM == 3) {
+            U[2 * ncell + cell] = uz;
+            Fo[2 * ncell + cell] = Fz;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Peskin 4-point kernel
+// ---------------------------------------------------------------------------
+// For a node at coordinate q the four taps are the cells base..base+3 with
+// base = floor(q - 1/2) - 1, at distances 1 + r, r, 1 - r, 2 - r from the
+// node (r = q - 1/2 - floor(q - 1/2) in [0, 1)).  With s = sqrt(1 + 4r - 4r^2)
+// both branches of Psi reduce to
+//   Psi(1+r) = (3 - 2r - s)/8, Psi(r) = (3 - 2r + s)/8,
+//   Psi(1-r) = (1 + 2r + s)/8, Psi(2-r) = (1 + 2r - s)/8,
+// so one square root serves all four taps.
+__device__ __forceinline__ void peskin_taps(double q, int& base, float w[4]) {
+    const double u = q - 0.5;
+    const double fl = floor(u);
+    const float r = (float)(u - fl);
+    base = (int)fl - 1;
+    const float s = sqrtf(1.f + 4.f * r * (1.f - r));
+    const float a = 3.f - 2.f * r, b = 1.f + 2.f * r;
+    w[0] = (a - s) * 0.125f;
+    w[1] = (a + s) * 0.125f;
+    w[2] = (b + s) * 0.125f;
+    w[3] = (b - s) * 0.125f;
+}
+
+// Cell index of tap base + k along an axis of n cells: wrapped on a periodic
+// axis, -1 beyond a wall.
+__device__ __forceinline__ int tap_index(int base, int k, int n, int wall) {
+    int i = base + k;
+    if (wall) return (i >= 0 && i < n) ? i : -1;
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+struct NodeArrays {
+    const double* pos;   // [3][stride]
+    double* pos_w;       // same array, written by the advection
+    float* phi;          // [3][stride]
+    float* qdot;         // [3][stride]
+    float* dropped;      // [3][stride]
+    const int* node_drop;
+    const int* tri;      // [3][tstride] global node ids
+    const int* inc;      // incidence entries (triangle << 2 | slot)
+    const int* inc_beg;
+    const int* inc_end;
+    int stride, tstride, ntot;
+};
+
+__device__ __forceinline__ double ipow(double s, int n) {
+    double p = 1.0;
+    for (int k = 0; k < n; ++k) p *= s;
+    return p;
+}
+
+// Pi(h) of eq. (disjoin-p)
+__device__ __forceinline__ double wetting_pi(const DropDev& D, double h) {
+    const double s = D.xi / h;
+    return D.A * (ipow(s, D.n_exp) - ipow(s, D.m_exp));
+}
+
+// Geometry of node j of a 2D closed CCW polygon: surface-tension force
+// sigma (t_j - t_{j-1}), node normal (mean of the adjacent outward edge
+// normals), node length chi = l_{j-1} + l_j.
+__device__ __forceinline__ void node_geom_2d(const DropDev& D, const NodeArrays& A, int j,
+                                             double q[2], double fs[2], double n[2],
+                                             double& chi, double& le) {
+    const int N = D.n_nodes, loc = j - D.node_off;
+    const int jm = D.node_off + (loc == 0 ? N - 1 : loc - 1);
+    const int jp = D.node_off + (loc == N - 1 ? 0 : loc + 1);
+    const int st = A.stride;
+    q[0] = A.pos[j];
+    q[1] = A.pos[st + j];
+    const double ex = A.pos[jp] - q[0], ey = A.pos[st + jp] - q[1];
+    const double fx = q[0] - A.pos[jm], fy = q[1] - A.pos[st + jm];
+    le = sqrt(ex * ex + ey * ey);
+    const double lf = sqrt(fx * fx + fy * fy);
+    fs[0] = D.sigma * (ex / le - fx / lf);
+    fs[1] = D.sigma * (ey / le - fy / lf);
+    double nx = ey / le + fy / lf, ny = -ex / le - fx / lf;
+    const double nn = sqrt(nx * nx + ny * ny);
+    n[0] = nx / nn;
+    n[1] = ny / nn;
+    chi = le + lf;
+}
+
+// Geometry of vertex j of a closed 3D triangle mesh (CCW seen from
+// outside): surface-tension force -sigma d(area)/dq_j summed over the
+// incident triangles, vertex normal (mean of the incident unit normals),
+// chi = sum of the incident areas.
+__device__ __forceinline__ void node_geom_3d(const DropDev& D, const NodeArrays& A, int j,
+                                             double q[3], double fs[3], double n[3],
+                                             double& chi) {
+    const int st = A.stride, ts = A.tstride;
+    q[0] = A.pos[j];
+    q[1] = A.pos[st + j];
+    q[2] = A.pos[2 * st + j];
+    fs[0] = fs[1] = fs[2] = 0.0;
+    double ns[3] = {0.0, 0.0, 0.0};
+    chi = 0.0;
+    for (int k = A.inc_beg[j]; k < A.inc_end[j]; ++k) {
+        const int e = A.inc[k];
+        const int t = e >> 2, s = e & 3;
+        const int v0 = A.tri[t], v1 = A.tri[ts + t], v2 = A.tri[2 * ts + t];
+        double P[3][3];
+        const int vv[3] = {v0, v1, v2};
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            P[m][0] = A.pos[vv[m]];
+            P[m][1] = A.pos[st + vv[m]];
+            P[m][2] = A.pos[2 * st + vv[m]];
+        }
+        const double e1[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+        const double e2[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+        double nt[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                        e1[0] * e2[1] - e1[1] * e2[0]};
+        const double len = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+        nt[0] /= len;
+        nt[1] /= len;
+        nt[2] /= len;
+        const int sb = s == 2 ? 0 : s + 1, sc = s == 0 ? 2 : s - 1;
+        const double d[3] = {P[sc][0] - P[sb][0], P[sc][1] - P[sb][1], P[sc][2] - P[sb][2]};
+        // -sigma/2 n_t x (q_c - q_b)
+        fs[0] -= 0.5 * D.sigma * (nt[1] * d[2] - nt[2] * d[1]);
+        fs[1] -= 0.5 * D.sigma * (nt[2] * d[0] - nt[0] * d[2]);
+        fs[2] -= 0.5 * D.sigma * (nt[0] * d[1] - nt[1] * d[0]);
+        ns[0] += nt[0];
+        ns[1] += nt[1];
+        ns[2] += nt[2];
+        chi += 0.5 * len;
+    }
+    const double nn = sqrt(ns[0] * ns[0] + ns[1] * ns[1] + ns[2] * ns[2]);
+    n[0] = ns[0] / nn;
+    n[1] = ns[1] / nn;
+    n[2] = ns[2] / nn;
+}
+
+// ---------------------------------------------------------------------------
+// Nodal forces + spreading
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_force_spread(const DropDev* __restrict__ drops,
+                                                         NodeArrays A, float* __restrict__ F_all,
+                                                         uint8_t* __restrict__ flags_all,
+                                                         int want_dropped) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= A.ntot) return;
+    const DropDev& D = drops[A.node_drop[j]];
+    if (!D.active || D.force_mode != 0) return;
+    double q[3] = {0, 0, 0}, fs[3] = {0, 0, 0}, n[3] = {0, 0, 0}, chi;
+    double share;
+    if (DIM == 2) {
+        double le;
+        node_geom_2d(D, A, j, q, fs, n, chi, le);
+        share = 0.5 * chi;
+    } else {
+        node_geom_3d(D, A, j, q, fs, n, chi);
+        share = chi / 3.0;
+    }
+    if (D.wetting) {
+        const double P = wetting_pi(D, q[DIM - 1]);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) fs[a] -= share * P * n[a];
+    }
+    float ph[3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        ph[a] = (float)fs[a];
+        A.phi[a * A.stride + j] = ph[a];
+    }
+
+    const int nx = D.nx, ny = D.ny, ncell = D.ncell;
+    int bx, by, bz = 0;
+    float wx[4], wy[4], wz[4] = {1.f, 0.f, 0.f, 0.f};
+    peskin_taps(q[0], bx, wx);
+    peskin_taps(q[1], by, wy);
+    if (DIM == 3) peskin_taps(q[2], bz, wz);
+    float* __restrict__ F = F_all + (long long)DIM * D.c_off;
+    uint8_t* __restrict__ flags = flags_all + D.flag_off;
+    float lost[3] = {0.f, 0.f, 0.f};
+    constexpr int KZ = DIM == 3 ? 4 : 1;
+    for (int kz = 0; kz < KZ; ++kz) {
+        const int iz = DIM == 3 ? tap_index(bz, kz, D.nz, D.bcz) : 0;
+        for (int ky = 0; ky < 4; ++ky) {
+            const int iy = tap_index(by, ky, ny, D.bcy);
+            const float wyz = wy[ky] * wz[kz];
+#pragma unroll
+            for (int kx = 0; kx < 4; ++kx) {
+                const int ix = tap_index(bx, kx, nx, D.bcx);
+                const float w = wx[kx] * wyz;
+                if ((ix | iy | iz) < 0) {
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) lost[a] += ph[a] * w;
+                    continue;
+                }
+                const int cell = (iz * ny + iy) * nx + ix;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) unsafeAtomicAdd(F + a * ncell + cell, ph[a] * w);
+                flags[(iz * ny + iy) * D.nstrip + (ix >> 6)] = 1;
+            }
+        }
+    }
+    if (want_dropped) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) A.dropped[a * A.stride + j] = lost[a];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Interpolation + advection
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_interp_advect(const DropDev* __restrict__ drops,
+                                                          NodeArrays A,
+                                                          const float* __restrict__ U_all,
+                                                          int* __restrict__ status) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= A.ntot) return;
+    const int d = A.node_drop[j];
+    const DropDev& D = drops[d];
+    if (!D.active || D.force_mode != 0) return;
+    const int st = A.stride;
+    double q[3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) q[a] = A.pos[a * st + j];
+    const int nx = D.nx, ny = D.ny, ncell = D.ncell;
+    int bx, by, bz = 0;
+    float wx[4], wy[4], wz[4] = {1.f, 0.f, 0.f, 0.f};
+    peskin_taps(q[0], bx, wx);
+    peskin_taps(q[1], by, wy);
+    if (DIM == 3) peskin_taps(q[2], bz, wz);
+    const float* __restrict__ U = U_all + (long long)DIM * D.c_off;
+    float acc[3] = {0.f, 0.f, 0.f};
+    constexpr int KZ = DIM == 3 ? 4 : 1;
+    for (int kz = 0; kz < KZ; ++kz) {
+        const int iz = DIM == 3 ? tap_index(bz, kz, D.nz, D.bcz) : 0;
+        for (int ky = 0; ky < 4; ++ky) {
+            const int iy = tap_index(by, ky, ny, D.bcy);
+            const float wyz = wy[ky] * wz[kz];
+#pragma unroll
+            for (int kx = 0; kx < 4; ++kx) {
+                const int ix = tap_index(bx, kx, nx, D.bcx);
+                if ((ix | iy | iz) < 0) continue;  // no-slip wall: U = 0 there
+                const float w = wx[kx] * wyz;
+                const int cell = (iz * ny + iy) * nx + ix;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) acc[a] += U[a * ncell + cell] * w;
+            }
+        }
+    }
+    float sp = 0.f;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        A.qdot[a * st + j] = acc[a];
+        A.pos_w[a * st + j] = q[a] + (double)acc[a];
+        sp += acc[a] * acc[a];
+    }
+    int bad = 0;
+    if (!(sp <= 0.09f)) bad |= 2;  // |qdot| > 0.3 or not finite
+    if (D.wetting && !(q[DIM - 1] + (double)acc[DIM - 1] > 0.0)) bad |= 1;
+    if (bad) atomicOr(status + d, bad);
+}
+
+// ---------------------------------------------------------------------------
+// Population I/O and initialisation
+// ---------------------------------------------------------------------------
+template <int S>
+__global__ void k_pop_write(typename Codec<S>::T* __restrict__ f, long long n,
+                            const double* __restrict__ src) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) f[i] = Codec<S>::from_double(src[i]);
+}
+
+template <int S>
+__global__ void k_pop_read(const typename Codec<S>::T* __restrict__ f, long long n,
+                           double* __restrict__ dst) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) dst[i] = Codec<S>::to_double(f[i]);
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, long long n, float v) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block-wide reduction of 256 threads (4 wavefronts); every thread gets the
+// result.  kind: 0 sum, 1 min, 2 max.
+__device__ double block_reduce(double v, int kind, double* sh) {
+    v = kind == 0 ? wave_sum(v) : (kind == 1 ? wave_min(v) : wave_max(v));
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double r = sh[0];
+    for (int k = 1; k < kBlock / 64; ++k)
+        r = kind == 0 ? r + sh[k] : (kind == 1 ? fmin(r, sh[k]) : fmax(r, sh[k]));
+    return r;
+}
+
+// Per-tile partial sums over cells: [0] sum of f - w, [1..3] rho U,
+// [4..6] F of the last step.
+template <int DIM, int S, int BX>
+__global__ __launch_bounds__(kBlock) void k_cell_sums(const DropDev* __restrict__ drops,
+                                                      const int4* __restrict__ tiles,
+                                                      const typename Codec<S>::T* __restrict__ f_all,
+                                                      const float* __restrict__ U_all,
+                                                      const float* __restrict__ rho_all,
+                                                      const float* __restrict__ Fout_all,
+                                                      double* __restrict__ partials) {
+    __shared__ double sh[kBlock / 64];
+    using L = Lattice<DIM>;
+    constexpr int BY = kBlock / BX;
+    const int t = blockIdx.x;
+    const int4 tile = tiles[t];
+    const DropDev& D = drops[tile.x];
+    const int x = tile.y * BX + (int)(threadIdx.x % BX);
+    const int y = tile.z * BY + (int)(threadIdx.x / BX);
+    const int z = tile.w;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (x < D.nx && y < D.ny) {
+        const int ncell = D.ncell;
+        const int cell = (z * D.ny + y) * D.nx + x;
+        const typename Codec<S>::T* f = f_all + D.f_off;
+        double s = 0.0;
+        for (int i = 0; i < L::Q; ++i) s += (double)Codec<S>::load(f, i * ncell + cell);
+        v[0] = s;
+        const double rho = rho_all[D.c_off + cell];
+        const float* U = U_all + (long long)DIM * D.c_off;
+        const float* Fo = Fout_all + (long long)DIM * D.c_off;
+        for (int a = 0; a < DIM; ++a) {
+            v[1 + a] = rho * (double)U[a * ncell + cell];
+            v[4 + a] = (double)Fo[a * ncell + cell];
+        }
+    }
+    for (int k = 0; k < 7; ++k) {
+        const double r = block_reduce(v[k], 0, sh);
+        if (threadIdx.x == 0) partials[(long long)t * 8 + k] = r;
+    }
+}
+
+// One block per droplet: cell partials + interface reductions.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_diag(const DropDev* __restrict__ drops, NodeArrays A,
+                                                 const double* __restrict__ partials,
+                                                 DiagDev* __restrict__ out) {
+    __shared__ double sh[kBlock / 64];
+    const int d = blockIdx.x;
+    const DropDev& D = drops[d];
+    DiagDev r;
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int t = D.tile_off + threadIdx.x; t < D.tile_off + D.n_tiles; t += kBlock)
+        for (int k = 0; k < 7; ++k) acc[k] += partials[(long long)t * 8 + k];
+    for (int k = 0; k < 7; ++k) acc[k] = block_reduce(acc[k], 0, sh);
+    r.mass_dev = acc[0];
+    for (int a = 0; a < 3; ++a) {
+        r.mom[a] = acc[1 + a];
+        r.sum_F[a] = acc[4 + a];
+    }
+
+    const int st = A.stride, N = D.n_nodes, j0 = D.node_off;
+    double sphi[3] = {0, 0, 0}, sdrop[3] = {0, 0, 0};
+    double vol = 0, area = 0, hmin = 1e300, hmax = -1e300, un = 0, us = 0;
+    double emin = 1e300, emax = 0, lo = 1e300, hi = -1e300, cx = 0, cy = 0, cn = 0;
+    const double zc = D.zcut;
+    for (int l = threadIdx.x; l < N; l += kBlock) {
+        const int j = j0 + l;
+        double q[3], fs[3], n[3], chi;
+        if (DIM == 2) {
+            double le;
+            node_geom_2d(D, A, j, q, fs, n, chi, le);
+        } else {
+            node_geom_3d(D, A, j, q, fs, n, chi);
+        }
+        double u2 = 0, udn = 0;
+        for (int a = 0; a < DIM; ++a) {
+            sphi[a] += A.phi[a * st + j];
+            sdrop[a] += A.dropped[a * st + j];
+            const double v = A.qdot[a * st + j];
+            u2 += v * v;
+            udn += v * n[a];
+        }
+        un = fmax(un, fabs(udn));
+        us = fmax(us, sqrt(u2));
+        hmin = fmin(hmin, q[DIM - 1]);
+        hmax = fmax(hmax, q[DIM - 1]);
+        if (DIM == 2) {
+            const int jp = j0 + (l == N - 1 ? 0 : l + 1);
+            const double x0 = q[0], y0 = q[1], x1 = A.pos[jp], y1 = A.pos[st + jp];
+            vol += 0.5 * (x0 * y1 - x1 * y0);
+            const double e = sqrt((x1 - x0) * (x1 - x0) + (y1 - y0) * (y1 - y0));
+            area += e;
+            emin = fmin(emin, e);
+            emax = fmax(emax, e);
+            const double a0 = y0 - zc, a1 = y1 - zc;
+            if (a0 * a1 < 0.0 || (a0 == 0.0 && a1 != 0.0)) {
+                const double xs = x0 + a0 / (a0 - a1) * (x1 - x0);
+                lo = fmin(lo, xs);
+                hi = fmax(hi, xs);
+            }
+        }
+    }
+    if (DIM == 3) {
+        const int ts = A.tstride;
+        for (int t = D.tri_off + threadIdx.x; t < D.tri_off + D.n_tris; t += kBlock) {
+            const int v[3] = {A.tri[t], A.tri[ts + t], A.tri[2 * ts + t]};
+            double P[3][3];
+            for (int m = 0; m < 3; ++m)
+                for (int a = 0; a < 3; ++a) P[m][a] = A.pos[a * st + v[m]];
+            const double cr[3] = {P[1][1] * P[2][2] - P[1][2] * P[2][1],
+                                  P[1][2] * P[2][0] - P[1][0] * P[2][2],
+                                  P[1][0] * P[2][1] - P[1][1] * P[2][0]};
+            vol += (P[0][0] * cr[0] + P[0][1] * cr[1] + P[0][2] * cr[2]) / 6.0;
+            const double e1[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+            const double e2[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+            const double nt[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                                  e1[0] * e2[1] - e1[1] * e2[0]};
+            area += 0.5 * sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+            for (int m = 0; m < 3; ++m) {
+                const int m1 = m == 2 ? 0 : m + 1;
+                const double dx = P[m1][0] - P[m][0], dy = P[m1][1] - P[m][1],
+                             dz = P[m1][2] - P[m][2];
+                const double e = sqrt(dx * dx + dy * dy + dz * dz);
+                emin = fmin(emin, e);
+                emax = fmax(emax, e);
+                if (v[m] < v[m1]) {  // each edge once
+                    const double a0 = P[m][2] - zc, a1 = P[m1][2] - zc;
+                    if (a0 * a1 < 0.0) {
+                        const double s = a0 / (a0 - a1);
+                        cx += P[m][0] + s * dx;
+                        cy += P[m][1] + s * dy;
+                        cn += 1.0;
+                    }
+                }
+            }
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        r.sum_phi[a] = block_reduce(sphi[a], 0, sh);
+        r.dropped[a] = block_reduce(sdrop[a], 0, sh);
+    }
+    r.volume = block_reduce(vol, 0, sh);
+    r.area = block_reduce(area, 0, sh);
+    r.min_h = block_reduce(hmin, 1, sh);
+    r.max_h = block_reduce(hmax, 2, sh);
+    r.max_un = block_reduce(un, 2, sh);
+    r.max_u = block_reduce(us, 2, sh);
+    r.edge_min = block_reduce(emin, 1, sh);
+    r.edge_max = block_reduce(emax, 2, sh);
+    r.cross_lo = block_reduce(lo, 1, sh);
+    r.cross_hi = block_reduce(hi, 2, sh);
+    r.cross_r = 0.0;
+    r.cross_n = 0.0;
+    if (DIM == 3) {
+        const double n = block_reduce(cn, 0, sh);
+        const double mx = block_reduce(cx, 0, sh) / n, my = block_reduce(cy, 0, sh) / n;
+        double dsum = 0.0;
+        const int ts = A.tstride;
+        for (int t = D.tri_off + threadIdx.x; t < D.tri_off + D.n_tris; t += kBlock) {
+            const int v[3] = {A.tri[t], A.tri[ts + t], A.tri[2 * ts + t]};
+            for (int m = 0; m < 3; ++m) {
+                const int m1 = m == 2 ? 0 : m + 1;
+                if (v[m] >= v[m1]) continue;
+                const double z0 = A.pos[2 * st + v[m]] - zc, z1 = A.pos[2 * st + v[m1]] - zc;
+                if (z0 * z1 < 0.0) {
+                    const double s = z0 / (z0 - z1);
+                    const double px = A.pos[v[m]] + s * (A.pos[v[m1]] - A.pos[v[m]]);
+                    const double py = A.pos[st + v[m]] + s * (A.pos[st + v[m1]] - A.pos[st + v[m]]);
+                    dsum += sqrt((px - mx) * (px - mx) + (py - my) * (py - my));
+                }
+            }
+        }
+        r.cross_r = block_reduce(dsum, 0, sh) / n;
+        r.cross_n = n;
+    }
+    if (threadIdx.x == 0) out[d] = r;
+}
+
+}  // namespace iblb
