@@ -63,8 +63,10 @@ typedef enum {
     IBLB_EINVAL = -1,     /* bad argument: see iblb_last_error()            */
     IBLB_ENOMEM = -2,     /* workspace smaller than iblb_workspace_bytes()  */
     IBLB_EDEVICE = -3,    /* a HIP runtime call failed                      */
-    IBLB_EUNSTABLE = -4   /* a node reached h <= 0 with wetting on, or a
-                             node speed became non-finite or above 0.3      */
+    IBLB_EUNSTABLE = -4   /* a node reached h <= 0 with wetting on, a node
+                             speed became non-finite or above 0.3, or a node
+                             position became non-finite (such nodes are
+                             then left out of spreading and interpolation) */
 } iblb_status;
 
 typedef enum { IBLB_PERIODIC = 0, IBLB_WALL = 1 } iblb_bc;

@@ -305,10 +305,10 @@ void launch_nodes(const iblb_ctx* c, hipStream_t s, int phase, int full) {
     if (phase == 0) {
         if (c->dim == 2)
             hipLaunchKernelGGL(k_force_spread<2>, grid, block, 0, s, D, A, c->at<float>(c->L.F),
-                               c->at<uint8_t>(c->L.flags), full);
+                               c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status), full);
         else
             hipLaunchKernelGGL(k_force_spread<3>, grid, block, 0, s, D, A, c->at<float>(c->L.F),
-                               c->at<uint8_t>(c->L.flags), full);
+                               c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status), full);
     } else {
         if (c->dim == 2)
             hipLaunchKernelGGL(k_interp_advect<2>, grid, block, 0, s, D, A, c->at<float>(c->L.U),
@@ -758,9 +758,11 @@ int iblb_step(iblb_ctx* c, int n_steps) {
     for (int d = 0; d < c->n; ++d)
         if (c->status_h[d] && c->drops[d].active) {
             char buf[160];
-            snprintf(buf, sizeof buf, "droplet %d unstable (code %d: %s) by step %lld", d,
-                     c->status_h[d],
-                     (c->status_h[d] & 1) ? "node at or below the substrate" : "node speed",
+            const int code = c->status_h[d];
+            snprintf(buf, sizeof buf, "droplet %d unstable (code %d:%s%s%s) by step %lld", d, code,
+                     (code & 1) ? " node at or below the substrate" : "",
+                     (code & 2) ? " node speed above 0.3 or not finite" : "",
+                     (code & 4) ? " node position not finite or far outside the box" : "",
                      (long long)c->step);
             return fail(c, IBLB_EUNSTABLE, buf);
         }

@@ -223,8 +223,16 @@ __device__ __forceinline__ void peskin_taps(double q, int& base, float w[4]) {
     w[3] = (b - s) * 0.125f;
 }
 
+// Nodes whose coordinates are not finite or lie absurdly far from any box
+// (|q| > 2^24) are never turned into tap indices: converting such a value to
+// int is undefined and could yield an index far outside the lattice.  The
+// kernels skip the node and flag its droplet unstable instead.
+constexpr double kFarCoord = 16777216.0;
+__device__ __forceinline__ bool coord_ok(double v) { return fabs(v) <= kFarCoord; }  // NaN: false
+
 // Cell index of tap base + k along an axis of n cells: wrapped on a periodic
-// axis, -1 beyond a wall.
+// axis, -1 beyond a wall.  base comes from a coordinate that passed coord_ok,
+// so base + k cannot overflow.
 __device__ __forceinline__ int tap_index(int base, int k, int n, int wall) {
     int i = base + k;
     if (wall) return (i >= 0 && i < n) ? i : -1;
@@ -341,10 +349,12 @@ template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_force_spread(const DropDev* __restrict__ drops,
                                                          NodeArrays A, float* __restrict__ F_all,
                                                          uint8_t* __restrict__ flags_all,
+                                                         int* __restrict__ status,
                                                          int want_dropped) {
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= A.ntot) return;
-    const DropDev& D = drops[A.node_drop[j]];
+    const int d = A.node_drop[j];
+    const DropDev& D = drops[d];
     if (!D.active || D.force_mode != 0) return;
     double q[3] = {0, 0, 0}, fs[3] = {0, 0, 0}, n[3] = {0, 0, 0}, chi;
     double share;
@@ -366,6 +376,13 @@ __global__ __launch_bounds__(kBlock) void k_force_spread(const DropDev* __restri
     for (int a = 0; a < DIM; ++a) {
         ph[a] = (float)fs[a];
         A.phi[a * A.stride + j] = ph[a];
+    }
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) ok &= coord_ok(q[a]);
+    if (!ok) {
+        atomicOr(status + d, 4);
+        return;
     }
 
     const int nx = D.nx, ny = D.ny, ncell = D.ncell;
@@ -420,8 +437,16 @@ __global__ __launch_bounds__(kBlock) void k_interp_advect(const DropDev* __restr
     if (!D.active || D.force_mode != 0) return;
     const int st = A.stride;
     double q[3];
+    bool ok = true;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) q[a] = A.pos[a * st + j];
+    for (int a = 0; a < DIM; ++a) {
+        q[a] = A.pos[a * st + j];
+        ok &= coord_ok(q[a]);
+    }
+    if (!ok) {
+        atomicOr(status + d, 4);
+        return;
+    }
     const int nx = D.nx, ny = D.ny, ncell = D.ncell;
     int bx, by, bz = 0;
     float wx[4], wy[4], wz[4] = {1.f, 0.f, 0.f, 0.f};

@@ -1,0 +1,163 @@
+// CPU harness driver: runs one case through the C ABI of the library
+// sources compiled for the host (see include/hip/hip_runtime.h here) under
+// AddressSanitizer + UndefinedBehaviorSanitizer.  TEST INFRASTRUCTURE.
+//
+// usage: driver <case_dir>
+//   case_dir/config.txt   "key value" lines: n, storage, steps (comma list of
+//                         step counts, run one after another), graph_steps,
+//                         shape, and per droplet d: nodes_d, tris_d,
+//                         f0dev_d (0/1), force_d (0/1)
+//   case_dir/params.bin   n iblb_params records
+//   case_dir/pos_d.bin    [dim][N] float64;  tris_d.bin [T][3] int32
+//   case_dir/f0dev_d.bin  [Q][cells] float64; force_d.bin [dim][cells] float32
+// writes case_dir/out_d_{rho,U,F,fdev,q,qdot,phi,diag}.bin and status.txt
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "iblb.h"
+
+static std::string dir;
+
+template <typename T>
+static std::vector<T> load(const std::string& name, size_t count) {
+    std::vector<T> v(count);
+    FILE* f = fopen((dir + "/" + name).c_str(), "rb");
+    if (!f) { fprintf(stderr, "missing %s\n", name.c_str()); exit(3); }
+    size_t got = fread(v.data(), sizeof(T), count, f);
+    fclose(f);
+    if (got != count) { fprintf(stderr, "short %s\n", name.c_str()); exit(3); }
+    return v;
+}
+
+template <typename T>
+static void save(const std::string& name, const T* p, size_t count) {
+    FILE* f = fopen((dir + "/" + name).c_str(), "wb");
+    fwrite(p, sizeof(T), count, f);
+    fclose(f);
+}
+
+// exact-size heap buffers so the sanitizer sees any access past their end
+template <typename T>
+static T* buf(size_t count) {
+    void* p = nullptr;
+    if (posix_memalign(&p, 256, count * sizeof(T) ? count * sizeof(T) : 1)) exit(4);
+    memset(p, 0, count * sizeof(T));
+    return static_cast<T*>(p);
+}
+
+int main(int argc, char** argv) {
+    if (argc < 2) return 2;
+    dir = argv[1];
+    std::map<std::string, std::string> cfg;
+    {
+        std::ifstream in(dir + "/config.txt");
+        std::string k, v;
+        while (in >> k >> v) cfg[k] = v;
+    }
+    auto geti = [&](const std::string& k, int def) { return cfg.count(k) ? atoi(cfg[k].c_str()) : def; };
+    const int n = geti("n", 1), storage = geti("storage", 0);
+    std::vector<iblb_params> P = load<iblb_params>("params.bin", n);
+    const int dim = P[0].dim, Q = dim == 2 ? 9 : 19;
+    std::vector<int> nn(n), nt(n);
+    for (int d = 0; d < n; ++d) {
+        nn[d] = geti("nodes_" + std::to_string(d), 0);
+        nt[d] = geti("tris_" + std::to_string(d), 0);
+    }
+    size_t ws = iblb_workspace_bytes(n, P.data(), nn.data(), nt.data(), storage);
+    if (!ws) { fprintf(stderr, "workspace: %s\n", iblb_last_error(nullptr)); return 5; }
+    char* w = buf<char>(ws);
+    iblb_ctx* ctx = nullptr;
+    int rc = iblb_create(n, P.data(), nn.data(), nt.data(), storage, w, ws, nullptr, &ctx);
+    if (rc) { fprintf(stderr, "create: %s\n", iblb_last_error(nullptr)); return 6; }
+    for (int d = 0; d < n; ++d) {
+        const std::string s = std::to_string(d);
+        const long cells = (long)P[d].nx * P[d].ny * (dim == 3 ? P[d].nz : 1);
+        if (nn[d] > 0) {
+            auto pos = load<double>("pos_" + s + ".bin", (size_t)dim * nn[d]);
+            std::vector<int32_t> tri;
+            if (dim == 3) tri = load<int32_t>("tris_" + s + ".bin", (size_t)3 * nt[d]);
+            double* pb = buf<double>(pos.size());
+            memcpy(pb, pos.data(), pos.size() * 8);
+            int32_t* tb = nullptr;
+            if (dim == 3) {
+                tb = buf<int32_t>(tri.size());
+                memcpy(tb, tri.data(), tri.size() * 4);
+            }
+            rc = iblb_set_interface(ctx, d, pb, tb);
+            free(pb);
+            free(tb);
+            if (rc) { fprintf(stderr, "set_interface: %s\n", iblb_last_error(ctx)); return 7; }
+        }
+        if (geti("f0dev_" + s, 0)) {
+            auto f = load<double>("f0dev_" + s + ".bin", (size_t)Q * cells);
+            double* fb = buf<double>(f.size());
+            memcpy(fb, f.data(), f.size() * 8);
+            rc = iblb_write_populations(ctx, d, fb);
+            free(fb);
+            if (rc) return 8;
+        }
+        if (geti("force_" + s, 0)) {
+            auto F = load<float>("force_" + s + ".bin", (size_t)dim * cells);
+            float* fb = buf<float>(F.size());
+            memcpy(fb, F.data(), F.size() * 4);
+            rc = iblb_set_force_field(ctx, d, fb);
+            free(fb);
+            if (rc) return 9;
+        }
+    }
+    if (cfg.count("graph_steps")) iblb_set_graph_steps(ctx, geti("graph_steps", 64));
+    if (cfg.count("shape")) iblb_set_tile_shape(ctx, geti("shape", 0), nullptr);
+    if (cfg.count("timing")) iblb_set_timing(ctx, geti("timing", 0));
+    for (int d = 0; d < n; ++d)
+        if (geti("inactive_" + std::to_string(d), 0)) iblb_set_active(ctx, d, 0);
+    int step_rc = 0;
+    {
+        std::stringstream ss(cfg.count("steps") ? cfg["steps"] : "1");
+        std::string tok;
+        while (std::getline(ss, tok, ',')) {
+            step_rc = iblb_step(ctx, atoi(tok.c_str()));
+            if (step_rc) break;
+        }
+    }
+    FILE* st = fopen((dir + "/status.txt").c_str(), "w");
+    fprintf(st, "%d\n%s\n", step_rc, iblb_last_error(ctx));
+    fclose(st);
+    std::vector<iblb_diag> dg(n);
+    rc = iblb_diagnostics(ctx, -1, dg.data());
+    if (rc) { fprintf(stderr, "diag: %s\n", iblb_last_error(ctx)); return 10; }
+    for (int d = 0; d < n; ++d) {
+        const std::string s = std::to_string(d);
+        const long cells = (long)P[d].nx * P[d].ny * (dim == 3 ? P[d].nz : 1);
+        float* rho = buf<float>(cells);
+        float* U = buf<float>((size_t)dim * cells);
+        float* F = buf<float>((size_t)dim * cells);
+        double* fd = buf<double>((size_t)Q * cells);
+        if (iblb_read_fields(ctx, d, rho, U, F) || iblb_read_populations(ctx, d, fd)) return 11;
+        save("out_" + s + "_rho.bin", rho, cells);
+        save("out_" + s + "_U.bin", U, (size_t)dim * cells);
+        save("out_" + s + "_F.bin", F, (size_t)dim * cells);
+        save("out_" + s + "_fdev.bin", fd, (size_t)Q * cells);
+        free(rho); free(U); free(F); free(fd);
+        if (nn[d] > 0) {
+            double* q = buf<double>((size_t)dim * nn[d]);
+            float* v = buf<float>((size_t)dim * nn[d]);
+            float* ph = buf<float>((size_t)dim * nn[d]);
+            if (iblb_read_nodes(ctx, d, q, v, ph)) return 12;
+            save("out_" + s + "_q.bin", q, (size_t)dim * nn[d]);
+            save("out_" + s + "_qdot.bin", v, (size_t)dim * nn[d]);
+            save("out_" + s + "_phi.bin", ph, (size_t)dim * nn[d]);
+            free(q); free(v); free(ph);
+        }
+        save("out_" + s + "_diag.bin", &dg[d], 1);
+    }
+    iblb_destroy(ctx);
+    free(w);
+    return 0;
+}

@@ -1,0 +1,411 @@
+// Host-only stand-in for <hip/hip_runtime.h>, used by the CPU bounds and
+// parity harness under tests/cpu_emu.  TEST INFRASTRUCTURE: the product
+// library is always built by hipcc for gfx950; this header lets the very
+// same kernel and runtime sources be compiled for the host under
+// AddressSanitizer + UndefinedBehaviorSanitizer, so that every memory
+// access of every kernel is checked on the CPU before it runs on a GPU.
+//
+// Execution model: a launch runs its blocks one after another; the threads
+// of a block are fibers (ucontext) that run until they reach a point where
+// lanes exchange data -- __syncthreads(), __shfl_xor() or
+// __builtin_amdgcn_readfirstlane() -- which act as barriers of the block or
+// of the 64-lane wavefront, exactly as lock-step execution would order
+// them.  Lanes that have returned no longer take part, like inactive lanes.
+// Atomics are plain read-modify-writes (fibers switch only at barriers).
+// Stream operations execute immediately; a captured graph records the
+// launches (arguments evaluated at capture time) and replays them.
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <ucontext.h>
+
+#include <functional>
+#include <vector>
+
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__ static
+
+struct dim3 {
+    unsigned x, y, z;
+    constexpr dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+struct int4 {
+    int x, y, z, w;
+};
+inline int4 make_int4(int a, int b, int c, int d) { return int4{a, b, c, d}; }
+
+typedef enum {
+    hipSuccess = 0,
+    hipErrorInvalidValue = 1,
+    hipErrorInvalidConfiguration = 9,
+    hipErrorStreamCaptureUnsupported = 900,
+} hipError_t;
+
+inline const char* hipGetErrorString(hipError_t e) {
+    switch (e) {
+        case hipSuccess: return "hipSuccess";
+        case hipErrorInvalidValue: return "hipErrorInvalidValue";
+        case hipErrorInvalidConfiguration: return "hipErrorInvalidConfiguration";
+        default: return "hipError(emulated)";
+    }
+}
+
+typedef enum { hipMemcpyHostToHost = 0, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2,
+               hipMemcpyDeviceToDevice = 3, hipMemcpyDefault = 4 } hipMemcpyKind;
+typedef enum { hipStreamCaptureModeGlobal = 0, hipStreamCaptureModeThreadLocal = 1,
+               hipStreamCaptureModeRelaxed = 2 } hipStreamCaptureMode;
+#define hipStreamNonBlocking 1
+
+namespace hipemu {
+
+struct Stream { int id; };
+struct Graph { std::vector<std::function<void()>> ops; };
+struct Event { int id; };
+
+enum State { READY, AT_WAVE_FIRST, AT_WAVE_XOR, AT_BLOCK, DONE };
+
+struct Fiber {
+    ucontext_t ctx;
+    char* stack = nullptr;
+    int tid = 0;
+    State st = READY;
+    uint64_t in = 0, out = 0;
+    int mask = 0;
+    void* asan_fake = nullptr;
+};
+
+struct Runtime {
+    dim3 grid, block, bidx;
+    std::vector<Fiber> fibers;
+    ucontext_t sched;
+    Fiber* cur = nullptr;
+    const std::function<void()>* body = nullptr;
+    Stream* capturing = nullptr;
+    Graph* graph = nullptr;
+    hipError_t last = hipSuccess;
+    const void* sched_bottom = nullptr;
+    size_t sched_size = 0;
+    long long launches = 0;
+};
+
+Runtime& rt();
+
+dim3 thread_idx();
+inline dim3 block_idx() { return rt().bidx; }
+inline dim3 block_dim() { return rt().block; }
+inline dim3 grid_dim() { return rt().grid; }
+
+uint64_t wave_op(State kind, uint64_t v, int mask);
+void block_barrier();
+void run_grid(dim3 g, dim3 b, const std::function<void()>& fn);
+
+template <typename T>
+inline uint64_t pack(T v) {
+    uint64_t u = 0;
+    memcpy(&u, &v, sizeof(T));
+    return u;
+}
+template <typename T>
+inline T unpack(uint64_t u) {
+    T v;
+    memcpy(&v, &u, sizeof(T));
+    return v;
+}
+
+template <typename K, typename... A>
+inline void launch(void* stream, dim3 g, dim3 b, K k, A... a) {
+    Runtime& r = rt();
+    if (g.x == 0 || g.y == 0 || g.z == 0 || b.x * b.y * b.z == 0 || b.x * b.y * b.z > 1024) {
+        r.last = hipErrorInvalidConfiguration;
+        return;
+    }
+    std::function<void()> fn = [=]() { k(a...); };
+    if (r.capturing && static_cast<Stream*>(stream) == r.capturing) {
+        r.graph->ops.push_back([g, b, fn]() { run_grid(g, b, fn); });
+        return;
+    }
+    run_grid(g, b, fn);
+}
+
+}  // namespace hipemu
+
+#define threadIdx (::hipemu::thread_idx())
+#define blockIdx (::hipemu::block_idx())
+#define blockDim (::hipemu::block_dim())
+#define gridDim (::hipemu::grid_dim())
+
+#define hipLaunchKernelGGL(kern, grid, block, shmem, stream, ...) \
+    ::hipemu::launch((void*)(stream), dim3(grid), dim3(block), kern, __VA_ARGS__)
+
+inline void __syncthreads() { ::hipemu::block_barrier(); }
+
+inline int __builtin_amdgcn_readfirstlane(int v) {
+    return ::hipemu::unpack<int>(::hipemu::wave_op(::hipemu::AT_WAVE_FIRST, ::hipemu::pack(v), 0));
+}
+
+template <typename T>
+inline T __shfl_xor(T v, int mask, int width = 64) {
+    (void)width;
+    return ::hipemu::unpack<T>(::hipemu::wave_op(::hipemu::AT_WAVE_XOR, ::hipemu::pack(v), mask));
+}
+
+inline float unsafeAtomicAdd(float* p, float v) {
+    float old = *p;
+    *p = old + v;
+    return old;
+}
+inline int atomicOr(int* p, int v) {
+    int old = *p;
+    *p = old | v;
+    return old;
+}
+
+typedef hipemu::Stream* hipStream_t;
+typedef hipemu::Graph* hipGraph_t;
+typedef hipemu::Graph* hipGraphExec_t;
+typedef hipemu::Event* hipEvent_t;
+typedef void* hipGraphNode_t;
+
+inline hipError_t hipGetLastError() {
+    hipError_t e = hipemu::rt().last;
+    hipemu::rt().last = hipSuccess;
+    return e;
+}
+inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) {
+    if (n) memcpy(d, s, n);
+    return hipSuccess;
+}
+inline hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t) {
+    if (n) memset(d, v, n);
+    return hipSuccess;
+}
+inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+inline hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) {
+    *s = new hipemu::Stream{1};
+    return hipSuccess;
+}
+inline hipError_t hipStreamDestroy(hipStream_t s) {
+    delete s;
+    return hipSuccess;
+}
+inline hipError_t hipEventCreate(hipEvent_t* e) {
+    *e = new hipemu::Event{0};
+    return hipSuccess;
+}
+inline hipError_t hipEventDestroy(hipEvent_t e) {
+    delete e;
+    return hipSuccess;
+}
+inline hipError_t hipEventRecord(hipEvent_t, hipStream_t = nullptr) { return hipSuccess; }
+inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) {
+    *ms = 1e-3f;
+    return hipSuccess;
+}
+inline hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode) {
+    hipemu::Runtime& r = hipemu::rt();
+    if (r.capturing || !s) return hipErrorStreamCaptureUnsupported;
+    r.capturing = s;
+    r.graph = new hipemu::Graph();
+    return hipSuccess;
+}
+inline hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t* g) {
+    hipemu::Runtime& r = hipemu::rt();
+    if (r.capturing != s) return hipErrorInvalidValue;
+    *g = r.graph;
+    r.graph = nullptr;
+    r.capturing = nullptr;
+    return hipSuccess;
+}
+inline hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode_t*, char*, size_t) {
+    *e = new hipemu::Graph(*g);
+    return hipSuccess;
+}
+inline hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t) {
+    for (auto& op : e->ops) op();
+    return hipSuccess;
+}
+inline hipError_t hipGraphExecDestroy(hipGraphExec_t e) {
+    delete e;
+    return hipSuccess;
+}
+inline hipError_t hipGraphDestroy(hipGraph_t g) {
+    delete g;
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// implementation (header-only; one definition through inline functions)
+// ---------------------------------------------------------------------------
+#if defined(__has_feature)
+#if __has_feature(address_sanitizer)
+#define HIPEMU_ASAN 1
+#endif
+#endif
+#ifdef HIPEMU_ASAN
+extern "C" void __sanitizer_start_switch_fiber(void** fake_stack_save, const void* bottom, size_t size);
+extern "C" void __sanitizer_finish_switch_fiber(void* fake_stack_save, const void** bottom_old,
+                                                size_t* size_old);
+#endif
+
+namespace hipemu {
+
+constexpr size_t kStack = 512 * 1024;
+
+inline Runtime& rt() {
+    static Runtime r;
+    return r;
+}
+
+inline dim3 thread_idx() {
+    Runtime& r = rt();
+    const int t = r.cur->tid;
+    return dim3(t % r.block.x, (t / r.block.x) % r.block.y, t / (r.block.x * r.block.y));
+}
+
+// switch from the running fiber back to the scheduler
+inline void yield_to_sched(bool finished) {
+    Runtime& r = rt();
+    Fiber* f = r.cur;
+#ifdef HIPEMU_ASAN
+    __sanitizer_start_switch_fiber(finished ? nullptr : &f->asan_fake, r.sched_bottom, r.sched_size);
+#endif
+    swapcontext(&f->ctx, &r.sched);
+#ifdef HIPEMU_ASAN
+    __sanitizer_finish_switch_fiber(f->asan_fake, nullptr, nullptr);
+#endif
+    (void)finished;
+}
+
+inline void fiber_entry() {
+    Runtime& r = rt();
+#ifdef HIPEMU_ASAN
+    __sanitizer_finish_switch_fiber(nullptr, &r.sched_bottom, &r.sched_size);
+#endif
+    (*r.body)();
+    r.cur->st = DONE;
+    yield_to_sched(true);
+    abort();  // a finished fiber is never resumed
+}
+
+inline uint64_t wave_op(State kind, uint64_t v, int mask) {
+    Fiber* f = rt().cur;
+    f->st = kind;
+    f->in = v;
+    f->mask = mask;
+    yield_to_sched(false);
+    return f->out;
+}
+
+inline void block_barrier() {
+    Fiber* f = rt().cur;
+    f->st = AT_BLOCK;
+    yield_to_sched(false);
+}
+
+inline void run_block(const std::function<void()>& fn) {
+    Runtime& r = rt();
+    const int n = (int)(r.block.x * r.block.y * r.block.z);
+    if ((int)r.fibers.size() < n) r.fibers.resize(n);
+    r.body = &fn;
+    for (int t = 0; t < n; ++t) {
+        Fiber& f = r.fibers[t];
+        if (!f.stack) f.stack = static_cast<char*>(malloc(kStack));
+        f.tid = t;
+        f.st = READY;
+        f.asan_fake = nullptr;
+        getcontext(&f.ctx);
+        f.ctx.uc_stack.ss_sp = f.stack;
+        f.ctx.uc_stack.ss_size = kStack;
+        f.ctx.uc_link = nullptr;
+        makecontext(&f.ctx, fiber_entry, 0);
+    }
+    const int nw = (n + 63) / 64;
+    for (;;) {
+        bool ran = false;
+        for (int t = 0; t < n; ++t) {
+            Fiber& f = r.fibers[t];
+            if (f.st != READY) continue;
+            ran = true;
+            r.cur = &f;
+            void* fake = nullptr;
+#ifdef HIPEMU_ASAN
+            __sanitizer_start_switch_fiber(&fake, f.stack, kStack);
+#endif
+            swapcontext(&r.sched, &f.ctx);
+#ifdef HIPEMU_ASAN
+            __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
+#endif
+        }
+        (void)ran;
+        bool all_done = true, resolved = false;
+        for (int t = 0; t < n; ++t) all_done &= r.fibers[t].st == DONE;
+        if (all_done) break;
+        for (int w = 0; w < nw; ++w) {
+            const int lo = w * 64, hi = lo + 64 < n ? lo + 64 : n;
+            int live = 0, first = -1, kindc = 0;
+            State kind = READY;
+            bool same = true;
+            for (int t = lo; t < hi; ++t) {
+                const State s = r.fibers[t].st;
+                if (s == DONE) continue;
+                ++live;
+                if (first < 0) { first = t; kind = s; }
+                same &= s == kind;
+                kindc += (s == AT_WAVE_FIRST || s == AT_WAVE_XOR);
+            }
+            if (!live || !same || (kind != AT_WAVE_FIRST && kind != AT_WAVE_XOR)) continue;
+            for (int t = lo; t < hi; ++t) {
+                Fiber& f = r.fibers[t];
+                if (f.st == DONE) continue;
+                if (kind == AT_WAVE_FIRST) {
+                    f.out = r.fibers[first].in;
+                } else {
+                    const int p = lo + ((t - lo) ^ f.mask);
+                    if (p >= hi || r.fibers[p].st != AT_WAVE_XOR) {
+                        fprintf(stderr, "hipemu: __shfl_xor partner lane %d inactive\n", p);
+                        abort();
+                    }
+                    f.out = r.fibers[p].in;
+                }
+            }
+            for (int t = lo; t < hi; ++t)
+                if (r.fibers[t].st != DONE) r.fibers[t].st = READY;
+            resolved = true;
+        }
+        if (resolved) continue;
+        bool barrier = true;
+        for (int t = 0; t < n; ++t) barrier &= (r.fibers[t].st == DONE || r.fibers[t].st == AT_BLOCK);
+        if (barrier) {
+            for (int t = 0; t < n; ++t)
+                if (r.fibers[t].st == AT_BLOCK) r.fibers[t].st = READY;
+            continue;
+        }
+        fprintf(stderr, "hipemu: lanes wait on different barriers (divergent sync) in block "
+                        "(%u,%u,%u)\n", r.bidx.x, r.bidx.y, r.bidx.z);
+        abort();
+    }
+}
+
+inline void run_grid(dim3 g, dim3 b, const std::function<void()>& fn) {
+    Runtime& r = rt();
+    r.grid = g;
+    r.block = b;
+    r.launches++;
+    for (unsigned z = 0; z < g.z; ++z)
+        for (unsigned y = 0; y < g.y; ++y)
+            for (unsigned x = 0; x < g.x; ++x) {
+                r.bidx = dim3(x, y, z);
+                run_block(fn);
+            }
+}
+
+}  // namespace hipemu

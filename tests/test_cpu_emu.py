@@ -1,0 +1,108 @@
+"""The library's own kernel and runtime sources, compiled for the host under
+AddressSanitizer + UndefinedBehaviorSanitizer (tests/cpu_emu), run small
+cases of every code path and are compared with the FP64 oracle.  Any read
+or write outside the caller's workspace or tensors, any undefined integer
+or float-to-int conversion, and any divergent barrier aborts the run.
+
+This is the CPU check of every kernel's indexing and launch shape before it
+runs on a GPU; it is not a fallback (the package never loads it)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as o
+import workloads as wl
+from emu import run_case
+from helpers import compare_fields, oracle_dev, weights
+
+
+def test_droplet_2d_graph_and_tiles():
+    W = wl.droplet_2d_small()
+    for shape, gs in ((0, 4), (1, 2), (2, 0)):
+        g = run_case([W.params], [W.nodes], steps=(5, 4), shape=shape, graph_steps=gs)[0]
+        r = o.run(W.params, W.nodes, 9)
+        drho, du, dq = compare_fields(g, r, 2, f"emu tile{shape}")
+        assert g["status"] == 0
+        assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
+        assert abs(g["diag"]["mass"] - r["f"].sum()) < 1e-6
+
+
+def test_ragged_box_and_periodic_crossing():
+    p = wl.Params(dim=2, nx=101, ny=37, tau=0.8, sigma=0.008, theta_eq_deg=110.0, xi=2.0)
+    q = wl.cap_polygon(10.0, 95.0, 2.0, 70, 2.0)
+    g = run_case([p], [q], steps=(7,), shape=2, graph_steps=2)[0]
+    r = o.run(p, q, 7)
+    drho, du, dq = compare_fields(g, r, 2, "emu ragged")
+    assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
+
+
+def test_batch_with_fluid_only_member():
+    ps = [wl.Params(dim=2, nx=96, ny=40, tau=0.7, sigma=0.006, theta_eq_deg=40.0, xi=2.0),
+          wl.Params(dim=2, nx=70, ny=33, tau=1.3, sigma=0.009, theta_eq_deg=140.0, xi=2.0),
+          wl.Params(dim=2, nx=64, ny=8, tau=0.9, wetting=False)]
+    qs = [wl.cap_polygon(12.0, 90.0, 2.0, 94, 48.0), wl.cap_polygon(9.0, 90.0, 2.0, 71, 35.0),
+          None]
+    out = run_case(ps, qs, steps=(6,), graph_steps=2)
+    for d in range(2):
+        r = o.run(ps[d], qs[d], 6)
+        drho, du, dq = compare_fields(out[d], r, 2, f"emu batch{d}")
+        assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
+    assert np.all(out[2]["fdev"] == 0)
+    # timed direct launches, and a frozen member that must not move
+    out = run_case(ps, qs, steps=(3, 3), timing=True, inactive=(1,))
+    r = o.run(ps[0], qs[0], 6)
+    drho, du, dq = compare_fields(out[0], r, 2, "emu batch timed")
+    assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
+    assert np.array_equal(out[1]["q"], qs[1]) and np.all(out[1]["fdev"] == 0)
+
+
+def test_droplet_3d_tiny():
+    p = wl.Params(dim=3, nx=20, ny=18, nz=12, bc=(0, 0, 1), tau=0.8, sigma=0.005,
+                  theta_eq_deg=70.0, xi=2.0)
+    V, T = wl.cap_mesh(5.0, 90.0, 2.0, 3, (10.0, 9.0))
+    g = run_case([p], [V], [T], steps=(3,), graph_steps=2)[0]
+    r = o.run(p, V, 3, tris=T)
+    drho, du, dq = compare_fields(g, r, 3, "emu 3d")
+    assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
+    assert abs(g["diag"]["volume"] - o.volume_3d(r["q"], T)) < 1e-9 * abs(g["diag"]["volume"])
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2])
+def test_streaming_bit_exact_all_storages(storage):
+    for dim, (nx, ny, nz), bc in ((2, (37, 9, 1), (0, 1, 0)), (3, (9, 5, 4), (1, 0, 1))):
+        Q = 9 if dim == 2 else 19
+        w = weights(dim)
+        dev = wl.tagged_deviation(Q, nx * ny * nz, 5).reshape(Q, nz, ny, nx)
+        p = wl.Params(dim=dim, nx=nx, ny=ny, nz=nz, bc=bc, tau=math.inf, wetting=False)
+        g = run_case([p], steps=(3,), storage=storage, f0dev=[dev], graph_steps=2)[0]
+        f = w[:, None, None, None] + dev
+        for _ in range(3):
+            f, _, _ = o.lb_step(dim, nx, ny, nz, bc, math.inf, f, None)
+        k = np.rint((f - w[:, None, None, None]) * 1024.0)
+        assert np.array_equal(g["fdev"], k / 1024.0)
+
+
+def test_prescribed_force_field():
+    nx, ny, nz = 23, 7, 1
+    w = weights(2)
+    rng = np.random.default_rng(9)
+    dev = 1e-2 * w[:, None, None, None] * rng.standard_normal((9, nz, ny, nx))
+    F = np.zeros((3, nz, ny, nx))
+    F[:2] = 1e-4 * rng.standard_normal((2, nz, ny, nx))
+    p = wl.Params(dim=2, nx=nx, ny=ny, bc=(0, 1, 0), tau=0.7, wetting=False)
+    g = run_case([p], steps=(4,), f0dev=[dev], forces=[F])[0]
+    r = o.run(p, None, 4, f0=w[:, None, None, None] + dev, F_fixed=F)
+    assert np.max(np.abs(g["fdev"] - oracle_dev(2, r["f"]))) <= 1e-8
+    assert np.max(np.abs(g["U"] - r["U"][:2])) <= 1e-8
+
+
+def test_blow_up_is_reported_without_undefined_behaviour():
+    """Huge surface tension: speeds and then positions become non-finite.
+    The step reports IBLB_EUNSTABLE and no tap index is formed from a
+    non-finite coordinate."""
+    p = wl.Params(dim=2, nx=64, ny=32, tau=1.0, sigma=50.0, theta_eq_deg=60.0, xi=2.0)
+    q = wl.cap_polygon(8.0, 90.0, 2.0, 40, 32.0)
+    g = run_case([p], [q], steps=(50,))[0]
+    assert g["status"] == -4
+    assert g["diag"]["status"] == -4

