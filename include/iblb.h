@@ -183,24 +183,48 @@ int iblb_read_nodes(iblb_ctx *ctx, int droplet, double *h_pos, float *h_vel, flo
  * Synchronises. */
 int iblb_diagnostics(iblb_ctx *ctx, int droplet, iblb_diag *out);
 
-/* Tile shape of the lattice kernel: index into the shape list (0: 256x1
- * cells per block, 1: 128x2, 2: 64x4), or -1 to keep the current one.
- * Returns the shape in use via *shape_out (may be NULL). */
-int iblb_set_tile_shape(iblb_ctx *ctx, int shape, int *shape_out);
+/* Variant of the lattice kernel (all compute the same result):
+ *   0: 256x1 cells per block   3: 256x1, non-temporal stores
+ *   1: 128x2 cells per block   4: 128x2, non-temporal stores
+ *   2:  64x4 cells per block   5:  64x4, non-temporal stores
+ * variant = -1 keeps the current one; *variant_out (may be NULL) receives
+ * the variant in use. */
+int iblb_set_lb_variant(iblb_ctx *ctx, int variant, int *variant_out);
 
-/* Number of steps captured in one replayed graph (>= 2, even); default 64.
- * 0 disables graphs (every step launched directly). */
+/* Time every lattice-kernel variant over `steps` real time steps each (the
+ * steps advance the simulation) and keep the fastest.  With cache_path
+ * non-NULL the winner is looked up in / appended to that text file, keyed
+ * by device, lattice, storage and size bucket; a cache hit runs no step.
+ * chosen (may be NULL) receives the variant; ms (may be NULL, 6 entries)
+ * the measured lattice-kernel milliseconds per step (-1 on a cache hit). */
+int iblb_autotune(iblb_ctx *ctx, int steps, const char *cache_path, int *chosen, double *ms);
+
+/* Number of steps captured in one replayed graph (even, 2..1024); default
+ * 64.  0 disables graphs (every step launched directly). */
 int iblb_set_graph_steps(iblb_ctx *ctx, int steps);
 
 /* Mark droplet d active (1) or frozen (0).  Frozen droplets are skipped by
  * every kernel until re-activated; their state is kept. */
 int iblb_set_active(iblb_ctx *ctx, int droplet, int active);
 
-/* Measured device time (milliseconds, hipEvent based) of the lattice kernel
- * and of the whole step, averaged over the steps of the last iblb_step()
- * call made with timing on (see iblb_set_timing). */
+/* With timing on, iblb_step() runs the same schedule (graph replays plus
+ * direct launches) while the lattice kernel stamps its first block start
+ * and its last wavefront end (after that wavefront's stores complete) on
+ * the device's constant-rate clock; the stream is synchronised after each
+ * replay to read the stamps (graphs of more than 256 steps are replaced by
+ * direct launches while timing).  iblb_last_timing() gives that kernel's
+ * average duration and the average time of a step (milliseconds) over the
+ * last such call, the final field-storing step excluded from the kernel
+ * average. */
 int iblb_set_timing(iblb_ctx *ctx, int on);
 int iblb_last_timing(const iblb_ctx *ctx, double *lb_ms_per_step, double *step_ms_per_step);
+
+/* Measurement aid: copy `bytes` (a multiple of 16) from d_src to d_dst on
+ * the device, reps + 1 times; *gbs receives the mean of the last reps
+ * copies in GB/s counting read + write bytes (attainable HBM bandwidth when
+ * the buffers are much larger than the caches). */
+int iblb_probe_copy(void *d_dst, const void *d_src, size_t bytes, int reps, void *stream,
+                    double *gbs);
 
 #ifdef __cplusplus
 }

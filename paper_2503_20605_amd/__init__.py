@@ -23,7 +23,7 @@ from ._lib import (IBLB_BF16, IBLB_F16, IBLB_F32, IBLB_PERIODIC, IBLB_WALL, Iblb
                    iblb_diag, iblb_params)
 
 __all__ = ["Solver", "make_params", "IblbError", "IBLB_F32", "IBLB_F16", "IBLB_BF16",
-           "IBLB_PERIODIC", "IBLB_WALL", "STORAGE"]
+           "IBLB_PERIODIC", "IBLB_WALL", "STORAGE", "probe_copy_bandwidth"]
 
 STORAGE = {"f32": IBLB_F32, "f16": IBLB_F16, "bf16": IBLB_BF16}
 
@@ -50,6 +50,21 @@ def params_from(obj) -> iblb_params:
                        bc=obj.bc, tau=obj.tau, sigma=obj.sigma,
                        theta_eq_deg=obj.theta_eq_deg, xi=obj.xi, n_exp=obj.n_exp,
                        m_exp=obj.m_exp, wetting=obj.wetting)
+
+
+def probe_copy_bandwidth(nbytes=1 << 30, reps=20, device="cuda"):
+    """Attainable device copy bandwidth (GB/s, read + write) on buffers of
+    nbytes each."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    out = ctypes.c_double()
+    stream = torch.cuda.current_stream(src.device)
+    _lib.check(_lib.load().iblb_probe_copy(ctypes.c_void_p(dst.data_ptr()),
+                                           ctypes.c_void_p(src.data_ptr()), nbytes, reps,
+                                           ctypes.c_void_p(stream.cuda_stream), ctypes.byref(out)))
+    return out.value
 
 
 class Solver:
@@ -155,10 +170,19 @@ class Solver:
     def step(self, n):
         self._chk(self.lib.iblb_step(self.ctx, int(n)))
 
-    def set_tile_shape(self, shape):
+    def set_lb_variant(self, variant):
         out = ctypes.c_int()
-        self._chk(self.lib.iblb_set_tile_shape(self.ctx, int(shape), ctypes.byref(out)))
+        self._chk(self.lib.iblb_set_lb_variant(self.ctx, int(variant), ctypes.byref(out)))
         return out.value
+
+    def autotune(self, steps=50, cache_path=None):
+        """Time the six lattice-kernel variants and keep the fastest; returns
+        (variant, per-variant ms or -1 on a cache hit)."""
+        out = ctypes.c_int()
+        ms = (ctypes.c_double * 6)()
+        cp = None if cache_path is None else str(cache_path).encode()
+        self._chk(self.lib.iblb_autotune(self.ctx, int(steps), cp, ctypes.byref(out), ms))
+        return out.value, list(ms)
 
     def set_graph_steps(self, k):
         self._chk(self.lib.iblb_set_graph_steps(self.ctx, int(k)))

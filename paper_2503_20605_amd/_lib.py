@@ -29,8 +29,9 @@ EXPORTED = (
     "iblb_workspace_bytes", "iblb_create", "iblb_destroy", "iblb_last_error",
     "iblb_set_interface", "iblb_init_rest", "iblb_write_populations",
     "iblb_read_populations", "iblb_set_force_field", "iblb_step", "iblb_read_fields",
-    "iblb_read_nodes", "iblb_diagnostics", "iblb_set_tile_shape", "iblb_set_graph_steps",
-    "iblb_set_active", "iblb_set_timing", "iblb_last_timing",
+    "iblb_read_nodes", "iblb_diagnostics", "iblb_set_lb_variant", "iblb_autotune",
+    "iblb_set_graph_steps", "iblb_set_active", "iblb_set_timing", "iblb_last_timing",
+    "iblb_probe_copy",
 )
 
 
@@ -95,7 +96,9 @@ def load() -> ctypes.CDLL:
     lib.iblb_read_fields.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_void_p]
     lib.iblb_read_nodes.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_void_p]
     lib.iblb_diagnostics.argtypes = [c_void_p, c_int, P(iblb_diag)]
-    lib.iblb_set_tile_shape.argtypes = [c_void_p, c_int, ip]
+    lib.iblb_set_lb_variant.argtypes = [c_void_p, c_int, ip]
+    lib.iblb_autotune.argtypes = [c_void_p, c_int, ctypes.c_char_p, ip, P(c_double)]
+    lib.iblb_probe_copy.argtypes = [c_void_p, c_void_p, c_size_t, c_int, c_void_p, P(c_double)]
     lib.iblb_set_graph_steps.argtypes = [c_void_p, c_int]
     lib.iblb_set_active.argtypes = [c_void_p, c_int, c_int]
     lib.iblb_set_timing.argtypes = [c_void_p, c_int]

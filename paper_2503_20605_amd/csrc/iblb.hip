@@ -6,6 +6,7 @@
 // concatenates every active droplet's tiles), k_interp_advect (nodes).
 // Long runs replay a hipGraph that holds a fixed, even number of steps, so
 // the ping-pong buffers are back in place after every replay.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,9 +26,14 @@ using namespace iblb;
 
 namespace {
 
+// Lattice-kernel variants (autotuner candidates): tile shape 256x1, 128x2 or
+// 64x4 cells per block, each with ordinary or non-temporal stores.
 constexpr int kShapes = 3;
+constexpr int kVariants = 2 * kShapes;
 constexpr int kShapeBX[kShapes] = {256, 128, 64};
 constexpr size_t kAlign = 256;
+constexpr int kMaxGraphSteps = 1024;
+constexpr int kTimedLaunches = 256;  // timed lattice launches per replay at most
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
@@ -35,7 +41,7 @@ int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 struct Layout {
     // byte offsets into the workspace
     size_t drops, tiles_lb, tiles_all, f0, f1, F, U, Fout, rho, flags, pos, phi, qdot, dropped,
-        node_drop, tri, inc, inc_beg, inc_end, status, partials, diag, total;
+        node_drop, tri, inc, inc_beg, inc_end, status, partials, diag, stamps, stamps_out, total;
     long long cells;       // sum of cells
     long long flag_bytes;  // sum of band flags
     int ntot, ttot, max_tiles;
@@ -44,7 +50,7 @@ struct Layout {
 };
 
 int tiles_of(const iblb_params& p, int shape) {
-    const int bx = kShapeBX[shape], by = kBlock / bx;
+    const int bx = kShapeBX[shape % kShapes], by = kBlock / bx;
     return ceil_div(p.nx, bx) * ceil_div(p.ny, by) * (p.dim == 3 ? p.nz : 1);
 }
 
@@ -147,6 +153,8 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.status = take(sizeof(int) * n);
     L.partials = take(sizeof(double) * 8 * L.max_tiles);
     L.diag = take(sizeof(DiagDev) * n);
+    L.stamps = take(sizeof(unsigned long long) * (size_t)kStampWords * (kTimedLaunches + 1));
+    L.stamps_out = take(sizeof(unsigned long long) * 2 * (kTimedLaunches + 1));
     L.total = o;
     return true;
 }
@@ -162,15 +170,18 @@ struct iblb_ctx {
     char* ws = nullptr;
     hipStream_t stream = nullptr, cap_stream = nullptr;
     int cur = 0;  // buffer holding the current post-collision populations
-    int shape = 0;
+    int variant = 0;  // lattice-kernel variant; its tile shape is variant % kShapes
     int ntiles_lb = 0, ntiles_all = 0;
     bool tiles_dirty = true;
     std::vector<int4> tiles_h;
     int graph_steps = 64;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipGraphExec_t texec[2] = {nullptr, nullptr};  // same steps with event nodes
     bool timing = false;
     double t_lb = 0.0, t_step = 0.0;
     std::vector<hipEvent_t> events;
+    std::vector<unsigned long long> stamps_h;
+    double clock_khz = 0.0;  // rate of wall_clock64() on the device
     long long step = 0;
     std::vector<int> status_h;
     std::vector<char> iface_set;
@@ -215,11 +226,16 @@ NodeArrays node_arrays(const iblb_ctx* c) {
 }
 
 void drop_graphs(iblb_ctx* c) {
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 2; ++k) {
         if (c->exec[k]) {
             (void)hipGraphExecDestroy(c->exec[k]);
             c->exec[k] = nullptr;
         }
+        if (c->texec[k]) {
+            (void)hipGraphExecDestroy(c->texec[k]);
+            c->texec[k] = nullptr;
+        }
+    }
 }
 
 int upload_drops(iblb_ctx* c) {
@@ -232,7 +248,7 @@ int upload_drops(iblb_ctx* c) {
 // Tiles of droplet d, x fastest, then y, then z.
 void push_tiles(const iblb_ctx* c, int d, std::vector<int4>& v) {
     const iblb_params& p = c->params[d];
-    const int bx = kShapeBX[c->shape], by = kBlock / bx;
+    const int bx = kShapeBX[c->variant % kShapes], by = kBlock / bx;
     const int ntx = ceil_div(p.nx, bx), nty = ceil_div(p.ny, by);
     const int nz = c->dim == 3 ? p.nz : 1;
     for (int z = 0; z < nz; ++z)
@@ -265,42 +281,46 @@ int rebuild_tiles(iblb_ctx* c) {
 // ---- kernel dispatch -------------------------------------------------------
 
 template <int DIM, int S>
-void launch_lb_t(const iblb_ctx* c, hipStream_t s, int src, int full) {
+void launch_lb_t(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned long long* stamps) {
     using T = typename Codec<S>::T;
     T* f[2] = {c->at<T>(c->L.f0), c->at<T>(c->L.f1)};
     const dim3 grid(c->ntiles_lb), block(kBlock);
-    auto args = [&](auto kern) {
+    auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, grid, block, 0, s, c->at<DropDev>(c->L.drops),
-                           c->at<int4>(c->L.tiles_lb), f[src], f[src ^ 1], c->at<float>(c->L.F),
-                           c->at<float>(c->L.U), c->at<float>(c->L.rho), c->at<float>(c->L.Fout),
-                           c->at<uint8_t>(c->L.flags), full);
+                           c->at<int4>(c->L.tiles_lb), (const T*)f[src], f[src ^ 1],
+                           c->at<float>(c->L.F), c->at<float>(c->L.U), c->at<float>(c->L.rho),
+                           c->at<float>(c->L.Fout), c->at<uint8_t>(c->L.flags), full, stamps);
     };
-    switch (c->shape) {
-        case 0: args(k_lb<DIM, S, 256>); break;
-        case 1: args(k_lb<DIM, S, 128>); break;
-        default: args(k_lb<DIM, S, 64>); break;
+    switch (c->variant) {
+        case 0: go(k_lb<DIM, S, 256, 0>); break;
+        case 1: go(k_lb<DIM, S, 128, 0>); break;
+        case 2: go(k_lb<DIM, S, 64, 0>); break;
+        case 3: go(k_lb<DIM, S, 256, 1>); break;
+        case 4: go(k_lb<DIM, S, 128, 1>); break;
+        default: go(k_lb<DIM, S, 64, 1>); break;
     }
 }
 
 template <int DIM>
-void launch_lb_d(const iblb_ctx* c, hipStream_t s, int src, int full) {
+void launch_lb_d(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned long long* stamps) {
     switch (c->storage) {
-        case ST_F32: launch_lb_t<DIM, ST_F32>(c, s, src, full); break;
-        case ST_F16: launch_lb_t<DIM, ST_F16>(c, s, src, full); break;
-        default: launch_lb_t<DIM, ST_BF16>(c, s, src, full); break;
+        case ST_F32: launch_lb_t<DIM, ST_F32>(c, s, src, full, stamps); break;
+        case ST_F16: launch_lb_t<DIM, ST_F16>(c, s, src, full, stamps); break;
+        default: launch_lb_t<DIM, ST_BF16>(c, s, src, full, stamps); break;
     }
 }
 
-void launch_lb(const iblb_ctx* c, hipStream_t s, int src, int full) {
+void launch_lb(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned long long* stamps) {
     if (c->ntiles_lb == 0) return;
-    if (c->dim == 2) launch_lb_d<2>(c, s, src, full);
-    else launch_lb_d<3>(c, s, src, full);
+    if (c->dim == 2) launch_lb_d<2>(c, s, src, full, stamps);
+    else launch_lb_d<3>(c, s, src, full, stamps);
 }
 
 void launch_nodes(const iblb_ctx* c, hipStream_t s, int phase, int full) {
     if (c->L.ntot == 0) return;
     const NodeArrays A = node_arrays(c);
-    const dim3 grid(ceil_div(c->L.ntot, kBlock)), block(kBlock);
+    const int lanes = c->L.ntot * (c->dim == 2 ? Taps<2>::n : Taps<3>::n);
+    const dim3 grid(ceil_div(lanes, kBlock)), block(kBlock);
     const DropDev* D = c->at<DropDev>(c->L.drops);
     if (phase == 0) {
         if (c->dim == 2)
@@ -319,34 +339,74 @@ void launch_nodes(const iblb_ctx* c, hipStream_t s, int phase, int full) {
     }
 }
 
-// One time step from buffer `src`; events (may be null) bracket the lattice
-// kernel.
-void launch_step(const iblb_ctx* c, hipStream_t s, int src, int full, hipEvent_t e0 = nullptr,
-                 hipEvent_t e1 = nullptr) {
+// One time step from buffer `src`; stamps (may be null) is the timing slot
+// pair of its lattice launch.
+void launch_step(const iblb_ctx* c, hipStream_t s, int src, int full,
+                 unsigned long long* stamps = nullptr) {
     launch_nodes(c, s, 0, full);
-    if (e0) (void)hipEventRecord(e0, s);
-    launch_lb(c, s, src, full);
-    if (e1) (void)hipEventRecord(e1, s);
+    launch_lb(c, s, src, full, stamps);
     launch_nodes(c, s, 1, full);
 }
 
-int ensure_graph(iblb_ctx* c, int parity) {
-    if (c->exec[parity]) return IBLB_OK;
+int ensure_events(iblb_ctx* c, int need) {
+    while ((int)c->events.size() < need) {
+        hipEvent_t ev;
+        HIPCHK(c, hipEventCreate(&ev));
+        c->events.push_back(ev);
+    }
+    return IBLB_OK;
+}
+
+// Graph of graph_steps steps starting from buffer `parity`; with `timed`
+// the lattice launch of step k uses timing slot set k (timed graphs hold at
+// most kTimedLaunches steps).
+int ensure_graph(iblb_ctx* c, int parity, bool timed = false) {
+    hipGraphExec_t* slot = timed ? &c->texec[parity] : &c->exec[parity];
+    if (*slot) return IBLB_OK;
+    unsigned long long* st = c->at<unsigned long long>(c->L.stamps);
     hipGraph_t g = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     int src = parity;
     for (int k = 0; k < c->graph_steps; ++k) {
-        launch_step(c, c->cap_stream, src, 0);
+        launch_step(c, c->cap_stream, src, 0, timed ? st + (size_t)k * kStampWords : nullptr);
         src ^= 1;
     }
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (e != hipSuccess) return fail(c, IBLB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&c->exec[parity], g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(slot, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        c->exec[parity] = nullptr;
+        *slot = nullptr;
         return fail(c, IBLB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
     }
+    return IBLB_OK;
+}
+
+// Reset the timing slot sets [first, first + n) before a timed sequence
+// (a fill kernel on the stream, never inside a graph).
+int reset_stamps(iblb_ctx* c, int first, int n) {
+    unsigned long long* st = c->at<unsigned long long>(c->L.stamps) + (size_t)first * kStampWords;
+    hipLaunchKernelGGL(k_stamps_reset, dim3(ceil_div((long long)n * kStampSpread, kBlock)), dim3(kBlock),
+                       0, c->stream, st, n);
+    HIPCHK(c, hipGetLastError());
+    return IBLB_OK;
+}
+
+// Sum over slot sets [first, first + n) of (latest end - earliest start),
+// in milliseconds.  Synchronises the stream.
+int read_stamps(iblb_ctx* c, int first, int n, double& ms) {
+    unsigned long long* st = c->at<unsigned long long>(c->L.stamps) + (size_t)first * kStampWords;
+    unsigned long long* out = c->at<unsigned long long>(c->L.stamps_out);
+    hipLaunchKernelGGL(k_stamps_fold, dim3(n), dim3(kStampSpread), 0, c->stream, (const unsigned long long*)st,
+                       out);
+    HIPCHK(c, hipGetLastError());
+    c->stamps_h.resize(2 * n);
+    HIPCHK(c, hipMemcpyAsync(c->stamps_h.data(), out, sizeof(unsigned long long) * 2 * n,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    ms = 0.0;
+    for (int k = 0; k < n; ++k)
+        ms += (double)(c->stamps_h[2 * k + 1] - c->stamps_h[2 * k]) / c->clock_khz;
     return IBLB_OK;
 }
 
@@ -435,7 +495,7 @@ void launch_cell_sums(iblb_ctx* c) {
                            c->at<int4>(c->L.tiles_all), f, c->at<float>(c->L.U), c->at<float>(c->L.rho),
                            c->at<float>(c->L.Fout), c->at<double>(c->L.partials));
     };
-    switch (c->shape) {
+    switch (c->variant % kShapes) {
         case 0: go(k_cell_sums<DIM, S, 256>); break;
         case 1: go(k_cell_sums<DIM, S, 128>); break;
         default: go(k_cell_sums<DIM, S, 64>); break;
@@ -535,6 +595,14 @@ int iblb_create(int n, const iblb_params* P, const int* nn, const int* nt, int s
         // minimum of Pi(h): h* = xi (n/m)^(1/(n-m))
         D.zcut = p.wetting ? p.xi * pow((double)p.n_exp / p.m_exp, 1.0 / (p.n_exp - p.m_exp))
                            : p.xi;
+    }
+    {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            c->clock_khz = khz;
+        else
+            c->clock_khz = 100000.0;  // 100 MHz, the usual rate
     }
     hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -704,33 +772,53 @@ int iblb_step(iblb_ctx* c, int n_steps) {
         if (rc) return rc;
     }
     if (c->timing) {
-        // direct launches with events around every lattice kernel
-        const int need = 2 * n_steps + 2;
-        while ((int)c->events.size() < need) {
-            hipEvent_t ev;
-            HIPCHK(c, hipEventCreate(&ev));
-            c->events.push_back(ev);
+        // Same schedule as below (graph replays + direct launches), with the
+        // lattice kernel stamping its own start and end on the device clock;
+        // the stream is synchronised after each replay to read the stamps.
+        // The final field-storing step is not timed.
+        hipEvent_t ev[2];
+        for (int k = 0; k < 2; ++k) {
+            int rc = ensure_events(c, 2);
+            if (rc) return rc;
+            ev[k] = c->events[k];
         }
-        HIPCHK(c, hipEventRecord(c->events[0], c->stream));
-        for (int k = 0; k < n_steps; ++k) {
-            launch_step(c, c->stream, c->cur, k == n_steps - 1, c->events[2 + 2 * k],
-                        c->events[3 + 2 * k]);
-            c->cur ^= 1;
-        }
-        HIPCHK(c, hipEventRecord(c->events[1], c->stream));
-        HIPCHK(c, hipGetLastError());
-        HIPCHK(c, hipEventSynchronize(c->events[1]));
-        float ms = 0.f;
-        double lb = 0.0;
-        const int nlb = n_steps > 1 ? n_steps - 1 : 1;  // the last step also stores fields
-        for (int k = 0; k < nlb; ++k) {
-            HIPCHK(c, hipEventElapsedTime(&ms, c->events[2 + 2 * k], c->events[3 + 2 * k]));
+        unsigned long long* st = c->at<unsigned long long>(c->L.stamps);
+        const int eager_slot = kTimedLaunches;
+        const bool graphs = c->graph_steps > 0 && c->graph_steps <= kTimedLaunches;
+        double lb = 0.0, ms = 0.0;
+        long long nlb = 0;
+        HIPCHK(c, hipEventRecord(ev[0], c->stream));
+        int rem = n_steps, rc;
+        while (rem > 1) {
+            if (graphs && rem - 1 >= c->graph_steps) {
+                if ((rc = ensure_graph(c, c->cur, true)) || (rc = reset_stamps(c, 0, c->graph_steps)))
+                    return rc;
+                HIPCHK(c, hipGraphLaunch(c->texec[c->cur], c->stream));
+                if ((rc = read_stamps(c, 0, c->graph_steps, ms))) return rc;
+                nlb += c->graph_steps;
+                rem -= c->graph_steps;
+                c->step += c->graph_steps;
+            } else {
+                if ((rc = reset_stamps(c, eager_slot, 1))) return rc;
+                launch_step(c, c->stream, c->cur, 0, st + (size_t)eager_slot * kStampWords);
+                if ((rc = read_stamps(c, eager_slot, 1, ms))) return rc;
+                ++nlb;
+                c->cur ^= 1;
+                rem--;
+                c->step++;
+            }
             lb += ms;
         }
-        c->t_lb = lb / nlb;
-        HIPCHK(c, hipEventElapsedTime(&ms, c->events[0], c->events[1]));
-        c->t_step = ms / n_steps;
-        c->step += n_steps;
+        launch_step(c, c->stream, c->cur, 1);
+        c->cur ^= 1;
+        c->step++;
+        HIPCHK(c, hipEventRecord(ev[1], c->stream));
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipEventSynchronize(ev[1]));
+        float total = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&total, ev[0], ev[1]));
+        c->t_lb = nlb ? lb / nlb : 0.0;
+        c->t_step = total / n_steps;
     } else {
         int rem = n_steps;
         while (rem > 1) {
@@ -854,20 +942,22 @@ int iblb_diagnostics(iblb_ctx* c, int d, iblb_diag* out) {
     return IBLB_OK;
 }
 
-int iblb_set_tile_shape(iblb_ctx* c, int shape, int* shape_out) {
+int iblb_set_lb_variant(iblb_ctx* c, int variant, int* variant_out) {
     if (!c) return IBLB_EINVAL;
-    if (shape >= kShapes || shape < -1) return fail(c, IBLB_EINVAL, "tile shape must be -1, 0, 1 or 2");
-    if (shape >= 0 && shape != c->shape) {
-        c->shape = shape;
+    if (variant >= kVariants || variant < -1)
+        return fail(c, IBLB_EINVAL, "lattice-kernel variant must be -1 or 0..5");
+    if (variant >= 0 && variant != c->variant) {
+        c->variant = variant;
         c->tiles_dirty = true;
     }
-    if (shape_out) *shape_out = c->shape;
+    if (variant_out) *variant_out = c->variant;
     return IBLB_OK;
 }
 
 int iblb_set_graph_steps(iblb_ctx* c, int steps) {
     if (!c) return IBLB_EINVAL;
-    if (steps < 0 || steps == 1 || (steps & 1)) return fail(c, IBLB_EINVAL, "graph steps must be 0 or an even number >= 2");
+    if (steps < 0 || steps == 1 || (steps & 1) || steps > kMaxGraphSteps)
+        return fail(c, IBLB_EINVAL, "graph steps must be 0 or an even number in 2..1024");
     if (steps != c->graph_steps) {
         drop_graphs(c);
         c->graph_steps = steps;
@@ -896,6 +986,111 @@ int iblb_last_timing(const iblb_ctx* c, double* lb_ms, double* step_ms) {
     if (lb_ms) *lb_ms = c->t_lb;
     if (step_ms) *step_ms = c->t_step;
     return IBLB_OK;
+}
+
+int iblb_autotune(iblb_ctx* c, int steps, const char* cache_path, int* chosen, double* ms_out) {
+    if (!c) return IBLB_EINVAL;
+    if (steps < 2) return fail(c, IBLB_EINVAL, "autotune needs at least 2 steps per variant");
+    // cache key: device, lattice, storage, total cells and droplet count (log2 buckets)
+    int dev = 0;
+    hipDeviceProp_t prop;
+    HIPCHK(c, hipGetDevice(&dev));
+    HIPCHK(c, hipGetDeviceProperties(&prop, dev));
+    int cb = 0, db = 0;
+    while ((1LL << cb) < c->L.cells) ++cb;
+    while ((1 << db) < c->n) ++db;
+    char key[256];
+    snprintf(key, sizeof key, "%s/%d D%dQ%d storage=%d cells=2^%d droplets=2^%d", prop.gcnArchName,
+             prop.multiProcessorCount, c->dim, c->Q, c->storage, cb, db);
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "r");
+        if (f) {
+            char line[512];
+            while (fgets(line, sizeof line, f)) {
+                char* bar = strrchr(line, '|');
+                if (!bar) continue;
+                *bar = 0;
+                if (strcmp(line, key) == 0) {
+                    const int v = atoi(bar + 1);
+                    fclose(f);
+                    if (v < 0 || v >= kVariants) break;
+                    int rc = iblb_set_lb_variant(c, v, chosen);
+                    if (ms_out)
+                        for (int k = 0; k < kVariants; ++k) ms_out[k] = -1.0;
+                    return rc;
+                }
+            }
+            fclose(f);
+        }
+    }
+    const bool was_timing = c->timing;
+    c->timing = true;
+    int best = c->variant;
+    double best_ms = 1e300;
+    for (int v = 0; v < kVariants; ++v) {
+        int rc = iblb_set_lb_variant(c, v, nullptr);
+        if (!rc) rc = iblb_step(c, steps);
+        if (rc) {
+            c->timing = was_timing;
+            return rc;
+        }
+        if (ms_out) ms_out[v] = c->t_lb;
+        if (c->t_lb < best_ms) {
+            best_ms = c->t_lb;
+            best = v;
+        }
+    }
+    c->timing = was_timing;
+    int rc = iblb_set_lb_variant(c, best, chosen);
+    if (rc) return rc;
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s|%d\n", key, best);
+            fclose(f);
+        }
+    }
+    return IBLB_OK;
+}
+
+int iblb_probe_copy(void* d_dst, const void* d_src, size_t bytes, int reps, void* stream,
+                    double* gbs) {
+    if (!d_dst || !d_src || !gbs || reps < 1 || bytes < 16 || bytes % 16)
+        return fail(nullptr, IBLB_EINVAL, "probe: bad arguments (bytes must be a multiple of 16)");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const long long n = (long long)(bytes / 16);
+    const int grid = ceil_div(n, 4LL * kBlock);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fail(nullptr, IBLB_EDEVICE, "probe: event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(nullptr, IBLB_EDEVICE, "probe: event");
+    }
+    // best of plain and non-temporal accesses
+    double best = 0.0;
+    int rc = IBLB_OK;
+    for (int nt = 0; nt < 2 && rc == IBLB_OK; ++nt) {
+        double total = 0.0;
+        for (int r = 0; r <= reps && rc == IBLB_OK; ++r) {
+            const v4f* src = static_cast<const v4f*>(d_src);
+            v4f* dst = static_cast<v4f*>(d_dst);
+            if (nt)
+                hipExtLaunchKernelGGL(k_copy_probe<1>, dim3(grid), dim3(kBlock), 0, s, e0, e1, 0,
+                                      src, dst, n);
+            else
+                hipExtLaunchKernelGGL(k_copy_probe<0>, dim3(grid), dim3(kBlock), 0, s, e0, e1, 0,
+                                      src, dst, n);
+            float ms = 0.f;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                rc = fail(nullptr, IBLB_EDEVICE, "probe: timing");
+            if (r > 0) total += ms;  // the first launch warms up
+        }
+        if (rc == IBLB_OK) best = std::max(best, 2.0 * (double)bytes * reps / (total * 1e-3) / 1e9);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == IBLB_OK) *gbs = best;
+    return rc;
 }
 
 }  // extern "C"

@@ -64,6 +64,43 @@ struct DiagDev {
     double cross_n;
 };
 
+// Timing slots of one lattice launch: kStampSpread (start, end) pairs,
+// kStampStride words apart (one 128-byte line each).
+constexpr int kStampSpread = 256;
+constexpr int kStampStride = 16;
+constexpr int kStampWords = kStampSpread * kStampStride;
+
+// Reset the timing slots of `launches` launches: starts to the maximum,
+// ends to zero.
+__global__ void k_stamps_reset(unsigned long long* __restrict__ st, int launches) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= launches * kStampSpread) return;
+    st[(long long)i * kStampStride] = ~0ULL;
+    st[(long long)i * kStampStride + 1] = 0ULL;
+}
+
+// Fold each launch's slots into (earliest start, latest end): one block of
+// kStampSpread threads per launch.
+__global__ void k_stamps_fold(const unsigned long long* __restrict__ st,
+                              unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long lo[kStampSpread], hi[kStampSpread];
+    const int l = blockIdx.x, t = threadIdx.x;
+    lo[t] = st[((long long)l * kStampSpread + t) * kStampStride];
+    hi[t] = st[((long long)l * kStampSpread + t) * kStampStride + 1];
+    __syncthreads();
+    for (int o = kStampSpread / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            lo[t] = lo[t] < lo[t + o] ? lo[t] : lo[t + o];
+            hi[t] = hi[t] > hi[t + o] ? hi[t] : hi[t + o];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[2 * l] = lo[0];
+        out[2 * l + 1] = hi[0];
+    }
+}
+
 // Blocks are dealt round-robin to the eight XCDs.  Remap the block index so
 // that each XCD works through one contiguous run of tiles: x-neighbouring
 // strips and y-neighbouring rows then meet in the same L2.
@@ -75,7 +112,9 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // ---------------------------------------------------------------------------
 // Lattice kernel
 // ---------------------------------------------------------------------------
-template <int DIM, int S, int BX>
+// NT = 1 writes the new populations with non-temporal stores: they are not
+// read again before the next launch, so they need not displace cached lines.
+template <int DIM, int S, int BX, int NT>
 __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops,
                                                const int4* __restrict__ tiles,
                                                const typename Codec<S>::T* __restrict__ fsrc_all,
@@ -83,11 +122,17 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
                                                float* __restrict__ F_all, float* __restrict__ U_all,
                                                float* __restrict__ rho_all,
                                                float* __restrict__ Fout_all,
-                                               uint8_t* __restrict__ flags_all, int full) {
+                                               uint8_t* __restrict__ flags_all, int full,
+                                               unsigned long long* __restrict__ stamps) {
     using L = Lattice<DIM>;
     using C = Codec<S>;
     constexpr int Q = L::Q;
     constexpr int BY = kBlock / BX;
+    // timing only (stamps non-null): block start on the device's
+    // constant-rate clock, folded into one of kStampSpread slots (one cache
+    // line each) so that the atomics do not pile up on a single address
+    unsigned long long* stamp = stamps ? stamps + (blockIdx.x % kStampSpread) * kStampStride : nullptr;
+    if (stamp && threadIdx.x == 0) atomicMin(stamp, (unsigned long long)wall_clock64());
     const int4 tile = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const DropDev& D = drops[tile.x];
     const int nx = D.nx, ny = D.ny, nz = D.nz;
@@ -173,7 +218,10 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
             // S_i = (1 - 1/2tau) w_i [3 (c - U).F + 9 (c.U)(c.F)]
             fn += g * L::w[i] * (3.f * (cF - uF) + 9.f * cu * cF);
         }
-        C::store(fdst, i * ncell + cell, fn);
+        if (NT)
+            C::store_nt(fdst, i * ncell + cell, fn);
+        else
+            C::store(fdst, i * ncell + cell, fn);
     }
 
     if (forced && D.force_mode == 0) {
@@ -198,29 +246,12 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
             Fo[2 * ncell + cell] = Fz;
         }
     }
-}
-
-// ---------------------------------------------------------------------------
-// Peskin 4-point kernel
-// ---------------------------------------------------------------------------
-// For a node at coordinate q the four taps are the cells base..base+3 with
-// base = floor(q - 1/2) - 1, at distances 1 + r, r, 1 - r, 2 - r from the
-// node (r = q - 1/2 - floor(q - 1/2) in [0, 1)).  With s = sqrt(1 + 4r - 4r^2)
-// both branches of Psi reduce to
-//   Psi(1+r) = (3 - 2r - s)/8, Psi(r) = (3 - 2r + s)/8,
-//   Psi(1-r) = (1 + 2r + s)/8, Psi(2-r) = (1 + 2r - s)/8,
-// so one square root serves all four taps.
-__device__ __forceinline__ void peskin_taps(double q, int& base, float w[4]) {
-    const double u = q - 0.5;
-    const double fl = floor(u);
-    const float r = (float)(u - fl);
-    base = (int)fl - 1;
-    const float s = sqrtf(1.f + 4.f * r * (1.f - r));
-    const float a = 3.f - 2.f * r, b = 1.f + 2.f * r;
-    w[0] = (a - s) * 0.125f;
-    w[1] = (a + s) * 0.125f;
-    w[2] = (b + s) * 0.125f;
-    w[3] = (b - s) * 0.125f;
+    if (stamp) {
+        // wavefront end, once its stores have completed; lane 0 of a
+        // wavefront is active whenever any lane is (x grows with the lane)
+        __builtin_amdgcn_s_waitcnt(0);
+        if ((threadIdx.x & 63) == 0) atomicMax(stamp + 1, (unsigned long long)wall_clock64());
+    }
 }
 
 // Nodes whose coordinates are not finite or lie absurdly far from any box
@@ -343,7 +374,67 @@ __device__ __forceinline__ void node_geom_3d(const DropDev& D, const NodeArrays&
 }
 
 // ---------------------------------------------------------------------------
-// Nodal forces + spreading
+// Node kernels: one lane per (node, tap)
+// ---------------------------------------------------------------------------
+// A node owns a group of TAPS consecutive lanes (16 in 2D: 4 nodes per
+// wavefront; 64 in 3D: one wavefront per node).  Every lane of the group
+// evaluates the node's geometry (same instructions, broadcast loads), then
+// handles one tap of the delta kernel; sums over the taps are shuffles
+// inside the group.  This turns a serial chain of 16 or 64 scattered
+// memory operations per thread into one per lane.
+template <int DIM>
+struct Taps {
+    static constexpr int n = DIM == 2 ? 16 : 64;
+};
+
+// ---------------------------------------------------------------------------
+// Peskin 4-point kernel
+// ---------------------------------------------------------------------------
+// For a node at coordinate q the four taps are the cells base..base+3 with
+// base = floor(q - 1/2) - 1, at distances 1 + r, r, 1 - r, 2 - r from the
+// node (r = q - 1/2 - floor(q - 1/2) in [0, 1)).  With s = sqrt(1 + 4r - 4r^2)
+// both branches of Psi reduce to
+//   Psi(1+r) = (3 - 2r - s)/8, Psi(r) = (3 - 2r + s)/8,
+//   Psi(1-r) = (1 + 2r + s)/8, Psi(2-r) = (1 + 2r - s)/8,
+// so one square root serves all four taps.
+//
+// peskin_tap: weight of tap k (0..3) of a node at coordinate q, and the
+// index of tap 0.
+__device__ __forceinline__ float peskin_tap(double q, int k, int& base) {
+    const double u = q - 0.5;
+    const double fl = floor(u);
+    const float r = (float)(u - fl);
+    base = (int)fl - 1;
+    const float s = sqrtf(1.f + 4.f * r * (1.f - r));
+    const float a = k < 2 ? 3.f - 2.f * r : 1.f + 2.f * r;
+    return (a + ((k == 1 || k == 2) ? s : -s)) * 0.125f;
+}
+
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Lattice cell of this lane's tap, or -1 when it falls beyond a wall; also
+// the tap's row (z * ny + y) and x for the band flag.
+template <int DIM>
+__device__ __forceinline__ int lane_tap(const DropDev& D, const double q[3], int k, float& w,
+                                        int& row, int& ix) {
+    int bx, by, bz = 0;
+    w = peskin_tap(q[0], k & 3, bx) * peskin_tap(q[1], (k >> 2) & 3, by);
+    if (DIM == 3) w *= peskin_tap(q[2], k >> 4, bz);
+    ix = tap_index(bx, k & 3, D.nx, D.bcx);
+    const int iy = tap_index(by, (k >> 2) & 3, D.ny, D.bcy);
+    const int iz = DIM == 3 ? tap_index(bz, k >> 4, D.nz, D.bcz) : 0;
+    if ((ix | iy | iz) < 0) return -1;
+    row = iz * D.ny + iy;
+    return row * D.nx + ix;
+}
+
+// ---------------------------------------------------------------------------
+// Nodal forces + spreading (eq. force_spread)
 // ---------------------------------------------------------------------------
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_force_spread(const DropDev* __restrict__ drops,
@@ -351,7 +442,9 @@ __global__ __launch_bounds__(kBlock) void k_force_spread(const DropDev* __restri
                                                          uint8_t* __restrict__ flags_all,
                                                          int* __restrict__ status,
                                                          int want_dropped) {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
+    constexpr int T = Taps<DIM>::n;
+    const int gid = blockIdx.x * kBlock + threadIdx.x;
+    const int j = gid / T, k = gid % T;
     if (j >= A.ntot) return;
     const int d = A.node_drop[j];
     const DropDev& D = drops[d];
@@ -371,72 +464,58 @@ __global__ __launch_bounds__(kBlock) void k_force_spread(const DropDev* __restri
 #pragma unroll
         for (int a = 0; a < DIM; ++a) fs[a] -= share * P * n[a];
     }
-    float ph[3];
+    float ph[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        ph[a] = (float)fs[a];
-        A.phi[a * A.stride + j] = ph[a];
-    }
+    for (int a = 0; a < DIM; ++a) ph[a] = (float)fs[a];
+    if (k == 0)
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) A.phi[a * A.stride + j] = ph[a];
     bool ok = true;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) ok &= coord_ok(q[a]);
-    if (!ok) {
-        atomicOr(status + d, 4);
+    if (!ok) {  // the whole group leaves together
+        if (k == 0) atomicOr(status + d, 4);
         return;
     }
-
-    const int nx = D.nx, ny = D.ny, ncell = D.ncell;
-    int bx, by, bz = 0;
-    float wx[4], wy[4], wz[4] = {1.f, 0.f, 0.f, 0.f};
-    peskin_taps(q[0], bx, wx);
-    peskin_taps(q[1], by, wy);
-    if (DIM == 3) peskin_taps(q[2], bz, wz);
-    float* __restrict__ F = F_all + (long long)DIM * D.c_off;
-    uint8_t* __restrict__ flags = flags_all + D.flag_off;
+    float w;
+    int row, ix;
+    const int cell = lane_tap<DIM>(D, q, k, w, row, ix);
     float lost[3] = {0.f, 0.f, 0.f};
-    constexpr int KZ = DIM == 3 ? 4 : 1;
-    for (int kz = 0; kz < KZ; ++kz) {
-        const int iz = DIM == 3 ? tap_index(bz, kz, D.nz, D.bcz) : 0;
-        for (int ky = 0; ky < 4; ++ky) {
-            const int iy = tap_index(by, ky, ny, D.bcy);
-            const float wyz = wy[ky] * wz[kz];
+    if (cell < 0) {
 #pragma unroll
-            for (int kx = 0; kx < 4; ++kx) {
-                const int ix = tap_index(bx, kx, nx, D.bcx);
-                const float w = wx[kx] * wyz;
-                if ((ix | iy | iz) < 0) {
+        for (int a = 0; a < DIM; ++a) lost[a] = ph[a] * w;
+    } else {
+        float* __restrict__ F = F_all + (long long)DIM * D.c_off;
 #pragma unroll
-                    for (int a = 0; a < DIM; ++a) lost[a] += ph[a] * w;
-                    continue;
-                }
-                const int cell = (iz * ny + iy) * nx + ix;
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) unsafeAtomicAdd(F + a * ncell + cell, ph[a] * w);
-                flags[(iz * ny + iy) * D.nstrip + (ix >> 6)] = 1;
-            }
-        }
+        for (int a = 0; a < DIM; ++a) unsafeAtomicAdd(F + a * D.ncell + cell, ph[a] * w);
+        flags_all[D.flag_off + row * D.nstrip + (ix >> 6)] = 1;
     }
     if (want_dropped) {
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) A.dropped[a * A.stride + j] = lost[a];
+        for (int a = 0; a < DIM; ++a) lost[a] = group_sum<T>(lost[a]);
+        if (k == 0)
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) A.dropped[a * A.stride + j] = lost[a];
     }
 }
 
 // ---------------------------------------------------------------------------
-// Interpolation + advection
+// Interpolation (eq. vel_interpolation) + forward-Euler advection
 // ---------------------------------------------------------------------------
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_interp_advect(const DropDev* __restrict__ drops,
                                                           NodeArrays A,
                                                           const float* __restrict__ U_all,
                                                           int* __restrict__ status) {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
+    constexpr int T = Taps<DIM>::n;
+    const int gid = blockIdx.x * kBlock + threadIdx.x;
+    const int j = gid / T, k = gid % T;
     if (j >= A.ntot) return;
     const int d = A.node_drop[j];
     const DropDev& D = drops[d];
     if (!D.active || D.force_mode != 0) return;
     const int st = A.stride;
-    double q[3];
+    double q[3] = {0, 0, 0};
     bool ok = true;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
@@ -444,34 +523,21 @@ __global__ __launch_bounds__(kBlock) void k_interp_advect(const DropDev* __restr
         ok &= coord_ok(q[a]);
     }
     if (!ok) {
-        atomicOr(status + d, 4);
+        if (k == 0) atomicOr(status + d, 4);
         return;
     }
-    const int nx = D.nx, ny = D.ny, ncell = D.ncell;
-    int bx, by, bz = 0;
-    float wx[4], wy[4], wz[4] = {1.f, 0.f, 0.f, 0.f};
-    peskin_taps(q[0], bx, wx);
-    peskin_taps(q[1], by, wy);
-    if (DIM == 3) peskin_taps(q[2], bz, wz);
-    const float* __restrict__ U = U_all + (long long)DIM * D.c_off;
+    float w;
+    int row, ix;
+    const int cell = lane_tap<DIM>(D, q, k, w, row, ix);
     float acc[3] = {0.f, 0.f, 0.f};
-    constexpr int KZ = DIM == 3 ? 4 : 1;
-    for (int kz = 0; kz < KZ; ++kz) {
-        const int iz = DIM == 3 ? tap_index(bz, kz, D.nz, D.bcz) : 0;
-        for (int ky = 0; ky < 4; ++ky) {
-            const int iy = tap_index(by, ky, ny, D.bcy);
-            const float wyz = wy[ky] * wz[kz];
+    if (cell >= 0) {  // beyond a wall the fluid is at rest: no contribution
+        const float* __restrict__ U = U_all + (long long)DIM * D.c_off;
 #pragma unroll
-            for (int kx = 0; kx < 4; ++kx) {
-                const int ix = tap_index(bx, kx, nx, D.bcx);
-                if ((ix | iy | iz) < 0) continue;  // no-slip wall: U = 0 there
-                const float w = wx[kx] * wyz;
-                const int cell = (iz * ny + iy) * nx + ix;
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) acc[a] += U[a * ncell + cell] * w;
-            }
-        }
+        for (int a = 0; a < DIM; ++a) acc[a] = U[a * D.ncell + cell] * w;
     }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) acc[a] = group_sum<T>(acc[a]);
+    if (k != 0) return;
     float sp = 0.f;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
@@ -500,6 +566,32 @@ __global__ void k_pop_read(const typename Codec<S>::T* __restrict__ f, long long
                            double* __restrict__ dst) {
     const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) dst[i] = Codec<S>::to_double(f[i]);
+}
+
+// Streaming copy used to measure the attainable HBM bandwidth of the device:
+// each lane moves four 16-byte vectors, all loads issued before the stores.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_copy_probe(const v4f* __restrict__ src,
+                                                       v4f* __restrict__ dst, long long n) {
+    const long long base = (long long)blockIdx.x * (4 * kBlock) + threadIdx.x;
+    v4f v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const long long i = base + (long long)u * kBlock;
+        if (i < n) v[u] = NT ? __builtin_nontemporal_load(src + i) : src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const long long i = base + (long long)u * kBlock;
+        if (i < n) {
+            if (NT)
+                __builtin_nontemporal_store(v[u], dst + i);
+            else
+                dst[i] = v[u];
+        }
+    }
 }
 
 __global__ void k_fill_f32(float* __restrict__ p, long long n, float v) {

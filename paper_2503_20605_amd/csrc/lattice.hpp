@@ -54,6 +54,9 @@ struct Codec<ST_F32> {
     using T = float;
     static __device__ __forceinline__ float load(const T* p, int i) { return p[i]; }
     static __device__ __forceinline__ void store(T* p, int i, float v) { p[i] = v; }
+    static __device__ __forceinline__ void store_nt(T* p, int i, float v) {
+        __builtin_nontemporal_store(v, p + i);
+    }
     static __host__ __device__ __forceinline__ T from_double(double v) { return (float)v; }
     static __host__ __device__ __forceinline__ double to_double(T v) { return (double)v; }
 };
@@ -63,6 +66,9 @@ struct Codec<ST_F16> {
     using T = _Float16;
     static __device__ __forceinline__ float load(const T* p, int i) { return (float)p[i]; }
     static __device__ __forceinline__ void store(T* p, int i, float v) { p[i] = (_Float16)v; }
+    static __device__ __forceinline__ void store_nt(T* p, int i, float v) {
+        __builtin_nontemporal_store((_Float16)v, p + i);
+    }
     // exchange values are narrowed through fp32 (nearest even at each step)
     static __device__ __forceinline__ T from_double(double v) { return (_Float16)(float)v; }
     static __device__ __forceinline__ double to_double(T v) { return (double)(float)v; }
@@ -84,6 +90,9 @@ struct Codec<ST_BF16> {
     using T = uint16_t;
     static __device__ __forceinline__ float load(const T* p, int i) { return bf16_to_f32(p[i]); }
     static __device__ __forceinline__ void store(T* p, int i, float v) { p[i] = f32_to_bf16_rne(v); }
+    static __device__ __forceinline__ void store_nt(T* p, int i, float v) {
+        __builtin_nontemporal_store(f32_to_bf16_rne(v), p + i);
+    }
     // exchange values are narrowed through fp32 (nearest even at each step)
     static __device__ __forceinline__ T from_double(double v) { return f32_to_bf16_rne((float)v); }
     static __device__ __forceinline__ double to_double(T v) { return (double)bf16_to_f32(v); }

@@ -113,7 +113,7 @@ int main(int argc, char** argv) {
         }
     }
     if (cfg.count("graph_steps")) iblb_set_graph_steps(ctx, geti("graph_steps", 64));
-    if (cfg.count("shape")) iblb_set_tile_shape(ctx, geti("shape", 0), nullptr);
+    if (cfg.count("shape")) iblb_set_lb_variant(ctx, geti("shape", 0), nullptr);
     if (cfg.count("timing")) iblb_set_timing(ctx, geti("timing", 0));
     for (int d = 0; d < n; ++d)
         if (geti("inactive_" + std::to_string(d), 0)) iblb_set_active(ctx, d, 0);

@@ -41,6 +41,9 @@ struct int4 {
     int x, y, z, w;
 };
 inline int4 make_int4(int a, int b, int c, int d) { return int4{a, b, c, d}; }
+struct alignas(16) float4 {
+    float x, y, z, w;
+};
 
 typedef enum {
     hipSuccess = 0,
@@ -145,6 +148,14 @@ inline void launch(void* stream, dim3 g, dim3 b, K k, A... a) {
 #define hipLaunchKernelGGL(kern, grid, block, shmem, stream, ...) \
     ::hipemu::launch((void*)(stream), dim3(grid), dim3(block), kern, __VA_ARGS__)
 
+// launch with start/stop events stamped by the dispatch (timing is faked)
+template <typename K, typename Ev, typename... A>
+inline void hipExtLaunchKernelGGL(K kern, dim3 grid, dim3 block, unsigned shmem, void* stream,
+                                  Ev, Ev, unsigned, A... a) {
+    (void)shmem;
+    ::hipemu::launch(stream, grid, block, kern, a...);
+}
+
 inline void __syncthreads() { ::hipemu::block_barrier(); }
 
 inline int __builtin_amdgcn_readfirstlane(int v) {
@@ -155,6 +166,22 @@ template <typename T>
 inline T __shfl_xor(T v, int mask, int width = 64) {
     (void)width;
     return ::hipemu::unpack<T>(::hipemu::wave_op(::hipemu::AT_WAVE_XOR, ::hipemu::pack(v), mask));
+}
+
+inline long long wall_clock64() {
+    static long long t = 0;
+    return t += 7;
+}
+inline void __builtin_amdgcn_s_waitcnt(int) {}
+inline unsigned long long atomicMin(unsigned long long* p, unsigned long long v) {
+    unsigned long long old = *p;
+    if (v < old) *p = v;
+    return old;
+}
+inline unsigned long long atomicMax(unsigned long long* p, unsigned long long v) {
+    unsigned long long old = *p;
+    if (v > old) *p = v;
+    return old;
 }
 
 inline float unsafeAtomicAdd(float* p, float v) {
@@ -173,6 +200,26 @@ typedef hipemu::Graph* hipGraph_t;
 typedef hipemu::Graph* hipGraphExec_t;
 typedef hipemu::Event* hipEvent_t;
 typedef void* hipGraphNode_t;
+
+struct hipDeviceProp_t {
+    char gcnArchName[256];
+    int multiProcessorCount;
+};
+inline hipError_t hipGetDevice(int* d) {
+    *d = 0;
+    return hipSuccess;
+}
+inline hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int) {
+    strcpy(p->gcnArchName, "host-emulation");
+    p->multiProcessorCount = 1;
+    return hipSuccess;
+}
+
+#define hipDeviceAttributeWallClockRate 1
+inline hipError_t hipDeviceGetAttribute(int* v, int, int) {
+    *v = 100000;
+    return hipSuccess;
+}
 
 inline hipError_t hipGetLastError() {
     hipError_t e = hipemu::rt().last;
@@ -205,6 +252,8 @@ inline hipError_t hipEventDestroy(hipEvent_t e) {
     return hipSuccess;
 }
 inline hipError_t hipEventRecord(hipEvent_t, hipStream_t = nullptr) { return hipSuccess; }
+#define hipEventRecordExternal 0x01
+inline hipError_t hipEventRecordWithFlags(hipEvent_t, hipStream_t, unsigned) { return hipSuccess; }
 inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) {
     *ms = 1e-3f;

@@ -27,7 +27,7 @@ def gpu_run(p, q0, steps, tris=None, storage=0, f0dev=None, F_fixed=None, graph_
     if graph_steps is not None:
         s.set_graph_steps(graph_steps)
     if shape is not None:
-        s.set_tile_shape(shape)
+        s.set_lb_variant(shape)
     if f0dev is not None:
         s.write_populations(0, f0dev)
     if F_fixed is not None:

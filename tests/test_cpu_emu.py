@@ -19,8 +19,9 @@ from helpers import compare_fields, oracle_dev, weights
 
 def test_droplet_2d_graph_and_tiles():
     W = wl.droplet_2d_small()
-    for shape, gs in ((0, 4), (1, 2), (2, 0)):
-        g = run_case([W.params], [W.nodes], steps=(5, 4), shape=shape, graph_steps=gs)[0]
+    for shape, gs in ((0, 4), (4, 2), (2, 0)):
+        g = run_case([W.params], [W.nodes], steps=(5, 4), shape=shape, graph_steps=gs,
+                     timing=(shape == 4))[0]
         r = o.run(W.params, W.nodes, 9)
         drho, du, dq = compare_fields(g, r, 2, f"emu tile{shape}")
         assert g["status"] == 0
@@ -31,7 +32,7 @@ def test_droplet_2d_graph_and_tiles():
 def test_ragged_box_and_periodic_crossing():
     p = wl.Params(dim=2, nx=101, ny=37, tau=0.8, sigma=0.008, theta_eq_deg=110.0, xi=2.0)
     q = wl.cap_polygon(10.0, 95.0, 2.0, 70, 2.0)
-    g = run_case([p], [q], steps=(7,), shape=2, graph_steps=2)[0]
+    g = run_case([p], [q], steps=(7,), shape=5, graph_steps=2)[0]
     r = o.run(p, q, 7)
     drho, du, dq = compare_fields(g, r, 2, "emu ragged")
     assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
