@@ -48,7 +48,73 @@ def parse():
                     help="also time the lattice kernel on working sets far above the LLC")
     ap.add_argument("--profile-only", action="store_true",
                     help="short run for profilers: no CPU leg, no extra sizes")
+    ap.add_argument("--tte", action="store_true",
+                    help="time to equilibrium of the 256-droplet batch instead of the step rate")
+    ap.add_argument("--droplets", type=int, default=256)
+    ap.add_argument("--max-steps", type=int, default=200000)
+    ap.add_argument("--workload", default="d2q9", choices=["d2q9", "d3q19"])
     return ap.parse_args()
+
+
+def run_batch_to_rest(draws, storage, max_steps, tol=1e-6):
+    """Run every droplet of the batch from its 90-degree start until its
+    interface is at rest.  Returns wall seconds, per-droplet steps and
+    measured angles (degrees)."""
+    import torch
+    from paper_2503_20605_amd import Solver, params_from
+    s = Solver([params_from(w.params) for w in draws], [w.nodes for w in draws], storage=storage)
+    s.set_graph_steps(100)
+    v, _ = s.autotune(steps=20)
+    s.init_rest(-1)
+    for d, w in enumerate(draws):
+        s.set_interface(d, w.nodes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = s.run_to_rest(tol=tol, check_every=100, hold=10, max_steps=max_steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dg = s.diagnostics(-1)
+    ang = [math.degrees(x["theta_meas"]) for x in dg]
+    s.close()
+    return wall, steps, ang, v
+
+
+def tte(a):
+    import numpy as np
+    import workloads as wl
+    draws = wl.batch_draws(a.droplets, seed=3)
+    cells = sum(w.params.nx * w.params.ny for w in draws)
+    res = {}
+    for name, st in (("f32", 0), ("f16", 1)):
+        wall, steps, ang, v = run_batch_to_rest(draws, st, a.max_steps)
+        res[name] = dict(wall_s=wall, steps=steps, theta_deg=ang, variant=v)
+        print(f"[tte] {name}: {wall:.1f} s, converged {sum(1 for x in steps if x > 0)}/"
+              f"{len(steps)}, median steps {np.median([x for x in steps if x > 0] or [0]):.0f}",
+              flush=True)
+    both = [i for i in range(len(draws))
+            if res["f16"]["steps"][i] > 0 and res["f32"]["steps"][i] > 0]
+    dth = np.abs(np.array(res["f16"]["theta_deg"]) - np.array(res["f32"]["theta_deg"]))
+    dth_both = dth[both] if both else np.zeros(1)
+    conv = lambda k: [x for x in res[k]["steps"] if x > 0]
+    out = {"metric": "time to equilibrium of the droplet batch (interface normal speed < 1e-6)",
+           "droplets": len(draws), "cells": cells,
+           "plain_f32": {"wall_s": round(res["f32"]["wall_s"], 2),
+                          "converged": len(conv("f32")),
+                          "median_steps": float(np.median(conv("f32") or [0])),
+                          "lb_variant": res["f32"]["variant"]},
+           "f16_storage": {"wall_s": round(res["f16"]["wall_s"], 2),
+                           "converged": len(conv("f16")),
+                           "median_steps": float(np.median(conv("f16") or [0])),
+                           "lb_variant": res["f16"]["variant"]},
+           "speedup_f16_vs_f32": round(res["f32"]["wall_s"] / res["f16"]["wall_s"], 3),
+           "theta_abs_diff_deg": {"all_max": round(float(dth.max()), 4),
+                                  "all_median": round(float(np.median(dth)), 4),
+                                  "all_within_1deg": int((dth < 1.0).sum()),
+                                  "converged_in_both": len(both),
+                                  "both_max": round(float(dth_both.max()), 4),
+                                  "both_within_1deg": int((dth_both < 1.0).sum())},
+           "max_steps": a.max_steps}
+    print(json.dumps(out), flush=True)
 
 
 def lb_only_rate(dim, nx, ny, nz, storage, steps):
@@ -81,11 +147,18 @@ def main():
     import workloads as wl
     from paper_2503_20605_amd import STORAGE, Solver, params_from
 
+    if a.tte:
+        tte(a)
+        return
     storage = STORAGE[a.storage]
-    W = wl.droplet_2d_large(run=a.run)
+    if a.workload == "d3q19":
+        W = wl.droplet_3d(theta_eq_deg=90.0, small=False)
+    else:
+        W = wl.droplet_2d_large(run=a.run)
     p = W.params
-    cells = p.nx * p.ny
-    s = Solver([params_from(p)], [W.nodes], storage=storage)
+    dim = p.dim
+    cells = p.nx * p.ny * (p.nz if dim == 3 else 1)
+    s = Solver([params_from(p)], [W.nodes], None if W.tris is None else [W.tris], storage=storage)
     s.set_graph_steps(a.graph_steps)
     steps, warm = a.steps, a.warmup
     if a.profile_only:
@@ -113,7 +186,7 @@ def main():
     s.step(nt + 1)
     lb_ms, step_ms_events = s.last_timing()
     s.set_timing(False)
-    bpc = bytes_per_cell(2, storage)
+    bpc = bytes_per_cell(dim, storage)
     achieved = bpc * cells / (lb_ms * 1e-3) / 1e9
     diag = s.diagnostics(0)
 
@@ -130,7 +203,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if storage == 0 else f"f32 compute, {a.storage} storage",
         "data": "synthetic (seeded droplet workload)",
-        "config": {"workload": W.name, "lattice": "D2Q9 1024x512", "nodes": 1024,
+        "config": {"workload": W.name,
+                   "lattice": "D2Q9 1024x512" if dim == 2 else "D3Q19 256x256x128",
+                   "nodes": len(W.nodes),
                    "tau": p.tau, "theta_eq_deg": p.theta_eq_deg, "sigma": p.sigma, "xi": p.xi,
                    "storage": a.storage, "graph_steps": a.graph_steps,
                    "lb_variant": variant},
@@ -139,8 +214,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_cell": bpc, "cells_per_launch": cells,
                      "lb_us_per_launch": round(lb_ms * 1e3, 3),
-                     "note": "38 MB working set (two population copies) fits the 256 MB "
-                             "Infinity Cache; see lb_hbm for working sets far above it"},
+                     "working_set_MB": round(bpc * cells / 1e6, 1)},
         "step_us_timed_pass": round(step_ms_events * 1e3, 3),
         "autotune_lb_ms": tune_ms,
         "diag": {"mass": diag["mass"], "theta_meas_deg": math.degrees(diag["theta_meas"]),
@@ -157,7 +231,7 @@ def main():
                          lb_only_rate(3, 256, 256, 128, 0, 100),
                          lb_only_rate(3, 256, 256, 128, 1, 100)]
 
-    if not a.no_cpu and not a.profile_only:
+    if not a.no_cpu and not a.profile_only and dim == 2:
         import oracle as o
         import numpy as np
         t0 = time.perf_counter()

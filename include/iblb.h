@@ -183,6 +183,18 @@ int iblb_read_nodes(iblb_ctx *ctx, int droplet, double *h_pos, float *h_vel, flo
  * Synchronises. */
 int iblb_diagnostics(iblb_ctx *ctx, int droplet, iblb_diag *out);
 
+/* Run every active droplet that has an interface until it comes to rest:
+ * every check_every steps the largest normal node speed |qdot . n| of each
+ * such droplet is compared with tol; a droplet below tol for `hold`
+ * consecutive checks is frozen (iblb_set_active(ctx, d, 0)) and
+ * steps_out[d] receives the number of steps it took.  A droplet that turns
+ * unstable is frozen with steps_out[d] = -2; one still moving after
+ * max_steps keeps -1; droplets without interface or frozen on entry get 0.
+ * steps_out: host array of n_droplets entries.  Returns when every tracked
+ * droplet is frozen or after max_steps steps. */
+int iblb_run_to_rest(iblb_ctx *ctx, double tol, int check_every, int hold, long long max_steps,
+                     long long *steps_out);
+
 /* Variant of the lattice kernel (all compute the same result):
  *   0: 256x1 cells per block   3: 256x1, non-temporal stores
  *   1: 128x2 cells per block   4: 128x2, non-temporal stores

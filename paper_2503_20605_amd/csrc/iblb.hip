@@ -503,14 +503,17 @@ void launch_cell_sums(iblb_ctx* c) {
 }
 
 template <int DIM>
-void launch_diag_d(iblb_ctx* c) {
-    switch (c->storage) {
-        case ST_F32: launch_cell_sums<DIM, ST_F32>(c); break;
-        case ST_F16: launch_cell_sums<DIM, ST_F16>(c); break;
-        default: launch_cell_sums<DIM, ST_BF16>(c); break;
+void launch_diag_d(iblb_ctx* c, bool cells = true) {
+    if (cells) {
+        switch (c->storage) {
+            case ST_F32: launch_cell_sums<DIM, ST_F32>(c); break;
+            case ST_F16: launch_cell_sums<DIM, ST_F16>(c); break;
+            default: launch_cell_sums<DIM, ST_BF16>(c); break;
+        }
     }
     hipLaunchKernelGGL(k_diag<DIM>, dim3(c->n), dim3(kBlock), 0, c->stream, c->at<DropDev>(c->L.drops),
-                       node_arrays(c), c->at<double>(c->L.partials), c->at<DiagDev>(c->L.diag));
+                       node_arrays(c), cells ? (const double*)c->at<double>(c->L.partials) : nullptr,
+                       c->at<DiagDev>(c->L.diag));
 }
 
 }  // namespace
@@ -938,6 +941,58 @@ int iblb_diagnostics(iblb_ctx* c, int d, iblb_diag* out) {
         fill_diag(c, d, r[d], st[d], out);
     } else {
         for (int k = 0; k < c->n; ++k) fill_diag(c, k, r[k], st[k], out + k);
+    }
+    return IBLB_OK;
+}
+
+int iblb_run_to_rest(iblb_ctx* c, double tol, int check_every, int hold, long long max_steps,
+                     long long* steps_out) {
+    if (!c) return IBLB_EINVAL;
+    if (!steps_out || !(tol > 0.0) || check_every < 1 || hold < 1 || max_steps < 1)
+        return fail(c, IBLB_EINVAL, "run_to_rest: bad arguments");
+    if (c->tiles_dirty) {
+        int rc = rebuild_tiles(c);
+        if (rc) return rc;
+    }
+    std::vector<int> below(c->n, 0);
+    std::vector<DiagDev> r(c->n);
+    int live = 0;
+    for (int d = 0; d < c->n; ++d) {
+        const bool tracked = c->drops[d].active && c->n_nodes[d] > 0;
+        steps_out[d] = tracked ? -1 : 0;
+        live += tracked;
+    }
+    const long long start = c->step;
+    while (live > 0 && c->step - start < max_steps) {
+        const int n = (int)std::min<long long>(check_every, max_steps - (c->step - start));
+        int rc = iblb_step(c, n);
+        if (rc == IBLB_EUNSTABLE) {
+            // freeze the droplets that failed; the others carry on
+            for (int d = 0; d < c->n; ++d)
+                if (c->status_h[d] && c->drops[d].active) {
+                    iblb_set_active(c, d, 0);
+                    steps_out[d] = -2;
+                    --live;
+                }
+            if (c->tiles_dirty && (rc = rebuild_tiles(c))) return rc;
+            continue;
+        }
+        if (rc) return rc;
+        if (c->dim == 2) launch_diag_d<2>(c, false);
+        else launch_diag_d<3>(c, false);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(r.data(), c->at<DiagDev>(c->L.diag), sizeof(DiagDev) * c->n,
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int d = 0; d < c->n; ++d) {
+            if (steps_out[d] != -1) continue;
+            below[d] = r[d].max_un < tol ? below[d] + 1 : 0;
+            if (below[d] >= hold) {
+                steps_out[d] = c->step - start;
+                iblb_set_active(c, d, 0);
+                --live;
+            }
+        }
     }
     return IBLB_OK;
 }

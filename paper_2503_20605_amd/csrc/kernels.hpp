@@ -674,6 +674,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_sums(const DropDev* __restrict_
 }
 
 // One block per droplet: cell partials + interface reductions.
+// partials may be null: interface quantities only (cell sums left zero).
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_diag(const DropDev* __restrict__ drops, NodeArrays A,
                                                  const double* __restrict__ partials,
@@ -683,8 +684,9 @@ __global__ __launch_bounds__(kBlock) void k_diag(const DropDev* __restrict__ dro
     const DropDev& D = drops[d];
     DiagDev r;
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int t = D.tile_off + threadIdx.x; t < D.tile_off + D.n_tiles; t += kBlock)
-        for (int k = 0; k < 7; ++k) acc[k] += partials[(long long)t * 8 + k];
+    if (partials)
+        for (int t = D.tile_off + threadIdx.x; t < D.tile_off + D.n_tiles; t += kBlock)
+            for (int k = 0; k < 7; ++k) acc[k] += partials[(long long)t * 8 + k];
     for (int k = 0; k < 7; ++k) acc[k] = block_reduce(acc[k], 0, sh);
     r.mass_dev = acc[0];
     for (int a = 0; a < 3; ++a) {

@@ -126,6 +126,15 @@ int main(int argc, char** argv) {
             if (step_rc) break;
         }
     }
+    if (cfg.count("rest")) {  // tol,check_every,hold,max_steps
+        double tol = 0;
+        int check = 0, hold = 0;
+        long long mx = 0;
+        sscanf(cfg["rest"].c_str(), "%lf,%d,%d,%lld", &tol, &check, &hold, &mx);
+        std::vector<long long> so(n);
+        step_rc = iblb_run_to_rest(ctx, tol, check, hold, mx, so.data());
+        save("rest_steps.bin", so.data(), n);
+    }
     FILE* st = fopen((dir + "/status.txt").c_str(), "w");
     fprintf(st, "%d\n%s\n", step_rc, iblb_last_error(ctx));
     fclose(st);

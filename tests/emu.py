@@ -21,7 +21,7 @@ def _params_struct(p):
 
 def run_case(params_list, nodes_list=None, tris_list=None, steps=(1,), storage=0,
              graph_steps=None, shape=None, f0dev=None, forces=None, timing=False,
-             inactive=(), timeout=600):
+             inactive=(), rest=None, timeout=600):
     import build as emu_build
     from paper_2503_20605_amd._lib import iblb_diag
     exe = emu_build.build()
@@ -44,6 +44,8 @@ def run_case(params_list, nodes_list=None, tris_list=None, steps=(1,), storage=0
             cfg.append("timing 1")
         for k in inactive:
             cfg.append(f"inactive_{k} 1")
+        if rest is not None:
+            cfg.append("rest " + ",".join(str(v) for v in rest))
         for k in range(n):
             q = nodes_list[k]
             if q is not None:
@@ -71,6 +73,8 @@ def run_case(params_list, nodes_list=None, tris_list=None, steps=(1,), storage=0
         if r.returncode != 0:
             raise RuntimeError(f"emulated run failed (rc={r.returncode}):\n{r.stderr[-6000:]}")
         status = open(os.path.join(d, "status.txt")).read().split("\n", 1)
+        rest_steps = (np.fromfile(os.path.join(d, "rest_steps.bin"), dtype=np.int64)
+                      if rest is not None else None)
         outs = []
         for k in range(n):
             p = params_list[k]
@@ -93,5 +97,7 @@ def run_case(params_list, nodes_list=None, tris_list=None, steps=(1,), storage=0
             o["diag"] = dg.to_dict(dim)
             o["status"] = int(status[0])
             o["message"] = status[1].strip() if len(status) > 1 else ""
+            if rest_steps is not None:
+                o["rest_steps"] = int(rest_steps[k])
             outs.append(o)
         return outs

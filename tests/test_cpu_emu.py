@@ -107,3 +107,21 @@ def test_blow_up_is_reported_without_undefined_behaviour():
     g = run_case([p], [q], steps=(50,))[0]
     assert g["status"] == -4
     assert g["diag"]["status"] == -4
+
+
+def test_run_to_rest_freezes_settled_droplets():
+    """A loose tolerance so that the tiny cases settle within a few checks:
+    each droplet's frozen state equals the oracle after its reported step
+    count; the fluid-only member is ignored."""
+    ps = [wl.Params(dim=2, nx=40, ny=24, tau=1.0, sigma=0.004, theta_eq_deg=90.0, xi=2.0),
+          wl.Params(dim=2, nx=48, ny=20, tau=0.8, sigma=0.02, theta_eq_deg=60.0, xi=2.0),
+          wl.Params(dim=2, nx=32, ny=8, tau=0.9, wetting=False)]
+    qs = [wl.cap_polygon(6.0, 90.0, 2.0, 40, 20.0), wl.cap_polygon(6.0, 90.0, 2.0, 40, 24.0), None]
+    out = run_case(ps, qs, steps=(0,), rest=(2e-3, 4, 2, 60), graph_steps=2)
+    assert out[2]["rest_steps"] == 0
+    for d in range(2):
+        n = out[d]["rest_steps"]
+        assert n > 0 or n == -1
+        r = o.run(ps[d], qs[d], n if n > 0 else 60)
+        assert np.max(np.abs(out[d]["q"] - r["q"])) <= 1e-7
+    assert out[0]["rest_steps"] > 0

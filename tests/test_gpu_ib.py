@@ -194,3 +194,24 @@ def test_interface_validation():
     q[3, 1] = -0.5
     with pytest.raises(IblbError):
         gpu_solver([p], [q])
+
+
+def test_run_to_rest_state_matches_oracle():
+    """Batch run to rest: each droplet is frozen at the check where its
+    normal node speed stayed below the tolerance; its frozen state equals
+    the oracle after the reported number of steps."""
+    ps = [wl.Params(dim=2, nx=96, ny=40, tau=1.0, sigma=0.01, theta_eq_deg=70.0, xi=2.0),
+          wl.Params(dim=2, nx=64, ny=48, tau=0.7, sigma=0.006, theta_eq_deg=120.0, xi=2.0)]
+    qs = [wl.cap_polygon(10.0, 90.0, 2.0, 79, 48.0), wl.cap_polygon(8.0, 90.0, 2.0, 63, 30.0)]
+    s = gpu_solver(ps, qs)
+    s.set_graph_steps(10)
+    steps = s.run_to_rest(tol=2e-4, check_every=50, hold=3, max_steps=4000)
+    print("[rest] steps", steps, flush=True)
+    assert all(n > 0 for n in steps)
+    for d in range(2):
+        g = collect(s, d, 2)
+        r = o.run(ps[d], qs[d], steps[d])
+        assert np.max(np.abs(g["q"] - r["q"])) <= 1e-5
+        A = o.wetting_strength(ps[d].sigma, math.radians(ps[d].theta_eq_deg), ps[d].xi)
+        _, nrm = o.forces_2d(r["q"], ps[d].sigma, A, ps[d].xi)
+        assert np.max(np.abs(np.sum(r["qdot"] * nrm, axis=1))) < 2e-4
