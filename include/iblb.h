@@ -238,6 +238,46 @@ int iblb_last_timing(const iblb_ctx *ctx, double *lb_ms_per_step, double *step_m
 int iblb_probe_copy(void *d_dst, const void *d_src, size_t bytes, int reps, void *stream,
                     double *gbs);
 
+/* ------------------------------------------------------------------------
+ * Warm-start network (learned initial state; not part of the paper's
+ * method): a fully connected network widths[0] -> widths[1] -> ... ->
+ * widths[n_layers], GELU (exact, erf form) after every layer except the last.
+ * Products run on the matrix cores with bf16 operands (weights and
+ * activations rounded to nearest even) and fp32 accumulation; the weights
+ * are kept in fp32 (master copy) and trained with Adam on the mean squared
+ * error.  Parameters are packed per layer l: W_l [widths[l]][widths[l+1]]
+ * row-major (y = x W + b), then b_l [widths[l+1]].  All device memory comes
+ * from the caller's workspace; every call is ordered on the given stream.
+ * ------------------------------------------------------------------------ */
+typedef struct iblb_mlp iblb_mlp;
+
+size_t iblb_mlp_workspace_bytes(int n_layers, const int *widths, int max_batch);
+int iblb_mlp_create(int n_layers, const int *widths, int max_batch, void *d_workspace,
+                    size_t ws_bytes, void *stream, iblb_mlp **out);
+int iblb_mlp_destroy(iblb_mlp *mlp);
+const char *iblb_mlp_last_error(const iblb_mlp *mlp);
+long long iblb_mlp_param_count(const iblb_mlp *mlp);
+
+/* Host fp32 packed parameters in / out.  Setting resets the Adam state. */
+int iblb_mlp_set_params(iblb_mlp *mlp, const float *h_params);
+int iblb_mlp_get_params(iblb_mlp *mlp, float *h_params);
+
+/* d_x [batch][widths[0]] -> d_y [batch][widths[n_layers]], device fp32,
+ * 1 <= batch <= max_batch. */
+int iblb_mlp_forward(iblb_mlp *mlp, const float *d_x, int batch, float *d_y);
+
+/* Forward + backward of the mean squared error against d_t [batch][out]
+ * (device fp32).  *loss (host, may be NULL) receives the loss; h_grads
+ * (host, may be NULL, param_count floats) the packed gradient.  The
+ * gradient is kept for iblb_mlp_adam_step.  Synchronises when loss or
+ * h_grads is requested. */
+int iblb_mlp_gradients(iblb_mlp *mlp, const float *d_x, const float *d_t, int batch,
+                       float *h_grads, double *loss);
+
+/* One Adam step (bias-corrected) with the gradient of the last
+ * iblb_mlp_gradients call. */
+int iblb_mlp_adam_step(iblb_mlp *mlp, float lr, float beta1, float beta2, float eps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,7 +22,7 @@ from . import _lib
 from ._lib import (IBLB_BF16, IBLB_F16, IBLB_F32, IBLB_PERIODIC, IBLB_WALL, IblbError,
                    iblb_diag, iblb_params)
 
-__all__ = ["Solver", "make_params", "IblbError", "IBLB_F32", "IBLB_F16", "IBLB_BF16",
+__all__ = ["Solver", "MLP", "make_params", "IblbError", "IBLB_F32", "IBLB_F16", "IBLB_BF16",
            "IBLB_PERIODIC", "IBLB_WALL", "STORAGE", "probe_copy_bandwidth"]
 
 STORAGE = {"f32": IBLB_F32, "f16": IBLB_F16, "bf16": IBLB_BF16}
@@ -237,3 +237,79 @@ class Solver:
         out = iblb_diag()
         self._chk(self.lib.iblb_diagnostics(self.ctx, d, ctypes.byref(out)))
         return out.to_dict(self.dim)
+
+
+class MLP:
+    """Warm-start network on the device (bf16 matrix-core products, fp32
+    master weights, Adam); thin wrapper of the iblb_mlp_* calls."""
+
+    def __init__(self, widths, max_batch, device="cuda", stream=None):
+        import torch
+        self._torch = torch
+        lib = _lib.load()
+        self.lib = lib
+        self.widths = list(widths)
+        self.max_batch = int(max_batch)
+        W = (ctypes.c_int * len(widths))(*widths)
+        self._W = W
+        n = lib.iblb_mlp_workspace_bytes(len(widths) - 1, W, self.max_batch)
+        if n == 0:
+            raise IblbError(-1, "bad network shape")
+        self.device = torch.device(device)
+        self.ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        h = ctypes.c_void_p()
+        _lib.check_mlp(lib.iblb_mlp_create(len(widths) - 1, W, self.max_batch,
+                                           ctypes.c_void_p(self.ws.data_ptr()), n,
+                                           ctypes.c_void_p(self.stream.cuda_stream),
+                                           ctypes.byref(h)))
+        self.h = h
+        self.P = lib.iblb_mlp_param_count(h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.iblb_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a):
+        t = self._torch.as_tensor(np.asarray(a) if not self._torch.is_tensor(a) else a)
+        return t.to(device=self.device, dtype=self._torch.float32).contiguous()
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.P
+        _lib.check_mlp(self.lib.iblb_mlp_set_params(self.h, p.ctypes.data_as(ctypes.c_void_p)), self.h)
+
+    def get_params(self):
+        p = np.zeros(self.P, dtype=np.float32)
+        _lib.check_mlp(self.lib.iblb_mlp_get_params(self.h, p.ctypes.data_as(ctypes.c_void_p)), self.h)
+        return p
+
+    def forward(self, x):
+        x = self._dev(x)
+        y = self._torch.empty((x.shape[0], self.widths[-1]), dtype=self._torch.float32,
+                              device=self.device)
+        _lib.check_mlp(self.lib.iblb_mlp_forward(self.h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                                 ctypes.c_void_p(y.data_ptr())), self.h)
+        self.stream.synchronize()
+        return y
+
+    def gradients(self, x, t, want_grads=True):
+        x, t = self._dev(x), self._dev(t)
+        g = np.zeros(self.P, dtype=np.float32) if want_grads else None
+        loss = ctypes.c_double()
+        _lib.check_mlp(self.lib.iblb_mlp_gradients(
+            self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()), x.shape[0],
+            None if g is None else g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss)), self.h)
+        return loss.value, g
+
+    def train_step(self, x, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        loss, _ = self.gradients(x, t, want_grads=False)
+        _lib.check_mlp(self.lib.iblb_mlp_adam_step(self.h, lr, beta1, beta2, eps), self.h)
+        return loss

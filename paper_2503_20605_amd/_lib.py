@@ -32,6 +32,9 @@ EXPORTED = (
     "iblb_read_nodes", "iblb_diagnostics", "iblb_set_lb_variant", "iblb_autotune",
     "iblb_set_graph_steps", "iblb_set_active", "iblb_set_timing", "iblb_last_timing",
     "iblb_probe_copy", "iblb_run_to_rest",
+    "iblb_mlp_workspace_bytes", "iblb_mlp_create", "iblb_mlp_destroy", "iblb_mlp_last_error",
+    "iblb_mlp_param_count", "iblb_mlp_set_params", "iblb_mlp_get_params", "iblb_mlp_forward",
+    "iblb_mlp_gradients", "iblb_mlp_adam_step",
 )
 
 
@@ -105,8 +108,23 @@ def load() -> ctypes.CDLL:
     lib.iblb_set_active.argtypes = [c_void_p, c_int, c_int]
     lib.iblb_set_timing.argtypes = [c_void_p, c_int]
     lib.iblb_last_timing.argtypes = [c_void_p, P(c_double), P(c_double)]
+    lib.iblb_mlp_workspace_bytes.argtypes = [c_int, ip, c_int]
+    lib.iblb_mlp_workspace_bytes.restype = c_size_t
+    lib.iblb_mlp_create.argtypes = [c_int, ip, c_int, c_void_p, c_size_t, c_void_p, P(c_void_p)]
+    lib.iblb_mlp_destroy.argtypes = [c_void_p]
+    lib.iblb_mlp_last_error.argtypes = [c_void_p]
+    lib.iblb_mlp_last_error.restype = ctypes.c_char_p
+    lib.iblb_mlp_param_count.argtypes = [c_void_p]
+    lib.iblb_mlp_param_count.restype = ctypes.c_longlong
+    lib.iblb_mlp_set_params.argtypes = [c_void_p, c_void_p]
+    lib.iblb_mlp_get_params.argtypes = [c_void_p, c_void_p]
+    lib.iblb_mlp_forward.argtypes = [c_void_p, c_void_p, c_int, c_void_p]
+    lib.iblb_mlp_gradients.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_void_p, P(c_double)]
+    lib.iblb_mlp_adam_step.argtypes = [c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                       ctypes.c_float]
     for name in EXPORTED:
-        if name not in ("iblb_workspace_bytes", "iblb_last_error"):
+        if name not in ("iblb_workspace_bytes", "iblb_last_error", "iblb_mlp_workspace_bytes",
+                        "iblb_mlp_last_error", "iblb_mlp_param_count"):
             getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -121,5 +139,12 @@ class IblbError(RuntimeError):
 def check(code, ctx=None):
     if code != IBLB_OK:
         msg = load().iblb_last_error(ctx)
+        raise IblbError(code, msg.decode() if msg else "")
+    return code
+
+
+def check_mlp(code, mlp=None):
+    if code != IBLB_OK:
+        msg = load().iblb_mlp_last_error(mlp)
         raise IblbError(code, msg.decode() if msg else "")
     return code

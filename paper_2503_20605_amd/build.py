@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "iblb.hip")
+SRCS = [os.path.join(HERE, "csrc", "iblb.hip"), os.path.join(HERE, "csrc", "mlp.hip")]
 LIB = os.path.join(HERE, "libiblb.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -20,7 +20,7 @@ FLAGS = [
 def build(verbose: bool = False, extra=None) -> str:
     cmd = [HIPCC] + FLAGS + (extra or []) + [
         "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-        "-o", LIB, SRC]
+        "-o", LIB] + SRCS
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1,0 +1,284 @@
+// Host runtime and C ABI of the warm-start network (see iblb.h): a fully
+// connected network widths[0] -> ... -> widths[L] with GELU after every
+// layer but the last, bf16 operands on the matrix cores, fp32 master
+// weights, MSE loss, Adam.  All device memory comes from the caller's
+// workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#pragma GCC visibility push(default)
+#include "iblb.h"
+#pragma GCC visibility pop
+#include "mlp.hpp"
+
+using namespace iblb;
+
+namespace {
+
+constexpr size_t kMlpAlign = 256;
+size_t mlp_align(size_t v) { return (v + kMlpAlign - 1) / kMlpAlign * kMlpAlign; }
+long long mlp_cdiv(long long a, long long b) { return (a + b - 1) / b; }
+
+struct MlpLayout {
+    int L = 0, B = 0, maxw = 0;
+    std::vector<int> w;
+    std::vector<long long> woff, boff;  // offsets in the packed parameter vector
+    long long P = 0;
+    size_t master, grad, m, v, wb, xb, partial, dHf, dZf, dZb, total;
+    std::vector<size_t> Z, H;  // Z[l]: layer l output (fp32); H[l]: layer l input (bf16)
+};
+
+bool mlp_plan(int L, const int* widths, int B, MlpLayout& Y, std::string& err) {
+    if (L < 1 || L > 16 || !widths) { err = "n_layers must be 1..16 with widths given"; return false; }
+    if (B < 1) { err = "max_batch must be >= 1"; return false; }
+    Y.L = L;
+    Y.B = B;
+    Y.w.assign(widths, widths + L + 1);
+    Y.maxw = 0;
+    for (int x : Y.w) {
+        if (x < 1 || x > 65536) { err = "layer widths must be 1..65536"; return false; }
+        Y.maxw = std::max(Y.maxw, x);
+    }
+    Y.woff.resize(L);
+    Y.boff.resize(L);
+    Y.P = 0;
+    for (int l = 0; l < L; ++l) {
+        Y.woff[l] = Y.P;
+        Y.P += (long long)Y.w[l] * Y.w[l + 1];
+        Y.boff[l] = Y.P;
+        Y.P += Y.w[l + 1];
+    }
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = mlp_align(o + bytes); return at; };
+    Y.master = take(4 * Y.P);
+    Y.grad = take(4 * Y.P);
+    Y.m = take(4 * Y.P);
+    Y.v = take(4 * Y.P);
+    Y.wb = take(2 * Y.P);
+    Y.Z.resize(L);
+    Y.H.resize(L);
+    for (int l = 0; l < L; ++l) {
+        Y.Z[l] = take(4ull * B * Y.w[l + 1]);
+        Y.H[l] = take(2ull * B * Y.w[l]);
+    }
+    Y.xb = Y.H[0];
+    Y.dHf = take(4ull * B * Y.maxw);
+    Y.dZf = take(4ull * B * Y.maxw);
+    Y.dZb = take(2ull * B * Y.maxw);
+    Y.partial = take(8ull * mlp_cdiv((long long)B * Y.w[L], kMlpBlock));
+    Y.total = o;
+    return true;
+}
+
+}  // namespace
+
+struct iblb_mlp {
+    MlpLayout Y;
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    long long t = 0;       // Adam steps taken
+    int last_batch = 0;    // batch of the last gradient evaluation
+    std::string err;
+    template <typename T>
+    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+thread_local std::string g_mlp_err;
+
+int mlp_fail(iblb_mlp* c, int code, const std::string& msg) {
+    if (c) c->err = msg; else g_mlp_err = msg;
+    return code;
+}
+
+#define MLPCHK(ctx, call)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return mlp_fail(ctx, IBLB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void gemm(const iblb_mlp* c, const uint16_t* A, long long sai, long long sak, const uint16_t* B,
+          long long sbk, long long sbj, float* Cf, uint16_t* Hb, long long ldc, const float* bias,
+          int M, int N, int K, int act) {
+    const dim3 grid((unsigned)mlp_cdiv(N, 64), (unsigned)mlp_cdiv(M, 64)), block(kMlpBlock);
+    hipLaunchKernelGGL(k_gemm_bf16, grid, block, 0, c->stream, A, sai, sak, B, sbk, sbj, Cf, Hb, ldc,
+                       bias, M, N, K, act);
+}
+
+// forward pass of `batch` rows from device fp32 input x
+int mlp_forward(iblb_mlp* c, const float* d_x, int batch) {
+    const MlpLayout& Y = c->Y;
+    const long long nx = (long long)batch * Y.w[0];
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)mlp_cdiv(nx, kMlpBlock)), dim3(kMlpBlock), 0, c->stream,
+                       d_x, c->at<uint16_t>(Y.xb), nx);
+    for (int l = 0; l < Y.L; ++l) {
+        const int in = Y.w[l], out = Y.w[l + 1];
+        const bool act = l < Y.L - 1;
+        gemm(c, c->at<uint16_t>(Y.H[l]), in, 1, c->at<uint16_t>(Y.wb) + Y.woff[l], out, 1,
+             c->at<float>(Y.Z[l]), act ? c->at<uint16_t>(Y.H[l + 1]) : nullptr, out,
+             c->at<float>(Y.master) + Y.boff[l], batch, out, in, act ? 1 : 0);
+    }
+    MLPCHK(c, hipGetLastError());
+    return IBLB_OK;
+}
+
+int check_batch(iblb_mlp* c, int batch) {
+    if (!c) return IBLB_EINVAL;
+    if (batch < 1 || batch > c->Y.B) return mlp_fail(c, IBLB_EINVAL, "batch must be 1..max_batch");
+    return IBLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t iblb_mlp_workspace_bytes(int n_layers, const int* widths, int max_batch) {
+    MlpLayout Y;
+    std::string err;
+    return mlp_plan(n_layers, widths, max_batch, Y, err) ? Y.total : 0;
+}
+
+int iblb_mlp_create(int n_layers, const int* widths, int max_batch, void* d_ws, size_t ws_bytes,
+                    void* stream, iblb_mlp** out) {
+    if (!out) return mlp_fail(nullptr, IBLB_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    MlpLayout Y;
+    std::string err;
+    if (!mlp_plan(n_layers, widths, max_batch, Y, err)) return mlp_fail(nullptr, IBLB_EINVAL, err);
+    if (!d_ws || reinterpret_cast<uintptr_t>(d_ws) % kMlpAlign)
+        return mlp_fail(nullptr, IBLB_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    if (ws_bytes < Y.total) return mlp_fail(nullptr, IBLB_ENOMEM, "workspace too small");
+    iblb_mlp* c = new iblb_mlp();
+    c->Y = Y;
+    c->ws = static_cast<char*>(d_ws);
+    c->stream = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemsetAsync(c->ws, 0, Y.total, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        g_mlp_err = std::string("hipMemsetAsync: ") + hipGetErrorString(e);
+        delete c;
+        return IBLB_EDEVICE;
+    }
+    *out = c;
+    return IBLB_OK;
+}
+
+int iblb_mlp_destroy(iblb_mlp* c) {
+    delete c;
+    return IBLB_OK;
+}
+
+const char* iblb_mlp_last_error(const iblb_mlp* c) { return c ? c->err.c_str() : g_mlp_err.c_str(); }
+
+long long iblb_mlp_param_count(const iblb_mlp* c) { return c ? c->Y.P : 0; }
+
+int iblb_mlp_set_params(iblb_mlp* c, const float* h_params) {
+    if (!c) return IBLB_EINVAL;
+    if (!h_params) return mlp_fail(c, IBLB_EINVAL, "NULL parameters");
+    const MlpLayout& Y = c->Y;
+    std::vector<float> tmp(h_params, h_params + Y.P);
+    MLPCHK(c, hipMemcpyAsync(c->at<float>(Y.master), tmp.data(), 4 * Y.P, hipMemcpyHostToDevice, c->stream));
+    MLPCHK(c, hipMemsetAsync(c->at<float>(Y.m), 0, 4 * Y.P, c->stream));
+    MLPCHK(c, hipMemsetAsync(c->at<float>(Y.v), 0, 4 * Y.P, c->stream));
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)mlp_cdiv(Y.P, kMlpBlock)), dim3(kMlpBlock), 0, c->stream,
+                       (const float*)c->at<float>(Y.master), c->at<uint16_t>(Y.wb), Y.P);
+    MLPCHK(c, hipGetLastError());
+    MLPCHK(c, hipStreamSynchronize(c->stream));
+    c->t = 0;
+    return IBLB_OK;
+}
+
+int iblb_mlp_get_params(iblb_mlp* c, float* h_params) {
+    if (!c) return IBLB_EINVAL;
+    if (!h_params) return mlp_fail(c, IBLB_EINVAL, "NULL parameters");
+    MLPCHK(c, hipMemcpyAsync(h_params, c->at<float>(c->Y.master), 4 * c->Y.P, hipMemcpyDeviceToHost,
+                             c->stream));
+    MLPCHK(c, hipStreamSynchronize(c->stream));
+    return IBLB_OK;
+}
+
+int iblb_mlp_forward(iblb_mlp* c, const float* d_x, int batch, float* d_y) {
+    int rc = check_batch(c, batch);
+    if (rc) return rc;
+    if (!d_x || !d_y) return mlp_fail(c, IBLB_EINVAL, "NULL input or output");
+    if ((rc = mlp_forward(c, d_x, batch))) return rc;
+    const MlpLayout& Y = c->Y;
+    MLPCHK(c, hipMemcpyAsync(d_y, c->at<float>(Y.Z[Y.L - 1]), 4ull * batch * Y.w[Y.L],
+                             hipMemcpyDeviceToDevice, c->stream));
+    return IBLB_OK;
+}
+
+int iblb_mlp_gradients(iblb_mlp* c, const float* d_x, const float* d_t, int batch, float* h_grads,
+                       double* loss) {
+    int rc = check_batch(c, batch);
+    if (rc) return rc;
+    if (!d_x || !d_t) return mlp_fail(c, IBLB_EINVAL, "NULL input or target");
+    if ((rc = mlp_forward(c, d_x, batch))) return rc;
+    const MlpLayout& Y = c->Y;
+    const int L = Y.L;
+    const long long ny = (long long)batch * Y.w[L];
+    const int nblk = (int)mlp_cdiv(ny, kMlpBlock);
+    float* dZf = c->at<float>(Y.dZf);
+    uint16_t* dZb = c->at<uint16_t>(Y.dZb);
+    float* dHf = c->at<float>(Y.dHf);
+    float* grad = c->at<float>(Y.grad);
+    hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(kMlpBlock), 0, c->stream, (const float*)c->at<float>(Y.Z[L - 1]),
+                       d_t, dZf, dZb, c->at<double>(Y.partial), ny);
+    for (int l = L - 1; l >= 0; --l) {
+        const int in = Y.w[l], out = Y.w[l + 1];
+        // bias: column sums of dZ; weights: H^T dZ; input: dZ W^T
+        hipLaunchKernelGGL(k_colsum, dim3((unsigned)mlp_cdiv(out, kMlpBlock)), dim3(kMlpBlock), 0, c->stream,
+                           (const float*)dZf, grad + Y.boff[l], batch, out);
+        gemm(c, c->at<uint16_t>(Y.H[l]), 1, in, dZb, out, 1, grad + Y.woff[l], nullptr, out, nullptr, in,
+             out, batch, 0);
+        if (l > 0) {
+            gemm(c, dZb, out, 1, c->at<uint16_t>(Y.wb) + Y.woff[l], 1, out, dHf, nullptr, in, nullptr,
+                 batch, in, out, 0);
+            const long long nh = (long long)batch * in;
+            hipLaunchKernelGGL(k_gelu_back, dim3((unsigned)mlp_cdiv(nh, kMlpBlock)), dim3(kMlpBlock), 0,
+                               c->stream, (const float*)dHf, (const float*)c->at<float>(Y.Z[l - 1]), dZf,
+                               dZb, nh);
+        }
+    }
+    MLPCHK(c, hipGetLastError());
+    c->last_batch = batch;
+    if (loss) {
+        std::vector<double> part(nblk);
+        MLPCHK(c, hipMemcpyAsync(part.data(), c->at<double>(Y.partial), 8ull * nblk, hipMemcpyDeviceToHost,
+                                 c->stream));
+        MLPCHK(c, hipStreamSynchronize(c->stream));
+        double s = 0.0;
+        for (double x : part) s += x;
+        *loss = s / (double)ny;
+    }
+    if (h_grads) {
+        MLPCHK(c, hipMemcpyAsync(h_grads, grad, 4 * Y.P, hipMemcpyDeviceToHost, c->stream));
+        MLPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return IBLB_OK;
+}
+
+int iblb_mlp_adam_step(iblb_mlp* c, float lr, float beta1, float beta2, float eps) {
+    if (!c) return IBLB_EINVAL;
+    if (c->last_batch == 0) return mlp_fail(c, IBLB_EINVAL, "no gradients yet");
+    if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return mlp_fail(c, IBLB_EINVAL, "bad Adam hyper-parameters");
+    const MlpLayout& Y = c->Y;
+    c->t += 1;
+    const float bc1 = 1.f - powf(beta1, (float)c->t), bc2 = 1.f - powf(beta2, (float)c->t);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)mlp_cdiv(Y.P, kMlpBlock)), dim3(kMlpBlock), 0, c->stream,
+                       c->at<float>(Y.master), c->at<uint16_t>(Y.wb), (const float*)c->at<float>(Y.grad),
+                       c->at<float>(Y.m), c->at<float>(Y.v), Y.P, lr, beta1, beta2, eps, bc1, bc2);
+    MLPCHK(c, hipGetLastError());
+    return IBLB_OK;
+}
+
+}  // extern "C"

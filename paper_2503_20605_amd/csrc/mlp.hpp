@@ -1,0 +1,145 @@
+// gfx950 kernels of the learned warm start: a small fully connected network
+// trained and evaluated with bf16 operands on the matrix cores (fp32
+// accumulation), fp32 master weights, Adam.
+//
+//   k_gemm_bf16     C = A B with A, B bf16 in any strides, fp32 result, one
+//                   32x32 tile per wavefront through v_mfma_f32_32x32x8_bf16;
+//                   epilogue: + bias, optional GELU (keeps the fp32
+//                   pre-activation and writes the bf16 activation)
+//   k_gelu_back     dZ = dH * GELU'(Z), bf16 copy for the next products
+//   k_colsum        bias gradient (column sums of dZ)
+//   k_mse           loss and dY = 2 (Y - T) / (B n)
+//   k_adam          Adam update of the fp32 master weights + bf16 copy
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "lattice.hpp"
+
+namespace iblb {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kMlpBlock = 256;  // 4 wavefronts, a 64x64 tile of C
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float z) {
+    const float cdf = 0.5f * (1.f + erff(z * 0.70710678118654752f));
+    const float pdf = 0.39894228040143268f * expf(-0.5f * z * z);
+    return cdf + z * pdf;
+}
+
+// C(i, j) = sum_k A(i, k) B(k, j) (+ bias[j]); A(i, k) = A[i * sai + k * sak],
+// B(k, j) = B[k * sbk + j * sbj].  act = 0: C fp32 to Cf[i * ldc + j];
+// act = 1: Cf gets the pre-activation and Hb[i * ldc + j] the bf16 GELU.
+// Operands outside M x N x K read as zero.
+//
+// Operand and result layout of one 32x32x8 product (lane l of 64):
+//   A: row l % 32, k = 4 (l / 32) + 0..3;  B: column l % 32, same k;
+//   result register r: row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
+__global__ __launch_bounds__(kMlpBlock) void k_gemm_bf16(
+    const uint16_t* __restrict__ A, long long sai, long long sak, const uint16_t* __restrict__ B,
+    long long sbk, long long sbj, float* __restrict__ Cf, uint16_t* __restrict__ Hb, long long ldc,
+    const float* __restrict__ bias, int M, int N, int K, int act) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i0 = blockIdx.y * 64 + (wave >> 1) * 32;
+    const int j0 = blockIdx.x * 64 + (wave & 1) * 32;
+    const int ra = i0 + (lane & 31);     // row of A this lane feeds
+    const int cb = j0 + (lane & 31);     // column of B this lane feeds
+    const int kq = (lane >> 5) * 4;
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    for (int k0 = 0; k0 < K; k0 += 8) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + kq + u;
+            a[u] = (ra < M && k < K) ? (short)A[ra * sai + k * sak] : (short)0;
+            b[u] = (cb < N && k < K) ? (short)B[k * sbk + cb * sbj] : (short)0;
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    const int j = j0 + (lane & 31);
+    if (j >= N) return;
+    const float bj = bias ? bias[j] : 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = i0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (i >= M) continue;
+        const float z = acc[r] + bj;
+        Cf[i * ldc + j] = z;
+        if (act) Hb[i * ldc + j] = f32_to_bf16_rne(gelu(z));
+    }
+}
+
+// dZ = dH * GELU'(Z) (fp32 and bf16 copies), n elements
+__global__ void k_gelu_back(const float* __restrict__ dH, const float* __restrict__ Z,
+                            float* __restrict__ dZf, uint16_t* __restrict__ dZb, long long n) {
+    const long long i = (long long)blockIdx.x * kMlpBlock + threadIdx.x;
+    if (i >= n) return;
+    const float g = dH[i] * gelu_grad(Z[i]);
+    dZf[i] = g;
+    dZb[i] = f32_to_bf16_rne(g);
+}
+
+// out[j] = sum_i X[i * N + j], one thread per column (columns are few)
+__global__ void k_colsum(const float* __restrict__ X, float* __restrict__ out, int M, int N) {
+    const int j = blockIdx.x * kMlpBlock + threadIdx.x;
+    if (j >= N) return;
+    float s = 0.f;
+    for (int i = 0; i < M; ++i) s += X[(long long)i * N + j];
+    out[j] = s;
+}
+
+// dY = 2 (Y - T) / n (fp32 and bf16), per-block partial sums of (Y - T)^2
+__global__ void k_mse(const float* __restrict__ Y, const float* __restrict__ T,
+                      float* __restrict__ dYf, uint16_t* __restrict__ dYb,
+                      double* __restrict__ partial, long long n) {
+    __shared__ double sh[kMlpBlock];
+    const long long i = (long long)blockIdx.x * kMlpBlock + threadIdx.x;
+    double e2 = 0.0;
+    if (i < n) {
+        const float e = Y[i] - T[i];
+        const float g = 2.f * e / (float)n;
+        dYf[i] = g;
+        dYb[i] = f32_to_bf16_rne(g);
+        e2 = (double)e * e;
+    }
+    sh[threadIdx.x] = e2;
+    __syncthreads();
+    for (int o = kMlpBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// Adam (Kingma & Ba) on the fp32 master copy; bc1 = 1 - beta1^t,
+// bc2 = 1 - beta2^t.  Writes the bf16 copy used by the products.
+__global__ void k_adam(float* __restrict__ w, uint16_t* __restrict__ wb, const float* __restrict__ g,
+                       float* __restrict__ m, float* __restrict__ v, long long n, float lr,
+                       float beta1, float beta2, float eps, float bc1, float bc2) {
+    const long long i = (long long)blockIdx.x * kMlpBlock + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = beta1 * m[i] + (1.f - beta1) * gi;
+    const float vi = beta2 * v[i] + (1.f - beta2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    w[i] = wi;
+    wb[i] = f32_to_bf16_rne(wi);
+}
+
+// fp32 -> bf16 (nearest even), n elements
+__global__ void k_to_bf16(const float* __restrict__ x, uint16_t* __restrict__ y, long long n) {
+    const long long i = (long long)blockIdx.x * kMlpBlock + threadIdx.x;
+    if (i < n) y[i] = f32_to_bf16_rne(x[i]);
+}
+
+}  // namespace iblb

@@ -7,7 +7,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
-SRC = os.path.join(ROOT, "paper_2503_20605_amd", "csrc", "iblb.hip")
+SRCS = [os.path.join(ROOT, "paper_2503_20605_amd", "csrc", f) for f in ("iblb.hip", "mlp.hip")]
 OUT = os.path.join(HERE, "iblb_emu_driver")
 CXX = "/opt/rocm/llvm/bin/clang++"
 
@@ -27,7 +27,7 @@ def build(force=False, verbose=False):
            "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
            "-I", os.path.join(HERE, "include"), "-I", os.path.join(ROOT, "include"),
            "-I", os.path.join(ROOT, "paper_2503_20605_amd", "csrc"),
-           "-x", "c++", SRC, "-x", "c++", os.path.join(HERE, "driver.cpp"), "-o", OUT]
+           "-x", "c++"] + SRCS + [os.path.join(HERE, "driver.cpp"), "-o", OUT]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -52,6 +52,53 @@ static T* buf(size_t count) {
     return static_cast<T*>(p);
 }
 
+// Network mode: config "mlp 1", "widths a,b,...", "batch B", "lr x";
+// files x.bin [B][w0] f32, t.bin [B][wL] f32, params.bin [P] f32.  Writes
+// y.bin, grads.bin, loss.txt and params_after.bin (after one Adam step).
+static int run_mlp(std::map<std::string, std::string>& cfg) {
+    std::vector<int> w;
+    {
+        std::stringstream ss(cfg["widths"]);
+        std::string tok;
+        while (std::getline(ss, tok, ',')) w.push_back(atoi(tok.c_str()));
+    }
+    const int L = (int)w.size() - 1, B = atoi(cfg["batch"].c_str());
+    const float lr = (float)atof(cfg["lr"].c_str());
+    size_t ws = iblb_mlp_workspace_bytes(L, w.data(), B);
+    if (!ws) return 20;
+    char* wsp = buf<char>(ws);
+    iblb_mlp* m = nullptr;
+    if (iblb_mlp_create(L, w.data(), B, wsp, ws, nullptr, &m)) return 21;
+    const long long P = iblb_mlp_param_count(m);
+    auto prm = load<float>("params.bin", P);
+    auto x = load<float>("x.bin", (size_t)B * w[0]);
+    auto t = load<float>("t.bin", (size_t)B * w[L]);
+    float* xb = buf<float>(x.size());
+    float* tb = buf<float>(t.size());
+    float* yb = buf<float>((size_t)B * w[L]);
+    float* gb = buf<float>(P);
+    float* pb = buf<float>(P);
+    memcpy(xb, x.data(), 4 * x.size());
+    memcpy(tb, t.data(), 4 * t.size());
+    memcpy(pb, prm.data(), 4 * P);
+    double loss = 0;
+    if (iblb_mlp_set_params(m, pb) || iblb_mlp_forward(m, xb, B, yb) ||
+        iblb_mlp_gradients(m, xb, tb, B, gb, &loss) || iblb_mlp_adam_step(m, lr, 0.9f, 0.999f, 1e-8f) ||
+        iblb_mlp_get_params(m, pb)) {
+        fprintf(stderr, "mlp: %s\n", iblb_mlp_last_error(m));
+        return 22;
+    }
+    save("y.bin", yb, (size_t)B * w[L]);
+    save("grads.bin", gb, P);
+    save("params_after.bin", pb, P);
+    FILE* f = fopen((dir + "/loss.txt").c_str(), "w");
+    fprintf(f, "%.17g\n", loss);
+    fclose(f);
+    iblb_mlp_destroy(m);
+    free(xb); free(tb); free(yb); free(gb); free(pb); free(wsp);
+    return 0;
+}
+
 int main(int argc, char** argv) {
     if (argc < 2) return 2;
     dir = argv[1];
@@ -61,6 +108,7 @@ int main(int argc, char** argv) {
         std::string k, v;
         while (in >> k >> v) cfg[k] = v;
     }
+    if (cfg.count("mlp")) return run_mlp(cfg);
     auto geti = [&](const std::string& k, int def) { return cfg.count(k) ? atoi(cfg[k].c_str()) : def; };
     const int n = geti("n", 1), storage = geti("storage", 0);
     std::vector<iblb_params> P = load<iblb_params>("params.bin", n);

@@ -73,14 +73,15 @@ struct Stream { int id; };
 struct Graph { std::vector<std::function<void()>> ops; };
 struct Event { int id; };
 
-enum State { READY, AT_WAVE_FIRST, AT_WAVE_XOR, AT_BLOCK, DONE };
+enum State { READY, AT_WAVE_FIRST, AT_WAVE_XOR, AT_WAVE_MFMA, AT_BLOCK, DONE };
 
 struct Fiber {
     ucontext_t ctx;
     char* stack = nullptr;
     int tid = 0;
     State st = READY;
-    uint64_t in = 0, out = 0;
+    uint64_t in = 0, out = 0, in2 = 0;
+    float acc[16];
     int mask = 0;
     void* asan_fake = nullptr;
 };
@@ -107,6 +108,7 @@ inline dim3 block_dim() { return rt().block; }
 inline dim3 grid_dim() { return rt().grid; }
 
 uint64_t wave_op(State kind, uint64_t v, int mask);
+void wave_mfma(uint64_t a, uint64_t b, float acc[16]);
 void block_barrier();
 void run_grid(dim3 g, dim3 b, const std::function<void()>& fn);
 
@@ -182,6 +184,24 @@ inline unsigned long long atomicMax(unsigned long long* p, unsigned long long v)
     unsigned long long old = *p;
     if (v > old) *p = v;
     return old;
+}
+
+// v_mfma_f32_32x32x8_bf16: every lane of the wavefront supplies four bf16
+// of A (row l % 32, k = 4 (l / 32) + u) and of B (column l % 32, same k);
+// lane l's result register r holds row 8 (r / 4) + 4 (l / 32) + r % 4,
+// column l % 32.
+template <typename V4, typename V16>
+inline V16 __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(V4 a, V4 b, V16 c, int, int, int) {
+    uint64_t pa = 0, pb = 0;
+    for (int u = 0; u < 4; ++u) {
+        pa |= (uint64_t)(uint16_t)a[u] << (16 * u);
+        pb |= (uint64_t)(uint16_t)b[u] << (16 * u);
+    }
+    float acc[16];
+    for (int r = 0; r < 16; ++r) acc[r] = c[r];
+    ::hipemu::wave_mfma(pa, pb, acc);
+    for (int r = 0; r < 16; ++r) c[r] = acc[r];
+    return c;
 }
 
 inline float unsafeAtomicAdd(float* p, float v) {
@@ -354,6 +374,16 @@ inline uint64_t wave_op(State kind, uint64_t v, int mask) {
     return f->out;
 }
 
+inline void wave_mfma(uint64_t a, uint64_t b, float acc[16]) {
+    Fiber* f = rt().cur;
+    f->st = AT_WAVE_MFMA;
+    f->in = a;
+    f->in2 = b;
+    for (int r = 0; r < 16; ++r) f->acc[r] = acc[r];
+    yield_to_sched(false);
+    for (int r = 0; r < 16; ++r) acc[r] = f->acc[r];
+}
+
 inline void block_barrier() {
     Fiber* f = rt().cur;
     f->st = AT_BLOCK;
@@ -409,9 +439,38 @@ inline void run_block(const std::function<void()>& fn) {
                 ++live;
                 if (first < 0) { first = t; kind = s; }
                 same &= s == kind;
-                kindc += (s == AT_WAVE_FIRST || s == AT_WAVE_XOR);
+                kindc += (s == AT_WAVE_FIRST || s == AT_WAVE_XOR || s == AT_WAVE_MFMA);
             }
-            if (!live || !same || (kind != AT_WAVE_FIRST && kind != AT_WAVE_XOR)) continue;
+            if (!live || !same || (kind != AT_WAVE_FIRST && kind != AT_WAVE_XOR && kind != AT_WAVE_MFMA))
+                continue;
+            if (kind == AT_WAVE_MFMA) {
+                if (live != 64) {
+                    fprintf(stderr, "hipemu: MFMA with inactive lanes\n");
+                    abort();
+                }
+                auto bf = [](uint64_t p, int u) {
+                    const uint32_t h = (uint32_t)((p >> (16 * u)) & 0xffffu) << 16;
+                    float x;
+                    memcpy(&x, &h, 4);
+                    return x;
+                };
+                float Am[32][8], Bm[8][32];
+                for (int l = 0; l < 64; ++l)
+                    for (int u = 0; u < 4; ++u) {
+                        Am[l % 32][4 * (l / 32) + u] = bf(r.fibers[lo + l].in, u);
+                        Bm[4 * (l / 32) + u][l % 32] = bf(r.fibers[lo + l].in2, u);
+                    }
+                for (int l = 0; l < 64; ++l)
+                    for (int q = 0; q < 16; ++q) {
+                        const int row = 8 * (q / 4) + 4 * (l / 32) + q % 4, col = l % 32;
+                        float s = 0.f;
+                        for (int k = 0; k < 8; ++k) s += Am[row][k] * Bm[k][col];
+                        r.fibers[lo + l].acc[q] += s;
+                    }
+                for (int t = lo; t < hi; ++t) r.fibers[t].st = READY;
+                resolved = true;
+                continue;
+            }
             for (int t = lo; t < hi; ++t) {
                 Fiber& f = r.fibers[t];
                 if (f.st == DONE) continue;

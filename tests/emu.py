@@ -101,3 +101,28 @@ def run_case(params_list, nodes_list=None, tris_list=None, steps=(1,), storage=0
                 o["rest_steps"] = int(rest_steps[k])
             outs.append(o)
         return outs
+
+
+def run_mlp(widths, params, x, t, lr=1e-3, timeout=600):
+    """One forward, one gradient evaluation and one Adam step of the network
+    kernels in the sanitizer build.  Returns (y, grads, loss, params_after)."""
+    import build as emu_build
+    exe = emu_build.build()
+    with tempfile.TemporaryDirectory() as d:
+        B = x.shape[0]
+        open(os.path.join(d, "config.txt"), "w").write(
+            f"mlp 1\nwidths {','.join(str(w) for w in widths)}\nbatch {B}\nlr {lr}\n")
+        np.ascontiguousarray(params, dtype=np.float32).tofile(os.path.join(d, "params.bin"))
+        np.ascontiguousarray(x, dtype=np.float32).tofile(os.path.join(d, "x.bin"))
+        np.ascontiguousarray(t, dtype=np.float32).tofile(os.path.join(d, "t.bin"))
+        env = dict(os.environ)
+        env["ASAN_OPTIONS"] = "detect_leaks=0:halt_on_error=1"
+        env["UBSAN_OPTIONS"] = "print_stacktrace=1:halt_on_error=1"
+        r = subprocess.run([exe, d], capture_output=True, text=True, timeout=timeout, env=env)
+        if r.returncode != 0:
+            raise RuntimeError(f"emulated network run failed (rc={r.returncode}):\n{r.stderr[-6000:]}")
+        y = np.fromfile(os.path.join(d, "y.bin"), dtype=np.float32).reshape(B, widths[-1])
+        g = np.fromfile(os.path.join(d, "grads.bin"), dtype=np.float32)
+        pa = np.fromfile(os.path.join(d, "params_after.bin"), dtype=np.float32)
+        loss = float(open(os.path.join(d, "loss.txt")).read())
+        return y, g, loss, pa

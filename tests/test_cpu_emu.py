@@ -125,3 +125,32 @@ def test_run_to_rest_freezes_settled_droplets():
         r = o.run(ps[d], qs[d], n if n > 0 else 60)
         assert np.max(np.abs(out[d]["q"] - r["q"])) <= 1e-7
     assert out[0]["rest_steps"] > 0
+
+
+def _bf16(a):
+    """Round to bf16 (nearest even) and back, like the network's operands."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def test_network_kernels_against_reference():
+    """Ragged sizes (K = 4, widths not multiples of the 32x32 tiles, batch
+    not a multiple of 64) through forward, gradients and one Adam step."""
+    from emu import run_mlp
+    from oracle import mlp
+    widths = [4, 40, 33, 70]
+    rng = np.random.default_rng(3)
+    p = mlp.init_params(widths, 7)
+    x = rng.standard_normal((37, 4))
+    t = 0.3 * rng.standard_normal((37, 70))
+    y, g, loss, pa = run_mlp(widths, p, x, t, lr=1e-3)
+    yo, _ = mlp.forward(p, widths, x)
+    lo, go = mlp.loss_and_grad(p, widths, x, t)
+    assert np.max(np.abs(y - yo)) <= 3e-2 * np.max(np.abs(yo))
+    assert abs(loss - lo) <= 2e-2 * lo
+    cos = float(np.dot(g, go) / (np.linalg.norm(g) * np.linalg.norm(go)))
+    assert cos >= 0.999 and np.linalg.norm(g - go) <= 2e-2 * np.linalg.norm(go)
+    # one Adam step from the library's own gradient
+    ref = mlp.Adam(len(p)).step(p.astype(np.float32).astype(np.float64), g.astype(np.float64), 1e-3)
+    assert np.max(np.abs(pa - ref)) <= 1e-6
