@@ -31,6 +31,9 @@ GRID = (16, 32)           # coarse velocity grid (rows in y, columns in x)
 N_OUT = K_RAYS + 2 * GRID[0] * GRID[1]
 WIDTHS = [4, 256, 256, 256, N_OUT]
 U_SCALE = 1e4             # velocity targets are O(1e-6 .. 1e-4) lattice units
+U_WEIGHT = 0.3            # weight of the (noise-dominated) velocity outputs in the loss
+U_MAX = 1e-3              # predicted velocities are clipped to this magnitude
+H_MIN = 0.85              # predicted nodes stay at least this many xi above the wall
 PHI = 2.0 * math.pi * np.arange(K_RAYS) / K_RAYS
 
 
@@ -162,14 +165,22 @@ def generate(draws, storage=1, max_steps=100000, tol=1e-6, batch=256, log=print)
         torch.cuda.synchronize()
         log(f"[generate] droplets {b0}..{b0 + len(part) - 1}: {time.perf_counter() - t0:.1f} s, "
             f"at rest {sum(1 for x in steps if x > 0)}/{len(part)}")
+        skipped = 0
         for d, w in enumerate(part):
             if steps[d] == -2:
+                skipped += 1
                 continue
-            tgt, area = equilibrium_state(s, d, w.params)
+            try:
+                tgt, area = equilibrium_state(s, d, w.params)
+            except ValueError:      # outline not star-shaped about the reference
+                skipped += 1
+                continue
             p = w.params
             X.append(features(math.radians(p.theta_eq_deg), area, p.tau, p.sigma))
             Y.append(tgt)
             S.append(steps[d])
+        if skipped:
+            log(f"[generate] skipped {skipped} droplets (unstable or not star-shaped)")
         s.close()
     return np.array(X), np.array(Y), np.array(S)
 
@@ -185,27 +196,37 @@ def _init_params(widths, seed):
 
 
 def fit(X, Y, steps=4000, lr=1e-3, seed=7, log=print):
-    """Full-batch Adam on the device with the library's network kernels;
-    the learning rate decays linearly to 5 % over the run."""
+    """Full-batch Adam on the device with the library's network kernels.
+    Each output is standardised over the training set (targets clipped to
+    5 standard deviations; the velocity outputs scaled down by U_WEIGHT so
+    that the interface shape dominates the loss); the learning rate decays
+    linearly to 5 %.
+    Returns the network, its output scaling (mean, std) and the loss
+    history."""
     from . import MLP
+    mu = Y.mean(axis=0)
+    sd = np.maximum(Y.std(axis=0), 1e-6)
+    sd[K_RAYS:] /= U_WEIGHT    # smaller standardised velocity targets weigh less
+    Z = np.clip((Y - mu) / sd, -5.0, 5.0)
     m = MLP(WIDTHS, X.shape[0])
     m.set_params(_init_params(WIDTHS, seed))
     x = m._dev(X)
-    y = m._dev(Y)
+    z = m._dev(Z)
     hist = []
     for k in range(steps):
-        loss = m.train_step(x, y, lr * (1.0 - 0.95 * k / steps))
+        loss = m.train_step(x, z, lr * (1.0 - 0.95 * k / steps))
         if k % 500 == 0 or k == steps - 1:
             hist.append((k, loss))
             log(f"[train] step {k} loss {loss:.4e}")
-    return m, hist
+    return m, (mu, sd), hist
 
 
-def predict_starts(m, draws):
-    """Initial outlines and fluid velocity fields predicted by the network."""
+def predict_starts(m, scale, draws):
+    """Initial outlines and fluid velocity fields predicted by the network
+    (scale: the output mean and std of fit)."""
     X = np.array([features(math.radians(w.params.theta_eq_deg), polygon_area(w.nodes),
                            w.params.tau, w.params.sigma) for w in draws])
-    out = m.forward(X).cpu().numpy().astype(np.float64)
+    out = m.forward(X).cpu().numpy().astype(np.float64) * scale[1] + scale[0]
     starts = []
     for w, o in zip(draws, out):
         p = w.params
@@ -213,8 +234,8 @@ def predict_starts(m, draws):
         area = polygon_area(w.nodes)
         ref, rcap, rc = reference(theta, area, p.xi, p.nx)
         r = np.maximum(rcap + rc * o[:K_RAYS], 0.05 * rc)
-        q = outline_from_profile(ref, r, len(w.nodes), 0.5 * p.xi)
-        Uc = o[K_RAYS:].reshape(2, *GRID) / U_SCALE
+        q = outline_from_profile(ref, r, len(w.nodes), H_MIN * p.xi)
+        Uc = np.clip(o[K_RAYS:].reshape(2, *GRID) / U_SCALE, -U_MAX, U_MAX)
         starts.append((q, fine_velocity(Uc, p.ny, p.nx), rc))
     return starts
 
@@ -227,7 +248,7 @@ def cap_starts(draws):
         theta = math.radians(p.theta_eq_deg)
         area = polygon_area(w.nodes)
         ref, rcap, rc = reference(theta, area, p.xi, p.nx)
-        q = outline_from_profile(ref, rcap, len(w.nodes), 0.5 * p.xi)
+        q = outline_from_profile(ref, rcap, len(w.nodes), H_MIN * p.xi)
         starts.append((q, np.zeros((2, p.ny, p.nx)), rc))
     return starts
 
@@ -321,8 +342,9 @@ def main(argv):
     elif what == "train":
         d = np.load(os.environ.get("IBLB_WARM_DATA", os.path.join(out_dir, "train.npz")))
         t0 = time.perf_counter()
-        m, hist = fit(d["X"], d["Y"], steps=int(os.environ.get("IBLB_WARM_STEPS", "4000")), log=log)
-        np.save(os.path.join(out_dir, "params.npy"), m.get_params())
+        m, scale, hist = fit(d["X"].astype(np.float64), d["Y"].astype(np.float64),
+                             steps=int(os.environ.get("IBLB_WARM_STEPS", "8000")), log=log)
+        np.savez(os.path.join(out_dir, "net.npz"), params=m.get_params(), mu=scale[0], sd=scale[1])
         json.dump({"loss": hist, "seconds": time.perf_counter() - t0},
                   open(os.path.join(out_dir, "train.json"), "w"))
     elif what == "evaluate":
@@ -331,10 +353,12 @@ def main(argv):
         n_test = int(os.environ.get("IBLB_WARM_TEST", "512"))
         draws = wl.batch_draws(n_test, seed=6)
         m = MLP(WIDTHS, n_test)
-        m.set_params(np.load(os.path.join(out_dir, "params.npy")))
+        net = np.load(os.path.join(out_dir, "net.npz"))
+        m.set_params(net["params"])
+        scale = (net["mu"], net["sd"])
         res = {}
         arms = [("plain_f32_90deg", 0, None), ("f16_90deg", 1, None),
-                ("f16_cap_prior", 1, cap_starts(draws)), ("f16_learned", 1, predict_starts(m, draws))]
+                ("f16_cap_prior", 1, cap_starts(draws)), ("f16_learned", 1, predict_starts(m, scale, draws))]
         for name, storage, starts in arms:
             wall, steps, ang, finals = run_from(draws, starts, storage, max_steps, log=log)
             res[name] = dict(wall=wall, steps=steps, theta=ang, finals=finals, starts=starts)
@@ -359,15 +383,21 @@ def main(argv):
                     p = w.params
                     ref, _, _ = reference(math.radians(p.theta_eq_deg), polygon_area(w.nodes),
                                           p.xi, p.nx)
-                    errs.append(shape_error(r["starts"][i][0], plain["finals"][i], ref))
-                e["start_shape_error_median"] = float(np.median(errs))
+                    try:
+                        errs.append(shape_error(r["starts"][i][0], plain["finals"][i], ref))
+                    except ValueError:
+                        pass
+                e["start_shape_error_median"] = float(np.median(errs)) if errs else None
             summary[name] = e
         errs = []
         for i, w in enumerate(draws):
             p = w.params
             ref, _, _ = reference(math.radians(p.theta_eq_deg), polygon_area(w.nodes), p.xi, p.nx)
-            errs.append(shape_error(w.nodes, plain["finals"][i], ref))
-        summary["plain_f32_90deg"]["start_shape_error_median"] = float(np.median(errs))
+            try:
+                errs.append(shape_error(w.nodes, plain["finals"][i], ref))
+            except ValueError:
+                pass
+        summary["plain_f32_90deg"]["start_shape_error_median"] = float(np.median(errs)) if errs else None
         summary["speedup_learned_f16_vs_plain_f32"] = round(
             res["plain_f32_90deg"]["wall"] / res["f16_learned"]["wall"], 3)
         json.dump(summary, open(os.path.join(out_dir, "evaluate.json"), "w"), indent=1)
