@@ -27,6 +27,41 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+# lattice-kernel variants: block width along x and non-temporal stores
+LB_BX = (256, 128, 64, 256, 128, 64)
+LB_NT = (0, 0, 0, 1, 1, 1)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lb_traffic.md")
+
+
+def lb_source_hash():
+    """Hash of the lattice kernel's source (lattice.hpp and the part of
+    kernels.hpp up to the end of the lattice kernel), to tell whether stored
+    counter readings still describe the kernel as built."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2503_20605_amd", "csrc")
+    h = hashlib.sha256()
+    h.update(open(os.path.join(csrc, "lattice.hpp"), "rb").read())
+    k = open(os.path.join(csrc, "kernels.hpp"), "rb").read()
+    h.update(k[:k.index(b"// Nodes whose coordinates are not finite")])
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM-side bytes per launch of `kernel` on `workload` from the stored
+    FETCH_SIZE / WRITE_SIZE counter runs (each scaled by what the counter
+    reads for a copy of known size), or None when there is no reading for
+    this kernel and workload or the kernel's source changed since."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, ValueError, IndexError):
+        return None
+    for r in rec.get("readings", []):
+        if r["kernel"] == kernel and r["workload"] == workload and r["source_hash"] == lb_source_hash():
+            return round(r["fetch_bytes"] + r["write_bytes"])
+    return None
+
+
 def bytes_per_cell(dim, storage):
     Q = 9 if dim == 2 else 19
     return 2 * Q * (4 if storage == 0 else 2)
@@ -53,6 +88,9 @@ def parse():
     ap.add_argument("--droplets", type=int, default=256)
     ap.add_argument("--max-steps", type=int, default=200000)
     ap.add_argument("--workload", default="d2q9", choices=["d2q9", "d3q19"])
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="only the lattice kernel on an 8192x4096 D2Q9 box and the copy probe "
+                         "(short; used for hardware-counter runs)")
     return ap.parse_args()
 
 
@@ -126,15 +164,21 @@ def lb_only_rate(dim, nx, ny, nz, storage, steps):
     v, _ = s.autotune(steps=16)
     s.set_timing(True)
     s.step(steps + 1)
-    lb_ms, _ = s.last_timing()
+    span_ms, _ = s.last_timing()
+    s.set_timing(False)
+    lb_ms = s.time_lattice(min(256, 2 * (steps // 2)))
     cells = nx * ny * nz
     gbs = bytes_per_cell(dim, storage) * cells / (lb_ms * 1e-3) / 1e9
     s.close()
     return {"lattice": f"{'D2Q9' if dim == 2 else 'D3Q19'} {nx}x{ny}" + (f"x{nz}" if dim == 3 else ""),
             "storage": ["f32", "f16", "bf16"][storage], "variant": v,
             "working_set_MB": round(bytes_per_cell(dim, storage) * cells / 1e6, 1),
-            "lb_us": round(lb_ms * 1e3, 2), "MLUPS": round(cells / (lb_ms * 1e-3) / 1e6, 1),
-            "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+            "lb_us": round(lb_ms * 1e3, 2), "lb_exec_span_us": round(span_ms * 1e3, 2),
+            "MLUPS": round(cells / (lb_ms * 1e-3) / 1e6, 1),
+            "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(f"k_lb<{dim}, {storage}, {LB_BX[v]}, {LB_NT[v]}>",
+                                        f"d{dim}q{9 if dim == 2 else 19}_{nx}x{ny}"
+                                        + (f"x{nz}" if dim == 3 else "") + "_lattice_only")}
 
 
 def main():
@@ -149,6 +193,12 @@ def main():
 
     if a.tte:
         tte(a)
+        return
+    if a.hbm_probe:
+        from paper_2503_20605_amd import probe_copy_bandwidth
+        res = {"lb": lb_only_rate(2, 8192, 4096, 1, 0, 20),
+               "copy_1GiB_GBs": round(probe_copy_bandwidth(1 << 30, 5), 1)}
+        print(json.dumps(res), flush=True)
         return
     storage = STORAGE[a.storage]
     if a.workload == "d3q19":
@@ -179,16 +229,22 @@ def main():
     ms_per_step = wall / steps * 1e3
     mlups = cells * steps / wall / 1e6
 
-    # dominant kernel: the same graph-replayed steps with event nodes around
-    # every lattice launch
+    # dominant kernel, two ways: (1) execution span stamped by the kernel
+    # itself on the device clock during further coupled steps of the same
+    # schedule; (2) per-launch time with dispatch, from events around a
+    # graph of 256 back-to-back lattice launches on the same lattice (run
+    # last: it advances the populations without the node work)
     s.set_timing(True)
     nt = min(steps, 4096)
     s.step(nt + 1)
-    lb_ms, step_ms_events = s.last_timing()
+    span_ms, step_ms_timed = s.last_timing()
     s.set_timing(False)
+    diag = s.diagnostics(0)
+    lb_ms = s.time_lattice(256)
     bpc = bytes_per_cell(dim, storage)
     achieved = bpc * cells / (lb_ms * 1e-3) / 1e9
-    diag = s.diagnostics(0)
+    lb_name = f"k_lb<{dim}, {storage}, {LB_BX[variant]}, {LB_NT[variant]}>"
+    traffic = measured_traffic(lb_name, W.name)
 
     out = {
         "metric": "MLUPS (coupled IB-LB step) + HBM GB/s fraction of the lattice kernel",
@@ -209,13 +265,16 @@ def main():
                    "tau": p.tau, "theta_eq_deg": p.theta_eq_deg, "sigma": p.sigma, "xi": p.xi,
                    "storage": a.storage, "graph_steps": a.graph_steps,
                    "lb_variant": variant},
-        "roofline": {"kernel": "k_lb (fused pull-stream + BGK + Guo)", "bound": "hbm",
+        "roofline": {"kernel": lb_name + " (fused pull-stream + BGK + Guo)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
                      "bytes_per_cell": bpc, "cells_per_launch": cells,
                      "lb_us_per_launch": round(lb_ms * 1e3, 3),
+                     "lb_exec_span_us": round(span_ms * 1e3, 3),
+                     "achieved_over_exec_span": round(bpc * cells / (span_ms * 1e-3) / 1e9, 1),
                      "working_set_MB": round(bpc * cells / 1e6, 1)},
-        "step_us_timed_pass": round(step_ms_events * 1e3, 3),
+        "step_us_timed_pass": round(step_ms_timed * 1e3, 3),
         "autotune_lb_ms": tune_ms,
         "diag": {"mass": diag["mass"], "theta_meas_deg": math.degrees(diag["theta_meas"]),
                  "volume": diag["volume"]},

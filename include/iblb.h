@@ -225,11 +225,21 @@ int iblb_set_active(iblb_ctx *ctx, int droplet, int active);
  * the device's constant-rate clock; the stream is synchronised after each
  * replay to read the stamps (graphs of more than 256 steps are replaced by
  * direct launches while timing).  iblb_last_timing() gives that kernel's
- * average duration and the average time of a step (milliseconds) over the
- * last such call, the final field-storing step excluded from the kernel
- * average. */
+ * average execution span and the average time of a step (milliseconds)
+ * over the last such call, the final field-storing step excluded from the
+ * kernel average.  Either output pointer may be NULL. */
 int iblb_set_timing(iblb_ctx *ctx, int on);
 int iblb_last_timing(const iblb_ctx *ctx, double *lb_ms_per_step, double *step_ms_per_step);
+
+/* Measurement aid: replay a graph of `launches` (even, 2..1024) lattice
+ * launches back to back, no node work between them, once to warm up and
+ * once between two events on the handle's stream; *ms_per_launch receives
+ * the timed replay's elapsed time divided by `launches` (per-launch time
+ * including dispatch, the quantity a kernel-trace profiler reports).  The
+ * populations advance by 2 * launches force-free lattice steps and the
+ * nodes stay where they are, so the handle no longer holds a coupled
+ * solution afterwards. */
+int iblb_time_lattice(iblb_ctx *ctx, int launches, double *ms_per_launch);
 
 /* Measurement aid: copy `bytes` (a multiple of 16) from d_src to d_dst on
  * the device, reps + 1 times; *gbs receives the mean of the last reps

@@ -202,9 +202,19 @@ class Solver:
         self._chk(self.lib.iblb_set_timing(self.ctx, int(bool(on))))
 
     def last_timing(self):
+        """(lattice-kernel execution span, whole step), milliseconds,
+        averaged over the last timed step() call."""
         a, b = ctypes.c_double(), ctypes.c_double()
         self._chk(self.lib.iblb_last_timing(self.ctx, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def time_lattice(self, launches=256):
+        """Per-launch time (ms) of the lattice kernel replayed back to back
+        in a graph (dispatch included).  Advances the populations without
+        moving the nodes: a measurement aid, not a simulation step."""
+        out = ctypes.c_double()
+        self._chk(self.lib.iblb_time_lattice(self.ctx, int(launches), ctypes.byref(out)))
+        return out.value
 
     # -- outputs -----------------------------------------------------------
     def read_fields(self, d):

@@ -30,7 +30,7 @@ EXPORTED = (
     "iblb_set_interface", "iblb_init_rest", "iblb_write_populations",
     "iblb_read_populations", "iblb_set_force_field", "iblb_step", "iblb_read_fields",
     "iblb_read_nodes", "iblb_diagnostics", "iblb_set_lb_variant", "iblb_autotune",
-    "iblb_set_graph_steps", "iblb_set_active", "iblb_set_timing", "iblb_last_timing",
+    "iblb_set_graph_steps", "iblb_set_active", "iblb_set_timing", "iblb_last_timing", "iblb_time_lattice",
     "iblb_probe_copy", "iblb_run_to_rest",
     "iblb_mlp_workspace_bytes", "iblb_mlp_create", "iblb_mlp_destroy", "iblb_mlp_last_error",
     "iblb_mlp_param_count", "iblb_mlp_set_params", "iblb_mlp_get_params", "iblb_mlp_forward",
@@ -108,6 +108,7 @@ def load() -> ctypes.CDLL:
     lib.iblb_set_active.argtypes = [c_void_p, c_int, c_int]
     lib.iblb_set_timing.argtypes = [c_void_p, c_int]
     lib.iblb_last_timing.argtypes = [c_void_p, P(c_double), P(c_double)]
+    lib.iblb_time_lattice.argtypes = [c_void_p, c_int, P(c_double)]
     lib.iblb_mlp_workspace_bytes.argtypes = [c_int, ip, c_int]
     lib.iblb_mlp_workspace_bytes.restype = c_size_t
     lib.iblb_mlp_create.argtypes = [c_int, ip, c_int, c_void_p, c_size_t, c_void_p, P(c_void_p)]

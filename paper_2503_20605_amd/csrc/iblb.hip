@@ -40,7 +40,7 @@ int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 struct Layout {
     // byte offsets into the workspace
-    size_t drops, tiles_lb, tiles_all, f0, f1, F, U, Fout, rho, flags, pos, phi, qdot, dropped,
+    size_t drops, tiles_lb, tiles_all, f0, f1, F, U, Fout, rho, flags, pos0, pos1, phi, qdot, dropped,
         node_drop, tri, inc, inc_beg, inc_end, status, partials, diag, stamps, stamps_out, total;
     long long cells;       // sum of cells
     long long flag_bytes;  // sum of band flags
@@ -141,7 +141,8 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.Fout = take(sizeof(float) * dim * C);
     L.rho = take(sizeof(float) * C);
     L.flags = take((size_t)L.flag_bytes);
-    L.pos = take(sizeof(double) * 3 * N);
+    L.pos0 = take(sizeof(double) * 3 * N);  // positions, one buffer per step parity
+    L.pos1 = take(sizeof(double) * 3 * N);
     L.phi = take(sizeof(float) * 3 * N);
     L.qdot = take(sizeof(float) * 3 * N);
     L.dropped = take(sizeof(float) * 3 * N);
@@ -153,8 +154,8 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.status = take(sizeof(int) * n);
     L.partials = take(sizeof(double) * 8 * L.max_tiles);
     L.diag = take(sizeof(DiagDev) * n);
-    L.stamps = take(sizeof(unsigned long long) * (size_t)kStampWords * (kTimedLaunches + 1));
-    L.stamps_out = take(sizeof(unsigned long long) * 2 * (kTimedLaunches + 1));
+    L.stamps = take(sizeof(unsigned long long) * (size_t)kStampWords * kTimedLaunches);
+    L.stamps_out = take(sizeof(unsigned long long) * 2 * kTimedLaunches);
     L.total = o;
     return true;
 }
@@ -176,7 +177,9 @@ struct iblb_ctx {
     std::vector<int4> tiles_h;
     int graph_steps = 64;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
-    hipGraphExec_t texec[2] = {nullptr, nullptr};  // same steps with event nodes
+    hipGraphExec_t texec[2] = {nullptr, nullptr};  // same steps, lattice launches stamped
+    hipGraphExec_t lexec = nullptr;                // lattice-only launches (time_lattice)
+    int lexec_n = 0, lexec_p = 0;                  // its launch count and start parity
     bool timing = false;
     double t_lb = 0.0, t_step = 0.0;
     std::vector<hipEvent_t> events;
@@ -207,10 +210,16 @@ int fail(iblb_ctx* c, int code, const std::string& msg) {
             return fail(ctx, IBLB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-NodeArrays node_arrays(const iblb_ctx* c) {
+double* positions(const iblb_ctx* c, int parity) {
+    return c->at<double>(parity ? c->L.pos1 : c->L.pos0);
+}
+
+// Node arrays of the step whose populations and positions have parity p:
+// positions read from buffer p, advected positions written to buffer p ^ 1.
+NodeArrays node_arrays(const iblb_ctx* c, int p) {
     NodeArrays A;
-    A.pos = c->at<double>(c->L.pos);
-    A.pos_w = c->at<double>(c->L.pos);
+    A.pos = positions(c, p);
+    A.pos_w = positions(c, p ^ 1);
     A.phi = c->at<float>(c->L.phi);
     A.qdot = c->at<float>(c->L.qdot);
     A.dropped = c->at<float>(c->L.dropped);
@@ -235,6 +244,10 @@ void drop_graphs(iblb_ctx* c) {
             (void)hipGraphExecDestroy(c->texec[k]);
             c->texec[k] = nullptr;
         }
+    }
+    if (c->lexec) {
+        (void)hipGraphExecDestroy(c->lexec);
+        c->lexec = nullptr;
     }
 }
 
@@ -316,36 +329,53 @@ void launch_lb(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned lon
     else launch_lb_d<3>(c, s, src, full, stamps);
 }
 
-void launch_nodes(const iblb_ctx* c, hipStream_t s, int phase, int full) {
+// Forces at the positions of parity p, spread for the step of parity p.
+void launch_spread(const iblb_ctx* c, hipStream_t s, int p, int want_dropped) {
     if (c->L.ntot == 0) return;
-    const NodeArrays A = node_arrays(c);
+    const NodeArrays A = node_arrays(c, p);
     const int lanes = c->L.ntot * (c->dim == 2 ? Taps<2>::n : Taps<3>::n);
     const dim3 grid(ceil_div(lanes, kBlock)), block(kBlock);
     const DropDev* D = c->at<DropDev>(c->L.drops);
-    if (phase == 0) {
-        if (c->dim == 2)
-            hipLaunchKernelGGL(k_force_spread<2>, grid, block, 0, s, D, A, c->at<float>(c->L.F),
-                               c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status), full);
-        else
-            hipLaunchKernelGGL(k_force_spread<3>, grid, block, 0, s, D, A, c->at<float>(c->L.F),
-                               c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status), full);
-    } else {
-        if (c->dim == 2)
-            hipLaunchKernelGGL(k_interp_advect<2>, grid, block, 0, s, D, A, c->at<float>(c->L.U),
-                               c->at<int>(c->L.status));
-        else
-            hipLaunchKernelGGL(k_interp_advect<3>, grid, block, 0, s, D, A, c->at<float>(c->L.U),
-                               c->at<int>(c->L.status));
-    }
+    if (c->dim == 2)
+        hipLaunchKernelGGL(k_force_spread<2>, grid, block, 0, s, D, A, c->at<float>(c->L.F),
+                           c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status), want_dropped);
+    else
+        hipLaunchKernelGGL(k_force_spread<3>, grid, block, 0, s, D, A, c->at<float>(c->L.F),
+                           c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status), want_dropped);
 }
 
-// One time step from buffer `src`; stamps (may be null) is the timing slot
-// pair of its lattice launch.
-void launch_step(const iblb_ctx* c, hipStream_t s, int src, int full,
+// Node work after the lattice step of parity p: interpolate and advect
+// (positions p -> p ^ 1) and, unless this is the last step of the call,
+// compute the forces at the new positions and spread them for the next
+// step (one fused launch in 2D).
+void launch_after(const iblb_ctx* c, hipStream_t s, int p, bool last, int want_dropped) {
+    if (c->L.ntot == 0) return;
+    const NodeArrays A = node_arrays(c, p);
+    const int lanes = c->L.ntot * (c->dim == 2 ? Taps<2>::n : Taps<3>::n);
+    const dim3 grid(ceil_div(lanes, kBlock)), block(kBlock);
+    const DropDev* D = c->at<DropDev>(c->L.drops);
+    if (c->dim == 2 && !last) {
+        hipLaunchKernelGGL(k_ib_fused2, grid, block, 0, s, D, A, (const float*)c->at<float>(c->L.U),
+                           c->at<float>(c->L.F), c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status),
+                           want_dropped);
+        return;
+    }
+    if (c->dim == 2)
+        hipLaunchKernelGGL(k_interp_advect<2>, grid, block, 0, s, D, A, (const float*)c->at<float>(c->L.U),
+                           c->at<int>(c->L.status));
+    else
+        hipLaunchKernelGGL(k_interp_advect<3>, grid, block, 0, s, D, A, (const float*)c->at<float>(c->L.U),
+                           c->at<int>(c->L.status));
+    if (!last) launch_spread(c, s, p ^ 1, want_dropped);
+}
+
+// One time step of parity p, its forces already spread: lattice update,
+// then the node work (see launch_after).  stamps (may be null) is the
+// timing slot set of the lattice launch.
+void launch_step(const iblb_ctx* c, hipStream_t s, int p, bool last, int full, int want_dropped,
                  unsigned long long* stamps = nullptr) {
-    launch_nodes(c, s, 0, full);
-    launch_lb(c, s, src, full, stamps);
-    launch_nodes(c, s, 1, full);
+    launch_lb(c, s, p, full, stamps);
+    launch_after(c, s, p, last, want_dropped);
 }
 
 int ensure_events(iblb_ctx* c, int need) {
@@ -357,9 +387,9 @@ int ensure_events(iblb_ctx* c, int need) {
     return IBLB_OK;
 }
 
-// Graph of graph_steps steps starting from buffer `parity`; with `timed`
-// the lattice launch of step k uses timing slot set k (timed graphs hold at
-// most kTimedLaunches steps).
+// Graph of graph_steps steps starting from buffer `parity` (none of them
+// the last step of a call); with `timed` the lattice launch of step k uses
+// timing slot set k (timed graphs hold at most kTimedLaunches steps).
 int ensure_graph(iblb_ctx* c, int parity, bool timed = false) {
     hipGraphExec_t* slot = timed ? &c->texec[parity] : &c->exec[parity];
     if (*slot) return IBLB_OK;
@@ -368,7 +398,7 @@ int ensure_graph(iblb_ctx* c, int parity, bool timed = false) {
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     int src = parity;
     for (int k = 0; k < c->graph_steps; ++k) {
-        launch_step(c, c->cap_stream, src, 0, timed ? st + (size_t)k * kStampWords : nullptr);
+        launch_step(c, c->cap_stream, src, false, 0, 0, timed ? st + (size_t)k * kStampWords : nullptr);
         src ^= 1;
     }
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
@@ -512,7 +542,7 @@ void launch_diag_d(iblb_ctx* c, bool cells = true) {
         }
     }
     hipLaunchKernelGGL(k_diag<DIM>, dim3(c->n), dim3(kBlock), 0, c->stream, c->at<DropDev>(c->L.drops),
-                       node_arrays(c), cells ? (const double*)c->at<double>(c->L.partials) : nullptr,
+                       node_arrays(c, c->cur), cells ? (const double*)c->at<double>(c->L.partials) : nullptr,
                        c->at<DiagDev>(c->L.diag));
 }
 
@@ -675,7 +705,7 @@ int iblb_set_interface(iblb_ctx* c, int d, const double* h_pos, const int32_t* h
                 return fail(c, IBLB_EINVAL, "a node lies at or below the substrate (h <= 0)");
     std::vector<double> pos(h_pos, h_pos + (size_t)c->dim * N);
     for (int a = 0; a < c->dim; ++a)
-        HIPCHK(c, hipMemcpyAsync(c->at<double>(c->L.pos) + (size_t)a * st + D.node_off,
+        HIPCHK(c, hipMemcpyAsync(positions(c, c->cur) + (size_t)a * st + D.node_off,
                                  pos.data() + (size_t)a * N, sizeof(double) * N,
                                  hipMemcpyHostToDevice, c->stream));
     std::vector<int> tri, inc, beg, end;
@@ -776,24 +806,22 @@ int iblb_step(iblb_ctx* c, int n_steps) {
     }
     if (c->timing) {
         // Same schedule as below (graph replays + direct launches), with the
-        // lattice kernel stamping its own start and end on the device clock;
-        // the stream is synchronised after each replay to read the stamps.
-        // The final field-storing step is not timed.
-        hipEvent_t ev[2];
-        for (int k = 0; k < 2; ++k) {
-            int rc = ensure_events(c, 2);
-            if (rc) return rc;
-            ev[k] = c->events[k];
-        }
+        // lattice kernel stamping its own first block start and last store
+        // on the device clock; the stream is synchronised after each replay
+        // to read the stamps.  The final field-storing step is not timed.
+        int rc = ensure_events(c, 2);
+        if (rc) return rc;
+        hipEvent_t* ev = c->events.data();
         unsigned long long* st = c->at<unsigned long long>(c->L.stamps);
-        const int eager_slot = kTimedLaunches;
+        const int eager_slot = 0;
         const bool graphs = c->graph_steps > 0 && c->graph_steps <= kTimedLaunches;
         double lb = 0.0, ms = 0.0;
         long long nlb = 0;
         HIPCHK(c, hipEventRecord(ev[0], c->stream));
-        int rem = n_steps, rc;
+        launch_spread(c, c->stream, c->cur, n_steps == 1);
+        int rem = n_steps;
         while (rem > 1) {
-            if (graphs && rem - 1 >= c->graph_steps) {
+            if (graphs && rem >= c->graph_steps + 2) {
                 if ((rc = ensure_graph(c, c->cur, true)) || (rc = reset_stamps(c, 0, c->graph_steps)))
                     return rc;
                 HIPCHK(c, hipGraphLaunch(c->texec[c->cur], c->stream));
@@ -803,7 +831,7 @@ int iblb_step(iblb_ctx* c, int n_steps) {
                 c->step += c->graph_steps;
             } else {
                 if ((rc = reset_stamps(c, eager_slot, 1))) return rc;
-                launch_step(c, c->stream, c->cur, 0, st + (size_t)eager_slot * kStampWords);
+                launch_step(c, c->stream, c->cur, false, 0, rem == 2, st + (size_t)eager_slot * kStampWords);
                 if ((rc = read_stamps(c, eager_slot, 1, ms))) return rc;
                 ++nlb;
                 c->cur ^= 1;
@@ -812,7 +840,7 @@ int iblb_step(iblb_ctx* c, int n_steps) {
             }
             lb += ms;
         }
-        launch_step(c, c->stream, c->cur, 1);
+        launch_step(c, c->stream, c->cur, true, 1, 0);
         c->cur ^= 1;
         c->step++;
         HIPCHK(c, hipEventRecord(ev[1], c->stream));
@@ -823,22 +851,26 @@ int iblb_step(iblb_ctx* c, int n_steps) {
         c->t_lb = nlb ? lb / nlb : 0.0;
         c->t_step = total / n_steps;
     } else {
+        // forces for the first step; every later spread is launched by the
+        // node work of the step before it; the drops lost at walls are
+        // recorded by the spread that feeds the last step
+        launch_spread(c, c->stream, c->cur, n_steps == 1);
         int rem = n_steps;
         while (rem > 1) {
-            if (c->graph_steps > 0 && rem - 1 >= c->graph_steps) {
+            if (c->graph_steps > 0 && rem >= c->graph_steps + 2) {
                 int rc = ensure_graph(c, c->cur);
                 if (rc) return rc;
                 HIPCHK(c, hipGraphLaunch(c->exec[c->cur], c->stream));
                 rem -= c->graph_steps;
                 c->step += c->graph_steps;
             } else {
-                launch_step(c, c->stream, c->cur, 0);
+                launch_step(c, c->stream, c->cur, false, 0, rem == 2);
                 c->cur ^= 1;
                 rem--;
                 c->step++;
             }
         }
-        launch_step(c, c->stream, c->cur, 1);
+        launch_step(c, c->stream, c->cur, true, 1, 0);
         c->cur ^= 1;
         c->step++;
         HIPCHK(c, hipGetLastError());
@@ -879,7 +911,7 @@ int iblb_read_nodes(iblb_ctx* c, int d, double* h_pos, float* h_vel, float* h_fo
     const int o = c->drops[d].node_off;
     for (int a = 0; a < c->dim && N > 0; ++a) {
         if (h_pos)
-            HIPCHK(c, hipMemcpyAsync(h_pos + (size_t)a * N, c->at<double>(c->L.pos) + (size_t)a * st + o,
+            HIPCHK(c, hipMemcpyAsync(h_pos + (size_t)a * N, positions(c, c->cur) + (size_t)a * st + o,
                                      sizeof(double) * N, hipMemcpyDeviceToHost, c->stream));
         if (h_vel)
             HIPCHK(c, hipMemcpyAsync(h_vel + (size_t)a * N, c->at<float>(c->L.qdot) + (size_t)a * st + o,
@@ -1040,6 +1072,48 @@ int iblb_last_timing(const iblb_ctx* c, double* lb_ms, double* step_ms) {
     if (!c) return IBLB_EINVAL;
     if (lb_ms) *lb_ms = c->t_lb;
     if (step_ms) *step_ms = c->t_step;
+    return IBLB_OK;
+}
+
+int iblb_time_lattice(iblb_ctx* c, int launches, double* ms_per_launch) {
+    if (!c || !ms_per_launch) return IBLB_EINVAL;
+    if (launches < 2 || launches > 1024 || launches % 2)
+        return fail(c, IBLB_EINVAL, "time_lattice: launches must be even, 2..1024");
+    if (c->tiles_dirty) {
+        int rc = rebuild_tiles(c);
+        if (rc) return rc;
+    }
+    if (c->lexec && (c->lexec_n != launches || c->lexec_p != c->cur)) {
+        (void)hipGraphExecDestroy(c->lexec);
+        c->lexec = nullptr;
+    }
+    if (!c->lexec) {
+        hipGraph_t g = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < launches; ++k) launch_lb(c, c->cap_stream, c->cur ^ (k & 1), 0, nullptr);
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (e != hipSuccess) return fail(c, IBLB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&c->lexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->lexec = nullptr;
+            return fail(c, IBLB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+        c->lexec_n = launches;
+        c->lexec_p = c->cur;
+    }
+    int rc = ensure_events(c, 2);
+    if (rc) return rc;
+    hipEvent_t* ev = c->events.data();
+    HIPCHK(c, hipGraphLaunch(c->lexec, c->stream));  // warm-up replay
+    HIPCHK(c, hipEventRecord(ev[0], c->stream));
+    HIPCHK(c, hipGraphLaunch(c->lexec, c->stream));
+    HIPCHK(c, hipEventRecord(ev[1], c->stream));
+    HIPCHK(c, hipEventSynchronize(ev[1]));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
+    c->step += 2LL * launches;
+    *ms_per_launch = (double)ms / launches;
     return IBLB_OK;
 }
 

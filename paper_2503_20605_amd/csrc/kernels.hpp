@@ -273,7 +273,7 @@ __device__ __forceinline__ int tap_index(int base, int k, int n, int wall) {
 
 struct NodeArrays {
     const double* pos;   // [3][stride]
-    double* pos_w;       // same array, written by the advection
+    double* pos_w;       // positions of the next step, written by the advection
     float* phi;          // [3][stride]
     float* qdot;         // [3][stride]
     float* dropped;      // [3][stride]
@@ -297,29 +297,42 @@ __device__ __forceinline__ double wetting_pi(const DropDev& D, double h) {
     return D.A * (ipow(s, D.n_exp) - ipow(s, D.m_exp));
 }
 
-// Geometry of node j of a 2D closed CCW polygon: surface-tension force
-// sigma (t_j - t_{j-1}), node normal (mean of the adjacent outward edge
-// normals), node length chi = l_{j-1} + l_j.
-__device__ __forceinline__ void node_geom_2d(const DropDev& D, const NodeArrays& A, int j,
-                                             double q[2], double fs[2], double n[2],
-                                             double& chi, double& le) {
-    const int N = D.n_nodes, loc = j - D.node_off;
-    const int jm = D.node_off + (loc == 0 ? N - 1 : loc - 1);
-    const int jp = D.node_off + (loc == N - 1 ? 0 : loc + 1);
-    const int st = A.stride;
-    q[0] = A.pos[j];
-    q[1] = A.pos[st + j];
-    const double ex = A.pos[jp] - q[0], ey = A.pos[st + jp] - q[1];
-    const double fx = q[0] - A.pos[jm], fy = q[1] - A.pos[st + jm];
-    le = sqrt(ex * ex + ey * ey);
+// Geometry of a node of a 2D closed CCW polygon from its own position q
+// and those of its ring neighbours qm (previous) and qp (next):
+// surface-tension force sigma (t_j - t_{j-1}), node normal (mean of the
+// adjacent outward edge normals), node length chi = l_{j-1} + l_j.
+__device__ __forceinline__ void geom_2d(double sigma, const double qm[2], const double q[2],
+                                        const double qp[2], double fs[2], double n[2],
+                                        double& chi) {
+    const double ex = qp[0] - q[0], ey = qp[1] - q[1];
+    const double fx = q[0] - qm[0], fy = q[1] - qm[1];
+    const double le = sqrt(ex * ex + ey * ey);
     const double lf = sqrt(fx * fx + fy * fy);
-    fs[0] = D.sigma * (ex / le - fx / lf);
-    fs[1] = D.sigma * (ey / le - fy / lf);
+    fs[0] = sigma * (ex / le - fx / lf);
+    fs[1] = sigma * (ey / le - fy / lf);
     double nx = ey / le + fy / lf, ny = -ex / le - fx / lf;
     const double nn = sqrt(nx * nx + ny * ny);
     n[0] = nx / nn;
     n[1] = ny / nn;
     chi = le + lf;
+}
+
+__device__ __forceinline__ void ring_2d(const DropDev& D, int j, int& jm, int& jp) {
+    const int N = D.n_nodes, loc = j - D.node_off;
+    jm = D.node_off + (loc == 0 ? N - 1 : loc - 1);
+    jp = D.node_off + (loc == N - 1 ? 0 : loc + 1);
+}
+
+__device__ __forceinline__ void node_geom_2d(const DropDev& D, const NodeArrays& A, int j,
+                                             double q[2], double fs[2], double n[2],
+                                             double& chi) {
+    int jm, jp;
+    ring_2d(D, j, jm, jp);
+    const int st = A.stride;
+    const double qm[2] = {A.pos[jm], A.pos[st + jm]}, qp[2] = {A.pos[jp], A.pos[st + jp]};
+    q[0] = A.pos[j];
+    q[1] = A.pos[st + j];
+    geom_2d(D.sigma, qm, q, qp, fs, n, chi);
 }
 
 // Geometry of vertex j of a closed 3D triangle mesh (CCW seen from
@@ -433,50 +446,15 @@ __device__ __forceinline__ int lane_tap(const DropDev& D, const double q[3], int
     return row * D.nx + ix;
 }
 
-// ---------------------------------------------------------------------------
-// Nodal forces + spreading (eq. force_spread)
-// ---------------------------------------------------------------------------
+// This lane's tap of the spreading of nodal force ph at q (eq.
+// force_spread); with want_dropped the group's wall losses are summed and
+// stored by lane 0.
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_force_spread(const DropDev* __restrict__ drops,
-                                                         NodeArrays A, float* __restrict__ F_all,
-                                                         uint8_t* __restrict__ flags_all,
-                                                         int* __restrict__ status,
-                                                         int want_dropped) {
+__device__ __forceinline__ void spread_lane(const DropDev& D, const NodeArrays& A, int j, int k,
+                                            const double q[3], const float ph[3],
+                                            float* __restrict__ F_all,
+                                            uint8_t* __restrict__ flags_all, int want_dropped) {
     constexpr int T = Taps<DIM>::n;
-    const int gid = blockIdx.x * kBlock + threadIdx.x;
-    const int j = gid / T, k = gid % T;
-    if (j >= A.ntot) return;
-    const int d = A.node_drop[j];
-    const DropDev& D = drops[d];
-    if (!D.active || D.force_mode != 0) return;
-    double q[3] = {0, 0, 0}, fs[3] = {0, 0, 0}, n[3] = {0, 0, 0}, chi;
-    double share;
-    if (DIM == 2) {
-        double le;
-        node_geom_2d(D, A, j, q, fs, n, chi, le);
-        share = 0.5 * chi;
-    } else {
-        node_geom_3d(D, A, j, q, fs, n, chi);
-        share = chi / 3.0;
-    }
-    if (D.wetting) {
-        const double P = wetting_pi(D, q[DIM - 1]);
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) fs[a] -= share * P * n[a];
-    }
-    float ph[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) ph[a] = (float)fs[a];
-    if (k == 0)
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) A.phi[a * A.stride + j] = ph[a];
-    bool ok = true;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) ok &= coord_ok(q[a]);
-    if (!ok) {  // the whole group leaves together
-        if (k == 0) atomicOr(status + d, 4);
-        return;
-    }
     float w;
     int row, ix;
     const int cell = lane_tap<DIM>(D, q, k, w, row, ix);
@@ -500,6 +478,60 @@ __global__ __launch_bounds__(kBlock) void k_force_spread(const DropDev* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Nodal forces + spreading (eq. force_spread)
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_force_spread(const DropDev* __restrict__ drops,
+                                                         NodeArrays A, float* __restrict__ F_all,
+                                                         uint8_t* __restrict__ flags_all,
+                                                         int* __restrict__ status,
+                                                         int want_dropped) {
+    constexpr int T = Taps<DIM>::n;
+    const int gid = blockIdx.x * kBlock + threadIdx.x;
+    const int j = gid / T, k = gid % T;
+    if (j >= A.ntot) return;
+    const int d = A.node_drop[j];
+    const DropDev& D = drops[d];
+    if (!D.active || D.force_mode != 0) return;
+    double q[3] = {0, 0, 0}, fs[3] = {0, 0, 0}, n[3] = {0, 0, 0}, chi;
+    double share;
+    if (DIM == 2) {
+        node_geom_2d(D, A, j, q, fs, n, chi);
+        share = 0.5 * chi;
+    } else {
+        node_geom_3d(D, A, j, q, fs, n, chi);
+        share = chi / 3.0;
+    }
+    if (D.wetting) {
+        const double P = wetting_pi(D, q[DIM - 1]);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) fs[a] -= share * P * n[a];
+    }
+    float ph[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) ph[a] = (float)fs[a];
+    if (k == 0)
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) A.phi[a * A.stride + j] = ph[a];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) ok &= coord_ok(q[a]);
+    if (!ok) {  // the whole group leaves together
+        if (k == 0) atomicOr(status + d, 4);
+        return;
+    }
+    spread_lane<DIM>(D, A, j, k, q, ph, F_all, flags_all, want_dropped);
+}
+
+// Nodes that do not move this step (droplet inactive, prescribed force
+// field, or non-finite input) still carry their positions into the buffer
+// of the next step.
+template <int DIM>
+__device__ __forceinline__ void hold_position(const NodeArrays& A, int j, int k) {
+    if (k < DIM) A.pos_w[k * A.stride + j] = A.pos[k * A.stride + j];
+}
+
+// ---------------------------------------------------------------------------
 // Interpolation (eq. vel_interpolation) + forward-Euler advection
 // ---------------------------------------------------------------------------
 template <int DIM>
@@ -513,16 +545,20 @@ __global__ __launch_bounds__(kBlock) void k_interp_advect(const DropDev* __restr
     if (j >= A.ntot) return;
     const int d = A.node_drop[j];
     const DropDev& D = drops[d];
-    if (!D.active || D.force_mode != 0) return;
     const int st = A.stride;
+    if (!D.active || D.force_mode != 0) {
+        hold_position<DIM>(A, j, k);
+        return;
+    }
     double q[3] = {0, 0, 0};
     bool ok = true;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         q[a] = A.pos[a * st + j];
-        ok &= coord_ok(q[a]);
+        ok = ok && coord_ok(q[a]);
     }
     if (!ok) {
+        hold_position<DIM>(A, j, k);
         if (k == 0) atomicOr(status + d, 4);
         return;
     }
@@ -549,6 +585,102 @@ __global__ __launch_bounds__(kBlock) void k_interp_advect(const DropDev* __restr
     if (!(sp <= 0.09f)) bad |= 2;  // |qdot| > 0.3 or not finite
     if (D.wetting && !(q[DIM - 1] + (double)acc[DIM - 1] > 0.0)) bad |= 1;
     if (bad) atomicOr(status + d, bad);
+}
+
+// ---------------------------------------------------------------------------
+// 2D: interpolation + advection of step t fused with the forces and the
+// spreading of step t + 1
+// ---------------------------------------------------------------------------
+// The lanes of node j's group also interpolate at its two ring neighbours,
+// so the new positions that the force at j needs are formed in registers
+// and no grid-wide wait separates the two halves.  Reads positions A.pos
+// (step t), writes A.pos_w (step t + 1).
+__global__ __launch_bounds__(kBlock) void k_ib_fused2(const DropDev* __restrict__ drops,
+                                                      NodeArrays A,
+                                                      const float* __restrict__ U_all,
+                                                      float* __restrict__ F_all,
+                                                      uint8_t* __restrict__ flags_all,
+                                                      int* __restrict__ status, int want_dropped) {
+    constexpr int T = Taps<2>::n;
+    const int gid = blockIdx.x * kBlock + threadIdx.x;
+    const int j = gid / T, k = gid % T;
+    if (j >= A.ntot) return;
+    const int d = A.node_drop[j];
+    const DropDev& D = drops[d];
+    const int st = A.stride;
+    if (!D.active || D.force_mode != 0) {
+        hold_position<2>(A, j, k);
+        return;
+    }
+    int jm, jp;
+    ring_2d(D, j, jm, jp);
+    const int id[3] = {jm, j, jp};
+    double q[3][3];
+    bool ok = true;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        q[m][0] = A.pos[id[m]];
+        q[m][1] = A.pos[st + id[m]];
+        q[m][2] = 0.0;
+        ok = ok && coord_ok(q[m][0]) && coord_ok(q[m][1]);
+    }
+    if (!ok) {
+        hold_position<2>(A, j, k);
+        if (k == 0) atomicOr(status + d, 4);
+        return;
+    }
+    const float* __restrict__ U = U_all + 2LL * D.c_off;
+    float acc[3][2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        float w;
+        int row, ix;
+        const int cell = lane_tap<2>(D, q[m], k, w, row, ix);
+        acc[m][0] = cell >= 0 ? U[cell] * w : 0.f;
+        acc[m][1] = cell >= 0 ? U[D.ncell + cell] * w : 0.f;
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        acc[m][0] = group_sum<T>(acc[m][0]);
+        acc[m][1] = group_sum<T>(acc[m][1]);
+    }
+    double qn[3][3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        qn[m][0] = q[m][0] + (double)acc[m][0];
+        qn[m][1] = q[m][1] + (double)acc[m][1];
+        qn[m][2] = 0.0;
+    }
+    if (k == 0) {
+        A.qdot[j] = acc[1][0];
+        A.qdot[st + j] = acc[1][1];
+        A.pos_w[j] = qn[1][0];
+        A.pos_w[st + j] = qn[1][1];
+        int bad = 0;
+        if (!(acc[1][0] * acc[1][0] + acc[1][1] * acc[1][1] <= 0.09f)) bad |= 2;
+        if (D.wetting && !(qn[1][1] > 0.0)) bad |= 1;
+        if (bad) atomicOr(status + d, bad);
+    }
+    ok = true;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) ok = ok && coord_ok(qn[m][0]) && coord_ok(qn[m][1]);
+    if (!ok) {
+        if (k == 0) atomicOr(status + d, 4);
+        return;
+    }
+    double fs[2], n[2], chi;
+    geom_2d(D.sigma, qn[0], qn[1], qn[2], fs, n, chi);
+    if (D.wetting) {
+        const double P = wetting_pi(D, qn[1][1]);
+        fs[0] -= 0.5 * chi * P * n[0];
+        fs[1] -= 0.5 * chi * P * n[1];
+    }
+    const float ph[3] = {(float)fs[0], (float)fs[1], 0.f};
+    if (k == 0) {
+        A.phi[j] = ph[0];
+        A.phi[st + j] = ph[1];
+    }
+    spread_lane<2>(D, A, j, k, qn[1], ph, F_all, flags_all, want_dropped);
 }
 
 // ---------------------------------------------------------------------------
@@ -703,8 +835,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(const DropDev* __restrict__ dro
         const int j = j0 + l;
         double q[3], fs[3], n[3], chi;
         if (DIM == 2) {
-            double le;
-            node_geom_2d(D, A, j, q, fs, n, chi, le);
+            node_geom_2d(D, A, j, q, fs, n, chi);
         } else {
             node_geom_3d(D, A, j, q, fs, n, chi);
         }

@@ -156,6 +156,45 @@ def test_full_size_large_droplet_in_graph_configuration():
     assert drho <= 1e-5 and du <= 1e-5 and dq <= 1e-5
 
 
+def test_steps_split_over_calls_and_timing_mode():
+    """The step count split over calls of 1, 2, 3, 66 and 128 steps (graph
+    replays of 16 steps, direct launches, the forces of each call's first
+    step computed at its start), with the timed schedule on for the last
+    two calls, reaches the oracle's state after the same 200 steps; the
+    lattice kernel's timed span is positive and shorter than a step."""
+    W = wl.droplet_2d_small()
+    s = gpu_solver([W.params], [W.nodes])
+    s.set_graph_steps(16)
+    print("[ib] split calls 1+2+3+66+128", flush=True)
+    for k, n in enumerate((1, 2, 3, 66, 128)):
+        s.set_timing(k >= 3)
+        s.step(n)
+    span, step = s.last_timing()
+    assert 0.0 < span < step
+    s.set_timing(False)
+    g = collect(s, 0, 2)
+    r = o.run(W.params, W.nodes, 200)
+    drho, du, dq = compare_fields(g, r, 2, "split-calls")
+    assert drho <= 1e-5 and du <= 1e-5 and dq <= 1e-5
+    assert np.max(np.abs(g["phi"] - r["phi"])) <= 1e-6 * max(1.0, np.max(np.abs(r["phi"])))
+
+
+def test_time_lattice_replays_plain_lattice_steps():
+    """The lattice-only timing graph advances the populations exactly as
+    the same number of force-free steps does (bit for bit: same kernel,
+    same inputs)."""
+    p = wl.Params(dim=2, nx=200, ny=70, tau=0.7, wetting=False)
+    f0 = wl.random_field((9, 1, p.ny, p.nx), seed=5, scale=1e-3)
+    a = gpu_solver([p])
+    a.write_populations(0, f0)
+    ms = a.time_lattice(6)
+    assert ms > 0.0
+    b = gpu_solver([p])
+    b.write_populations(0, f0)
+    b.step(12)
+    assert np.array_equal(a.read_populations(0).cpu().numpy(), b.read_populations(0).cpu().numpy())
+
+
 @pytest.mark.parametrize("storage,name", [(1, "f16"), (2, "bf16")])
 def test_shifted_low_precision_storage_error(storage, name):
     """Report the error of fp16 / bf16 storage of f - w against the oracle.
