@@ -45,9 +45,25 @@ struct Layout {
     long long cells;       // sum of cells
     long long flag_bytes;  // sum of band flags
     int ntot, ttot, max_tiles;
-    std::vector<long long> c_off, flag_off;
+    long long pop_elems;   // sum over droplets of Q * fst
+    std::vector<long long> c_off, flag_off, f_off;
+    std::vector<int> fst;
     std::vector<int> node_off, tri_off;
 };
+
+// Element stride between the Q population arrays of a droplet: the cell
+// count rounded up to 64 elements plus kPopPad.  Boxes of power-of-two size
+// would otherwise put the Q streams a power of two bytes apart; a pad of 64
+// elements measured best over the sizes and storages tried (2-4% faster
+// than none on an 8192x4096 D2Q9 box, neutral in 3D).
+#ifndef IBLB_POP_PAD
+#define IBLB_POP_PAD 64
+#endif
+constexpr int kPopPad = IBLB_POP_PAD;
+
+long long pop_stride(long long cells) {
+    return (cells + 63) / 64 * 64 + kPopPad;
+}
 
 int tiles_of(const iblb_params& p, int shape) {
     const int bx = kShapeBX[shape % kShapes], by = kBlock / bx;
@@ -69,6 +85,9 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.ttot = 0;
     L.max_tiles = 0;
     L.c_off.assign(n, 0);
+    L.f_off.assign(n, 0);
+    L.fst.assign(n, 0);
+    L.pop_elems = 0;
     L.flag_off.assign(n, 0);
     L.node_off.assign(n, 0);
     L.tri_off.assign(n, 0);
@@ -84,7 +103,7 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
             return false;
         }
         const long long cells = (long long)p.nx * p.ny * nz;
-        if (cells * Q >= (1LL << 31)) {
+        if ((long long)Q * pop_stride(cells) >= (1LL << 31)) {
             snprintf(buf, sizeof buf, "droplet %d: Q * cells must stay below 2^31", d);
             err = buf;
             return false;
@@ -118,6 +137,10 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
         }
         L.c_off[d] = L.cells;
         L.cells += cells;
+        L.fst[d] = pop_stride(cells);
+        L.f_off[d] = L.pop_elems;
+        L.pop_elems += (long long)Q * L.fst[d];
+        if (L.pop_elems >= (1LL << 40)) { err = "population arrays too large"; return false; }
         L.flag_off[d] = L.flag_bytes;
         L.flag_bytes += (long long)nz * p.ny * ceil_div(p.nx, kStrip);
         L.node_off[d] = L.ntot;
@@ -134,8 +157,8 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.drops = take(sizeof(DropDev) * n);
     L.tiles_lb = take(sizeof(int4) * L.max_tiles);
     L.tiles_all = take(sizeof(int4) * L.max_tiles);
-    L.f0 = take((size_t)Q * C * sb);
-    L.f1 = take((size_t)Q * C * sb);
+    L.f0 = take((size_t)L.pop_elems * sb);
+    L.f1 = take((size_t)L.pop_elems * sb);
     L.F = take(sizeof(float) * dim * C);
     L.U = take(sizeof(float) * dim * C);
     L.Fout = take(sizeof(float) * dim * C);
@@ -448,13 +471,14 @@ template <int S>
 void launch_pop_io(iblb_ctx* c, int d, const double* in, double* out) {
     using T = typename Codec<S>::T;
     T* f = c->at<T>(c->cur ? c->L.f1 : c->L.f0) + c->drops[d].f_off;
-    const long long n = (long long)c->Q * c->drops[d].ncell;
+    const DropDev& D = c->drops[d];
+    const long long n = (long long)c->Q * D.ncell;
     if (in)
         hipLaunchKernelGGL(k_pop_write<S>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, c->stream, f,
-                           n, in);
+                           D.ncell, D.fst, n, in);
     else
         hipLaunchKernelGGL(k_pop_read<S>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, c->stream,
-                           (const T*)f, n, out);
+                           (const T*)f, D.ncell, D.fst, n, out);
 }
 
 int pop_io(iblb_ctx* c, int d, const double* in, double* out) {
@@ -473,8 +497,8 @@ int reset_droplet(iblb_ctx* c, int d) {
     const DropDev& D = c->drops[d];
     const size_t sb = c->storage == ST_F32 ? 4 : 2;
     // zero deviation = rest state, in both buffers
-    HIPCHK(c, hipMemsetAsync(c->ws + c->L.f0 + D.f_off * sb, 0, (size_t)c->Q * D.ncell * sb, c->stream));
-    HIPCHK(c, hipMemsetAsync(c->ws + c->L.f1 + D.f_off * sb, 0, (size_t)c->Q * D.ncell * sb, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->ws + c->L.f0 + D.f_off * sb, 0, (size_t)c->Q * D.fst * sb, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->ws + c->L.f1 + D.f_off * sb, 0, (size_t)c->Q * D.fst * sb, c->stream));
     const size_t vb = sizeof(float) * c->dim * D.ncell, vo = sizeof(float) * c->dim * D.c_off;
     HIPCHK(c, hipMemsetAsync(c->ws + c->L.F + vo, 0, vb, c->stream));
     HIPCHK(c, hipMemsetAsync(c->ws + c->L.U + vo, 0, vb, c->stream));
@@ -605,7 +629,8 @@ int iblb_create(int n, const iblb_params* P, const int* nn, const int* nt, int s
         D.bcy = p.bc[1];
         D.bcz = c->dim == 3 ? p.bc[2] : 0;
         D.ncell = p.nx * p.ny * D.nz;
-        D.f_off = (long long)c->Q * L.c_off[d];
+        D.f_off = L.f_off[d];
+        D.fst = L.fst[d];
         D.c_off = L.c_off[d];
         D.flag_off = L.flag_off[d];
         D.omega = (float)(1.0 / p.tau);

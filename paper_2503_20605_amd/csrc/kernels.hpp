@@ -36,7 +36,7 @@ constexpr int kStrip = 64;    // cells per band flag (one wavefront)
 struct DropDev {
     int nx, ny, nz, nstrip;
     int bcx, bcy, bcz, ncell;
-    long long f_off;      // element offset of the populations (Q * ncell each)
+    long long f_off;      // element offset of the populations (Q arrays, fst apart)
     long long c_off;      // cell offset; vector arrays start at dim * c_off
     long long flag_off;   // byte offset of the band flags
     float omega, guo;     // 1/tau and 1 - 1/(2 tau)
@@ -45,7 +45,8 @@ struct DropDev {
     int node_off, n_nodes;
     int tri_off, n_tris;
     int tile_off, n_tiles;  // this droplet's run in the list of all tiles
-    int wetting, n_exp, m_exp, pad_;
+    int wetting, n_exp, m_exp;
+    int fst;              // element stride between population arrays (>= ncell)
     double sigma, A, xi, zcut;
 };
 
@@ -140,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
     const int y = tile.z * BY + (int)(threadIdx.x / BX);
     const int z = tile.w;
     if (x >= nx || y >= ny) return;
-    const int ncell = D.ncell;
+    const int ncell = D.ncell, fst = D.fst;
     const int cell = (z * ny + y) * nx + x;
     const typename C::T* __restrict__ fsrc = fsrc_all + D.f_off;
     typename C::T* __restrict__ fdst = fdst_all + D.f_off;
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         // a source beyond a wall means the population was reflected there:
         // take the opposite population of this cell (half-way bounce-back)
         const bool wall = (sx | sy | sz) < 0;
-        const int idx = wall ? opp(i) * ncell + cell : i * ncell + (sz * ny + sy) * nx + sx;
+        const int idx = wall ? opp(i) * fst + cell : i * fst + (sz * ny + sy) * nx + sx;
         f[i] = C::load(fsrc, idx);
     }
 
@@ -219,9 +220,9 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
             fn += g * L::w[i] * (3.f * (cF - uF) + 9.f * cu * cF);
         }
         if (NT)
-            C::store_nt(fdst, i * ncell + cell, fn);
+            C::store_nt(fdst, i * fst + cell, fn);
         else
-            C::store(fdst, i * ncell + cell, fn);
+            C::store(fdst, i * fst + cell, fn);
     }
 
     if (forced && D.force_mode == 0) {
@@ -686,18 +687,20 @@ __global__ __launch_bounds__(kBlock) void k_ib_fused2(const DropDev* __restrict_
 // ---------------------------------------------------------------------------
 // Population I/O and initialisation
 // ---------------------------------------------------------------------------
+// Dense [Q][ncell] doubles on the caller's side, population arrays fst
+// elements apart in the workspace.
 template <int S>
-__global__ void k_pop_write(typename Codec<S>::T* __restrict__ f, long long n,
+__global__ void k_pop_write(typename Codec<S>::T* __restrict__ f, int ncell, int fst, long long n,
                             const double* __restrict__ src) {
     const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) f[i] = Codec<S>::from_double(src[i]);
+    if (i < n) f[(i / ncell) * fst + i % ncell] = Codec<S>::from_double(src[i]);
 }
 
 template <int S>
-__global__ void k_pop_read(const typename Codec<S>::T* __restrict__ f, long long n,
+__global__ void k_pop_read(const typename Codec<S>::T* __restrict__ f, int ncell, int fst, long long n,
                            double* __restrict__ dst) {
     const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) dst[i] = Codec<S>::to_double(f[i]);
+    if (i < n) dst[i] = Codec<S>::to_double(f[(i / ncell) * fst + i % ncell]);
 }
 
 // Streaming copy used to measure the attainable HBM bandwidth of the device:
@@ -789,7 +792,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_sums(const DropDev* __restrict_
         const int cell = (z * D.ny + y) * D.nx + x;
         const typename Codec<S>::T* f = f_all + D.f_off;
         double s = 0.0;
-        for (int i = 0; i < L::Q; ++i) s += (double)Codec<S>::load(f, i * ncell + cell);
+        for (int i = 0; i < L::Q; ++i) s += (double)Codec<S>::load(f, i * D.fst + cell);
         v[0] = s;
         const double rho = rho_all[D.c_off + cell];
         const float* U = U_all + (long long)DIM * D.c_off;
