@@ -41,7 +41,9 @@ int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 struct Layout {
     // byte offsets into the workspace
     size_t drops, tiles_lb, tiles_all, f0, f1, F, U, Fout, rho, flags, pos0, pos1, phi, qdot, dropped,
-        node_drop, tri, inc, inc_beg, inc_end, status, partials, diag, stamps, stamps_out, total;
+        node_drop, tri, inc, inc_beg, inc_end, perm, chunks, status, partials, diag, stamps, stamps_out,
+        total;
+    int nchunks;           // capacity of the 3D spreading chunk table
     long long cells;       // sum of cells
     long long flag_bytes;  // sum of band flags
     int ntot, ttot, max_tiles;
@@ -60,6 +62,12 @@ struct Layout {
 #define IBLB_POP_PAD 64
 #endif
 constexpr int kPopPad = IBLB_POP_PAD;
+
+// Cell budget of a 3D spreading chunk's tap box when the host cuts chunks
+// (see morton_order); the kernel's own limit is kBoxCells.
+#ifndef IBLB_CHUNK_BUDGET
+#define IBLB_CHUNK_BUDGET 2560
+#endif
 
 long long pop_stride(long long cells) {
     return (cells + 63) / 64 * 64 + kPopPad;
@@ -88,6 +96,7 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.f_off.assign(n, 0);
     L.fst.assign(n, 0);
     L.pop_elems = 0;
+    L.nchunks = 0;
     L.flag_off.assign(n, 0);
     L.node_off.assign(n, 0);
     L.tri_off.assign(n, 0);
@@ -145,6 +154,7 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
         L.flag_bytes += (long long)nz * p.ny * ceil_div(p.nx, kStrip);
         L.node_off[d] = L.ntot;
         L.ntot += nn[d];
+        if (dim == 3) L.nchunks += nn[d];  // capacity: at worst one vertex per chunk
         L.tri_off[d] = L.ttot;
         L.ttot += T;
         for (int s = 0; s < kShapes; ++s) tiles[s] += tiles_of(p, s);
@@ -174,6 +184,8 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.inc = take(sizeof(int) * 3 * T);
     L.inc_beg = take(sizeof(int) * N);
     L.inc_end = take(sizeof(int) * N);
+    L.perm = take(sizeof(int) * N);
+    L.chunks = take(sizeof(int4) * std::max(L.nchunks, 1));
     L.status = take(sizeof(int) * n);
     L.partials = take(sizeof(double) * 8 * L.max_tiles);
     L.diag = take(sizeof(DiagDev) * n);
@@ -210,6 +222,8 @@ struct iblb_ctx {
     double clock_khz = 0.0;  // rate of wall_clock64() on the device
     long long step = 0;
     std::vector<int> status_h;
+    std::vector<std::vector<int4>> chunks_h;  // 3D spreading chunks per droplet
+    int nchunks = 0;                          // chunks on the device
     std::vector<char> iface_set;
     std::string err;
 
@@ -251,6 +265,7 @@ NodeArrays node_arrays(const iblb_ctx* c, int p) {
     A.inc = c->at<int>(c->L.inc);
     A.inc_beg = c->at<int>(c->L.inc_beg);
     A.inc_end = c->at<int>(c->L.inc_end);
+    A.perm = c->at<int>(c->L.perm);
     A.stride = std::max(c->L.ntot, 1);
     A.tstride = std::max(c->L.ttot, 1);
     A.ntot = c->L.ntot;
@@ -274,10 +289,31 @@ void drop_graphs(iblb_ctx* c) {
     }
 }
 
+void release_streams(iblb_ctx* c) {
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
+}
+
 int upload_drops(iblb_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(c->at<DropDev>(c->L.drops), c->drops.data(),
                              sizeof(DropDev) * c->n, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    return IBLB_OK;
+}
+
+// Concatenate the per-droplet spreading chunks into the device table.  The
+// chunk count is baked into captured graphs, so they are dropped.
+int upload_chunks(iblb_ctx* c) {
+    std::vector<int4> all;
+    for (const auto& v : c->chunks_h) all.insert(all.end(), v.begin(), v.end());
+    if ((long long)all.size() > std::max(c->L.nchunks, 1))
+        return fail(c, IBLB_EINVAL, "chunk table overflow");
+    if (!all.empty())
+        HIPCHK(c, hipMemcpyAsync(c->at<int4>(c->L.chunks), all.data(), sizeof(int4) * all.size(),
+                                 hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->nchunks = (int)all.size();
+    drop_graphs(c);
     return IBLB_OK;
 }
 
@@ -359,12 +395,16 @@ void launch_spread(const iblb_ctx* c, hipStream_t s, int p, int want_dropped) {
     const int lanes = c->L.ntot * (c->dim == 2 ? Taps<2>::n : Taps<3>::n);
     const dim3 grid(ceil_div(lanes, kBlock)), block(kBlock);
     const DropDev* D = c->at<DropDev>(c->L.drops);
-    if (c->dim == 2)
+    if (c->dim == 2) {
         hipLaunchKernelGGL(k_force_spread<2>, grid, block, 0, s, D, A, c->at<float>(c->L.F),
                            c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status), want_dropped);
-    else
-        hipLaunchKernelGGL(k_force_spread<3>, grid, block, 0, s, D, A, c->at<float>(c->L.F),
-                           c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status), want_dropped);
+        return;
+    }
+    hipLaunchKernelGGL(k_force3, dim3(ceil_div(c->L.ntot, kBlock)), block, 0, s, D, A);
+    if (c->nchunks == 0) return;
+    hipLaunchKernelGGL(k_spread3, dim3(c->nchunks), dim3(kSpreadBlock), 0, s, D, A,
+                       (const int4*)c->at<int4>(c->L.chunks), c->at<float>(c->L.F),
+                       c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status), want_dropped);
 }
 
 // Node work after the lattice step of parity p: interpolate and advect
@@ -665,6 +705,7 @@ int iblb_create(int n, const iblb_params* P, const int* nn, const int* nt, int s
     hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         g_create_err = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+        release_streams(c);
         delete c;
         return IBLB_EDEVICE;
     }
@@ -682,6 +723,17 @@ int iblb_create(int n, const iblb_params* P, const int* nn, const int* nt, int s
     chk(hipMemsetAsync(c->ws, 0, L.total, c->stream), "hipMemsetAsync");
     chk(hipMemcpyAsync(c->at<int>(L.node_drop), nd.data(), sizeof(int) * nd.size(),
                        hipMemcpyHostToDevice, c->stream), "hipMemcpyAsync");
+    // spatial order of the vertices: identity until an interface is set
+    std::vector<int> perm(std::max(L.ntot, 1), 0);
+    for (int k = 0; k < L.ntot; ++k) perm[k] = k;
+    chk(hipMemcpyAsync(c->at<int>(L.perm), perm.data(), sizeof(int) * perm.size(),
+                       hipMemcpyHostToDevice, c->stream), "hipMemcpyAsync");
+    if (c->dim == 3) {
+        c->chunks_h.assign(n, {});
+        for (int d = 0; d < n; ++d)
+            for (int b = 0; b < nn[d]; b += kChunk)
+                c->chunks_h[d].push_back(make_int4(d, L.node_off[d] + b, std::min(kChunk, nn[d] - b), 0));
+    }
     chk(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     if (rc == IBLB_OK) {
         for (int d = 0; d < n && rc == IBLB_OK; ++d) {
@@ -691,10 +743,11 @@ int iblb_create(int n, const iblb_params* P, const int* nn, const int* nt, int s
     }
     if (rc == IBLB_OK) {
         int r = rebuild_tiles(c);
+        if (!r) r = upload_chunks(c);
         if (r) { g_create_err = c->err; rc = r; }
     }
     if (rc != IBLB_OK) {
-        (void)hipStreamDestroy(c->cap_stream);
+        release_streams(c);
         delete c;
         return rc;
     }
@@ -706,12 +759,85 @@ int iblb_destroy(iblb_ctx* c) {
     if (!c) return IBLB_OK;
     drop_graphs(c);
     for (auto ev : c->events) (void)hipEventDestroy(ev);
-    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    release_streams(c);
     delete c;
     return IBLB_OK;
 }
 
 const char* iblb_last_error(const iblb_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+}  // extern "C"
+
+namespace {
+
+// Spread the low 10 bits of v to every third bit.
+uint32_t spread_bits3(uint32_t v) {
+    v &= 0x3ff;
+    v = (v | (v << 16)) & 0x030000ff;
+    v = (v | (v << 8)) & 0x0300f00f;
+    v = (v | (v << 4)) & 0x030c30c3;
+    v = (v | (v << 2)) & 0x09249249;
+    return v;
+}
+
+// Global node ids off + 0..N-1 sorted by the Morton code of their position
+// (SoA [3][N]) quantised to 1024 steps per axis over the vertices' bounding
+// box, so that consecutive vertices are close in space.
+void morton_order(const double* pos, int N, int off, std::vector<int>& perm, int d,
+                  std::vector<int4>& chunks) {
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = *std::min_element(pos + (size_t)a * N, pos + (size_t)(a + 1) * N);
+        hi[a] = *std::max_element(pos + (size_t)a * N, pos + (size_t)(a + 1) * N);
+    }
+    const double span = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+    std::vector<std::pair<uint32_t, int>> key(N);
+    for (int k = 0; k < N; ++k) {
+        uint32_t m = 0;
+        for (int a = 0; a < 3; ++a) {
+            const double u = (pos[(size_t)a * N + k] - lo[a]) / span * 1023.0;
+            m |= spread_bits3((uint32_t)std::min(std::max(u, 0.0), 1023.0)) << a;
+        }
+        key[k] = {m, k};
+    }
+    std::sort(key.begin(), key.end());
+    perm.resize(N);
+    for (int k = 0; k < N; ++k) perm[k] = off + key[k].second;
+    // Cut the order into chunks of at most kChunk vertices whose taps fit a
+    // box of kChunkBudget cells (below the kernel's kBoxCells, so that the
+    // vertices can move a little before a chunk overflows into the direct
+    // path).
+    constexpr long long kChunkBudget = IBLB_CHUNK_BUDGET;
+    chunks.clear();
+    int blo[3] = {0, 0, 0}, bhi[3] = {0, 0, 0}, first = 0, cnt = 0;
+    for (int r = 0; r < N; ++r) {
+        const int k = key[r].second;
+        int b[3];
+        for (int a = 0; a < 3; ++a) b[a] = (int)std::floor(pos[(size_t)a * N + k] - 0.5) - 1;
+        if (cnt > 0) {
+            long long cells = 1;
+            for (int a = 0; a < 3; ++a) cells *= std::max(bhi[a], b[a]) - std::min(blo[a], b[a]) + 4;
+            if (cnt == kChunk || cells > kChunkBudget) {
+                chunks.push_back(make_int4(d, off + first, cnt, 0));
+                cnt = 0;
+            }
+        }
+        if (cnt == 0) {
+            first = r;
+            for (int a = 0; a < 3; ++a) blo[a] = bhi[a] = b[a];
+        }
+        for (int a = 0; a < 3; ++a) {
+            blo[a] = std::min(blo[a], b[a]);
+            bhi[a] = std::max(bhi[a], b[a]);
+        }
+        ++cnt;
+    }
+    if (cnt > 0) chunks.push_back(make_int4(d, off + first, cnt, 0));
+}
+
+}  // namespace
+
+extern "C" {
 
 int iblb_set_interface(iblb_ctx* c, int d, const double* h_pos, const int32_t* h_tris) {
     if (!check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
@@ -733,7 +859,7 @@ int iblb_set_interface(iblb_ctx* c, int d, const double* h_pos, const int32_t* h
         HIPCHK(c, hipMemcpyAsync(positions(c, c->cur) + (size_t)a * st + D.node_off,
                                  pos.data() + (size_t)a * N, sizeof(double) * N,
                                  hipMemcpyHostToDevice, c->stream));
-    std::vector<int> tri, inc, beg, end;
+    std::vector<int> tri, inc, beg, end, perm;
     if (c->dim == 3) {
         const int T = c->n_tris[d];
         if (!h_tris) return fail(c, IBLB_EINVAL, "NULL triangle list");
@@ -775,6 +901,11 @@ int iblb_set_interface(iblb_ctx* c, int d, const double* h_pos, const int32_t* h
                                  hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(c->at<int>(c->L.inc_end) + D.node_off, end.data(), sizeof(int) * N,
                                  hipMemcpyHostToDevice, c->stream));
+        morton_order(pos.data(), N, D.node_off, perm, d, c->chunks_h[d]);
+        HIPCHK(c, hipMemcpyAsync(c->at<int>(c->L.perm) + D.node_off, perm.data(), sizeof(int) * N,
+                                 hipMemcpyHostToDevice, c->stream));
+        int rc = upload_chunks(c);
+        if (rc) return rc;
     }
     HIPCHK(c, hipMemsetAsync(c->at<int>(c->L.status) + d, 0, sizeof(int), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));  // host staging vectors go out of scope
@@ -905,7 +1036,7 @@ int iblb_step(iblb_ctx* c, int n_steps) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int d = 0; d < c->n; ++d)
         if (c->status_h[d] && c->drops[d].active) {
-            char buf[160];
+            char buf[256];
             const int code = c->status_h[d];
             snprintf(buf, sizeof buf, "droplet %d unstable (code %d:%s%s%s) by step %lld", d, code,
                      (code & 1) ? " node at or below the substrate" : "",

@@ -24,6 +24,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <limits.h>
 #include <stdint.h>
 
 #include "lattice.hpp"
@@ -267,7 +268,8 @@ __device__ __forceinline__ bool coord_ok(double v) { return fabs(v) <= kFarCoord
 // so base + k cannot overflow.
 __device__ __forceinline__ int tap_index(int base, int k, int n, int wall) {
     int i = base + k;
-    if (wall) return (i >= 0 && i < n) ? i : -1;
+    if (i >= 0 && i < n) return i;
+    if (wall) return -1;
     i %= n;
     return i < 0 ? i + n : i;
 }
@@ -283,6 +285,7 @@ struct NodeArrays {
     const int* inc;      // incidence entries (triangle << 2 | slot)
     const int* inc_beg;
     const int* inc_end;
+    const int* perm;     // node ids in spatial (Morton) order, per droplet
     int stride, tstride, ntot;
 };
 
@@ -589,6 +592,145 @@ __global__ __launch_bounds__(kBlock) void k_interp_advect(const DropDev* __restr
 }
 
 // ---------------------------------------------------------------------------
+// 3D: nodal forces, then spreading aggregated in LDS (eq. force_spread)
+// ---------------------------------------------------------------------------
+// Forces of every vertex (membrane + wetting), one lane per vertex.
+__global__ __launch_bounds__(kBlock) void k_force3(const DropDev* __restrict__ drops, NodeArrays A) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= A.ntot) return;
+    const DropDev& D = drops[A.node_drop[j]];
+    if (!D.active || D.force_mode != 0) return;
+    double q[3], fs[3], n[3], chi;
+    node_geom_3d(D, A, j, q, fs, n, chi);
+    if (D.wetting) {
+        const double P = wetting_pi(D, q[2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) fs[a] -= (chi / 3.0) * P * n[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) A.phi[a * A.stride + j] = (float)fs[a];
+}
+
+// A workgroup spreads one chunk of up to kChunk vertices that are close in
+// space (consecutive in Morton order, cut by the host where the taps' box
+// would grow beyond a budget).  Their 64 taps each overlap heavily,
+// so the contributions are first summed in an LDS box that covers the
+// chunk's taps, and each touched cell then takes one global atomic add per
+// component instead of one per contribution.  A chunk whose box exceeds
+// kBoxCells (vertices far apart) adds straight to global memory.
+constexpr int kChunk = 64;
+constexpr int kBoxCells = 4096;
+constexpr int kSpreadBlock = 1024;  // 16 wavefronts, each taking every 16th vertex
+
+__global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restrict__ drops, NodeArrays A,
+                                                    const int4* __restrict__ chunks,
+                                                    float* __restrict__ F_all,
+                                                    uint8_t* __restrict__ flags_all,
+                                                    int* __restrict__ status, int want_dropped) {
+    __shared__ float box[3 * kBoxCells];
+    __shared__ uint8_t touched[kBoxCells];
+    __shared__ double sq[kChunk][3];
+    __shared__ float sph[kChunk][3];
+    __shared__ int sok[kChunk];
+    __shared__ int lo[3], hi[3];
+    const int4 ch = chunks[blockIdx.x];  // (droplet, first index into perm, count, -)
+    const DropDev& D = drops[ch.x];
+    if (!D.active || D.force_mode != 0) return;
+    const int t = threadIdx.x, st = A.stride, count = ch.z;
+    if (t < 3) {
+        lo[t] = INT_MAX;
+        hi[t] = INT_MIN;
+    }
+    __syncthreads();
+    if (t < count) {
+        const int j = A.perm[ch.y + t];
+        bool ok = true;
+        double q[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            q[a] = A.pos[a * st + j];
+            ok = ok && coord_ok(q[a]);
+        }
+        sok[t] = ok;
+        if (ok) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                sq[t][a] = q[a];
+                sph[t][a] = A.phi[a * st + j];
+                const int b = (int)floor(q[a] - 0.5) - 1;
+                atomicMin(&lo[a], b);
+                atomicMax(&hi[a], b);
+            }
+        } else {
+            atomicOr(status + ch.x, 4);
+        }
+    }
+    __syncthreads();
+    const int ex = hi[0] - lo[0] + 4, ey = hi[1] - lo[1] + 4, ez = hi[2] - lo[2] + 4;
+    const bool any = lo[0] <= hi[0];
+    const bool fits = any && (long long)ex * ey * ez <= kBoxCells;
+    const int ncb = fits ? ex * ey * ez : 0;
+    for (int c = t; c < ncb; c += kSpreadBlock) {
+        box[c] = 0.f;
+        box[kBoxCells + c] = 0.f;
+        box[2 * kBoxCells + c] = 0.f;
+        touched[c] = 0;
+    }
+    __syncthreads();
+    float* __restrict__ F = F_all + 3LL * D.c_off;
+    const int k = t & 63;  // tap of this lane; one vertex per wavefront at a time
+    const int kx = k & 3, ky = (k >> 2) & 3, kz = k >> 4;
+    for (int v = t >> 6; v < count; v += kSpreadBlock / 64) {
+        if (!sok[v]) continue;  // the same for the whole wavefront
+        int bx, by, bz;
+        const float w = peskin_tap(sq[v][0], kx, bx) * peskin_tap(sq[v][1], ky, by) *
+                        peskin_tap(sq[v][2], kz, bz);
+        const int gx = tap_index(bx, kx, D.nx, D.bcx), gy = tap_index(by, ky, D.ny, D.bcy),
+                  gz = tap_index(bz, kz, D.nz, D.bcz);
+        float lost[3] = {0.f, 0.f, 0.f};
+        if ((gx | gy | gz) < 0) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) lost[a] = sph[v][a] * w;
+        } else if (fits) {
+            const int c = ((bz + kz - lo[2]) * ey + (by + ky - lo[1])) * ex + (bx + kx - lo[0]);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) atomicAdd(&box[a * kBoxCells + c], sph[v][a] * w);
+            touched[c] = 1;
+        } else {
+            const int row = gz * D.ny + gy, cell = row * D.nx + gx;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) unsafeAtomicAdd(F + a * D.ncell + cell, sph[v][a] * w);
+            flags_all[D.flag_off + row * D.nstrip + (gx >> 6)] = 1;
+        }
+        if (want_dropped) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) lost[a] = group_sum<64>(lost[a]);
+            if (k == 0) {
+                const int j = A.perm[ch.y + v];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) A.dropped[a * st + j] = lost[a];
+            }
+        }
+    }
+    if (!fits) return;
+    __syncthreads();
+    for (int c = t; c < ncb; c += kSpreadBlock) {
+        if (!touched[c]) continue;
+        const int cx = c % ex, cy = (c / ex) % ey, cz = c / (ex * ey);
+        // a touched cell received a fluid tap, so none of these is -1
+        const int gx = tap_index(lo[0], cx, D.nx, D.bcx), gy = tap_index(lo[1], cy, D.ny, D.bcy),
+                  gz = tap_index(lo[2], cz, D.nz, D.bcz);
+        const int row = gz * D.ny + gy, cell = row * D.nx + gx;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float v = box[a * kBoxCells + c];
+            if (v != 0.f) unsafeAtomicAdd(F + a * D.ncell + cell, v);
+        }
+        flags_all[D.flag_off + row * D.nstrip + (gx >> 6)] = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 2D: interpolation + advection of step t fused with the forces and the
 // spreading of step t + 1
 // ---------------------------------------------------------------------------
@@ -596,8 +738,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_advect(const DropDev* __restr
 // so the new positions that the force at j needs are formed in registers
 // and no grid-wide wait separates the two halves.  Reads positions A.pos
 // (step t), writes A.pos_w (step t + 1).
-__global__ __launch_bounds__(kBlock) void k_ib_fused2(const DropDev* __restrict__ drops,
-                                                      NodeArrays A,
+__global__ __launch_bounds__(kBlock) void k_ib_fused2(const DropDev* __restrict__ drops, NodeArrays A,
                                                       const float* __restrict__ U_all,
                                                       float* __restrict__ F_all,
                                                       uint8_t* __restrict__ flags_all,

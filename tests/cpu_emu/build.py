@@ -9,6 +9,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 SRCS = [os.path.join(ROOT, "paper_2503_20605_amd", "csrc", f) for f in ("iblb.hip", "mlp.hip")]
 OUT = os.path.join(HERE, "iblb_emu_driver")
+# Second build whose host-side chunking ignores the box budget (plain runs
+# of 64 vertices), so that spreading chunks overflow the kernel's LDS box
+# and take its direct-atomic path.
+OUT_DIRECT = os.path.join(HERE, "iblb_emu_driver_direct")
 CXX = "/opt/rocm/llvm/bin/clang++"
 
 
@@ -19,20 +23,24 @@ def sources():
         os.path.join(ROOT, "include", "iblb.h")]
 
 
-def build(force=False, verbose=False):
-    if (not force and os.path.exists(OUT)
-            and os.path.getmtime(OUT) > max(os.path.getmtime(s) for s in sources())):
-        return OUT
+def build(force=False, verbose=False, direct=False):
+    out = OUT_DIRECT if direct else OUT
+    if (not force and os.path.exists(out)
+            and os.path.getmtime(out) > max(os.path.getmtime(s) for s in sources())):
+        return out
     cmd = [CXX, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer",
            "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
            "-I", os.path.join(HERE, "include"), "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(ROOT, "paper_2503_20605_amd", "csrc"),
-           "-x", "c++"] + SRCS + [os.path.join(HERE, "driver.cpp"), "-o", OUT]
+           "-I", os.path.join(ROOT, "paper_2503_20605_amd", "csrc")]
+    if direct:
+        cmd += ["-DIBLB_CHUNK_BUDGET=1000000000"]
+    cmd += ["-x", "c++"] + SRCS + [os.path.join(HERE, "driver.cpp"), "-o", out]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    return OUT
+    return out
 
 
 if __name__ == "__main__":
     build(force=True, verbose=True)
+    build(force=True, verbose=True, direct=True)

@@ -16,6 +16,7 @@
 // launches (arguments evaluated at capture time) and replays them.
 #pragma once
 
+#include <limits.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -204,6 +205,21 @@ inline V16 __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(V4 a, V4 b, V16 c, int, int,
     return c;
 }
 
+inline int atomicMin(int* p, int v) {
+    int old = *p;
+    if (v < old) *p = v;
+    return old;
+}
+inline int atomicMax(int* p, int v) {
+    int old = *p;
+    if (v > old) *p = v;
+    return old;
+}
+inline float atomicAdd(float* p, float v) {
+    float old = *p;
+    *p = old + v;
+    return old;
+}
 inline float unsafeAtomicAdd(float* p, float v) {
     float old = *p;
     *p = old + v;

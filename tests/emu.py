@@ -21,10 +21,10 @@ def _params_struct(p):
 
 def run_case(params_list, nodes_list=None, tris_list=None, steps=(1,), storage=0,
              graph_steps=None, shape=None, f0dev=None, forces=None, timing=False,
-             inactive=(), rest=None, timeout=600):
+             inactive=(), rest=None, timeout=600, direct_chunks=False):
     import build as emu_build
     from paper_2503_20605_amd._lib import iblb_diag
-    exe = emu_build.build()
+    exe = emu_build.build(direct=direct_chunks)
     n = len(params_list)
     nodes_list = nodes_list or [None] * n
     tris_list = tris_list or [None] * n

@@ -69,6 +69,22 @@ def test_droplet_3d_tiny():
     assert abs(g["diag"]["volume"] - o.volume_3d(r["q"], T)) < 1e-9 * abs(g["diag"]["volume"])
 
 
+@pytest.mark.parametrize("direct", [False, True])
+def test_droplet_3d_coarse_mesh_across_periodic_edge(direct):
+    """Coarse cap centred on the periodic x edge, spreading boxes that wrap
+    around the periodic axis.  With `direct`, the host cuts plain runs of 64
+    vertices, so some chunks overflow the LDS box and add straight to
+    global memory next to chunks that fit."""
+    p = wl.Params(dim=3, nx=24, ny=22, nz=14, bc=(0, 0, 1), tau=0.9, sigma=0.006,
+                  theta_eq_deg=100.0, xi=2.0)
+    V, T = wl.cap_mesh(9.0, 90.0, 2.0, 4, (1.0, 11.0))
+    g = run_case([p], [V], [T], steps=(2,), graph_steps=2, direct_chunks=direct)[0]
+    r = o.run(p, V, 2, tris=T)
+    drho, du, dq = compare_fields(g, r, 3, "emu 3d periodic")
+    assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
+    assert np.min(r["q"][:, 0]) < 0.0
+
+
 @pytest.mark.parametrize("storage", [0, 1, 2])
 def test_streaming_bit_exact_all_storages(storage):
     for dim, (nx, ny, nz), bc in ((2, (37, 9, 1), (0, 1, 0)), (3, (9, 5, 4), (1, 0, 1))):

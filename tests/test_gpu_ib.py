@@ -80,6 +80,23 @@ def test_droplet_3d_small_copy():
     assert np.max(np.abs(g["phi"] - r["phi"])) <= 1e-6 * np.max(np.abs(r["phi"]))
 
 
+def test_droplet_3d_coarse_mesh_across_periodic_edge():
+    """Coarse cap centred on the periodic x edge of a 48x44x20 box: some
+    spreading chunks span more than the LDS box (direct global atomics),
+    others fit, and boxes wrap around the periodic axis."""
+    p = wl.Params(dim=3, nx=48, ny=44, nz=20, bc=(0, 0, 1), tau=0.9, sigma=0.006,
+                  theta_eq_deg=100.0, xi=2.0)
+    V, T = wl.cap_mesh(9.0, 90.0, 2.0, 4, (1.0, 22.0))
+    steps = 100
+    print("[ib] 3d coarse cap across the periodic edge", flush=True)
+    g = gpu_run(p, V, steps, tris=T, graph_steps=16)
+    r = o.run(p, V, steps, tris=T)
+    drho, du, dq = compare_fields(g, r, 3, "3d-periodic")
+    assert drho <= 1e-5 and du <= 1e-5 and dq <= 1e-5
+    assert np.max(np.abs(g["phi"] - r["phi"])) <= 1e-6 * np.max(np.abs(r["phi"]))
+    assert np.min(r["q"][:, 0]) < 0.0
+
+
 def test_batch_of_uneven_droplets_matches_each_alone():
     """Three droplets of different box size, angle and tau, plus a fluid-only
     box, stepped in one launch per kernel."""
