@@ -30,6 +30,12 @@ HBM_PEAK_GBS = 8000.0
 # lattice-kernel variants: block width along x and non-temporal stores
 LB_BX = (256, 128, 64, 256, 128, 64)
 LB_NT = (0, 0, 0, 1, 1, 1)
+
+
+def lb_kernel_name(dim, storage, variant):
+    if variant >= 6:
+        return f"k_lb_vec<{dim}, {storage}, {variant - 6}>"
+    return f"k_lb<{dim}, {storage}, {LB_BX[variant]}, {LB_NT[variant]}>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lb_traffic.md")
 
 
@@ -176,7 +182,7 @@ def lb_only_rate(dim, nx, ny, nz, storage, steps):
             "lb_us": round(lb_ms * 1e3, 2), "lb_exec_span_us": round(span_ms * 1e3, 2),
             "MLUPS": round(cells / (lb_ms * 1e-3) / 1e6, 1),
             "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(f"k_lb<{dim}, {storage}, {LB_BX[v]}, {LB_NT[v]}>",
+            "traffic": measured_traffic(lb_kernel_name(dim, storage, v),
                                         f"d{dim}q{9 if dim == 2 else 19}_{nx}x{ny}"
                                         + (f"x{nz}" if dim == 3 else "") + "_lattice_only")}
 
@@ -243,7 +249,7 @@ def main():
     lb_ms = s.time_lattice(256)
     bpc = bytes_per_cell(dim, storage)
     achieved = bpc * cells / (lb_ms * 1e-3) / 1e9
-    lb_name = f"k_lb<{dim}, {storage}, {LB_BX[variant]}, {LB_NT[variant]}>"
+    lb_name = lb_kernel_name(dim, storage, variant)
     traffic = measured_traffic(lb_name, W.name)
 
     out = {

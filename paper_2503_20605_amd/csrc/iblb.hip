@@ -26,11 +26,17 @@ using namespace iblb;
 
 namespace {
 
-// Lattice-kernel variants (autotuner candidates): tile shape 256x1, 128x2 or
-// 64x4 cells per block, each with ordinary or non-temporal stores.
-constexpr int kShapes = 3;
-constexpr int kVariants = 2 * kShapes;
-constexpr int kShapeBX[kShapes] = {256, 128, 64};
+// Lattice-kernel variants (autotuner candidates): variants 0-5 are the
+// scalar kernel on tiles of 256x1, 128x2 or 64x4 cells per block (shape
+// v % 3), with ordinary (v < 3) or non-temporal stores; 6 and 7 the vector
+// kernel (four cells per lane, tiles of 256x4 cells: shape 3), ordinary or
+// non-temporal stores, for boxes whose nx are all multiples of 4.
+constexpr int kShapes = 4;
+constexpr int kVariants = 8;
+constexpr int kShapeBX[kShapes] = {256, 128, 64, 256};
+constexpr int kShapeBY[kShapes] = {1, 2, 4, 4};
+int shape_of(int variant) { return variant < 6 ? variant % 3 : 3; }
+bool vector_variant(int variant) { return variant >= 6; }
 constexpr size_t kAlign = 256;
 constexpr int kMaxGraphSteps = 1024;
 constexpr int kTimedLaunches = 256;  // timed lattice launches per replay at most
@@ -74,7 +80,7 @@ long long pop_stride(long long cells) {
 }
 
 int tiles_of(const iblb_params& p, int shape) {
-    const int bx = kShapeBX[shape % kShapes], by = kBlock / bx;
+    const int bx = kShapeBX[shape], by = kShapeBY[shape];
     return ceil_div(p.nx, bx) * ceil_div(p.ny, by) * (p.dim == 3 ? p.nz : 1);
 }
 
@@ -100,7 +106,7 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.flag_off.assign(n, 0);
     L.node_off.assign(n, 0);
     L.tri_off.assign(n, 0);
-    int tiles[kShapes] = {0, 0, 0};
+    int tiles[kShapes] = {0, 0, 0, 0};
     for (int d = 0; d < n; ++d) {
         const iblb_params& p = P[d];
         char buf[256];
@@ -317,10 +323,10 @@ int upload_chunks(iblb_ctx* c) {
     return IBLB_OK;
 }
 
-// Tiles of droplet d, x fastest, then y, then z.
-void push_tiles(const iblb_ctx* c, int d, std::vector<int4>& v) {
+// Tiles of droplet d in the given shape, x fastest, then y, then z.
+void push_tiles(const iblb_ctx* c, int d, int shape, std::vector<int4>& v) {
     const iblb_params& p = c->params[d];
-    const int bx = kShapeBX[c->variant % kShapes], by = kBlock / bx;
+    const int bx = kShapeBX[shape], by = kShapeBY[shape];
     const int ntx = ceil_div(p.nx, bx), nty = ceil_div(p.ny, by);
     const int nz = c->dim == 3 ? p.nz : 1;
     for (int z = 0; z < nz; ++z)
@@ -331,10 +337,11 @@ void push_tiles(const iblb_ctx* c, int d, std::vector<int4>& v) {
 int rebuild_tiles(iblb_ctx* c) {
     std::vector<int4> all, lb;
     for (int d = 0; d < c->n; ++d) {
+        // the list of all tiles (diagnostics) always has shape 0
         c->drops[d].tile_off = (int)all.size();
-        push_tiles(c, d, all);
+        push_tiles(c, d, 0, all);
         c->drops[d].n_tiles = (int)all.size() - c->drops[d].tile_off;
-        if (c->drops[d].active) push_tiles(c, d, lb);
+        if (c->drops[d].active) push_tiles(c, d, shape_of(c->variant), lb);
     }
     c->ntiles_all = (int)all.size();
     c->ntiles_lb = (int)lb.size();
@@ -369,7 +376,9 @@ void launch_lb_t(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned l
         case 2: go(k_lb<DIM, S, 64, 0>); break;
         case 3: go(k_lb<DIM, S, 256, 1>); break;
         case 4: go(k_lb<DIM, S, 128, 1>); break;
-        default: go(k_lb<DIM, S, 64, 1>); break;
+        case 5: go(k_lb<DIM, S, 64, 1>); break;
+        case 6: go(k_lb_vec<DIM, S, 0>); break;
+        default: go(k_lb_vec<DIM, S, 1>); break;
     }
 }
 
@@ -395,12 +404,15 @@ void launch_spread(const iblb_ctx* c, hipStream_t s, int p, int want_dropped) {
     const int lanes = c->L.ntot * (c->dim == 2 ? Taps<2>::n : Taps<3>::n);
     const dim3 grid(ceil_div(lanes, kBlock)), block(kBlock);
     const DropDev* D = c->at<DropDev>(c->L.drops);
+    const bool one = c->n == 1;
     if (c->dim == 2) {
-        hipLaunchKernelGGL(k_force_spread<2>, grid, block, 0, s, D, A, c->at<float>(c->L.F),
-                           c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status), want_dropped);
+        hipLaunchKernelGGL((one ? k_force_spread<2, true> : k_force_spread<2, false>), grid, block, 0, s, D,
+                           A, c->at<float>(c->L.F), c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status),
+                           want_dropped);
         return;
     }
-    hipLaunchKernelGGL(k_force3, dim3(ceil_div(c->L.ntot, kBlock)), block, 0, s, D, A);
+    hipLaunchKernelGGL(one ? k_force3<true> : k_force3<false>, dim3(ceil_div(c->L.ntot, kBlock)), block, 0, s,
+                       D, A);
     if (c->nchunks == 0) return;
     hipLaunchKernelGGL(k_spread3, dim3(c->nchunks), dim3(kSpreadBlock), 0, s, D, A,
                        (const int4*)c->at<int4>(c->L.chunks), c->at<float>(c->L.F),
@@ -417,18 +429,20 @@ void launch_after(const iblb_ctx* c, hipStream_t s, int p, bool last, int want_d
     const int lanes = c->L.ntot * (c->dim == 2 ? Taps<2>::n : Taps<3>::n);
     const dim3 grid(ceil_div(lanes, kBlock)), block(kBlock);
     const DropDev* D = c->at<DropDev>(c->L.drops);
+    const bool one = c->n == 1;
+    const float* U = c->at<float>(c->L.U);
     if (c->dim == 2 && !last) {
-        hipLaunchKernelGGL(k_ib_fused2, grid, block, 0, s, D, A, (const float*)c->at<float>(c->L.U),
+        hipLaunchKernelGGL(one ? k_ib_fused2<true> : k_ib_fused2<false>, grid, block, 0, s, D, A, U,
                            c->at<float>(c->L.F), c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status),
                            want_dropped);
         return;
     }
     if (c->dim == 2)
-        hipLaunchKernelGGL(k_interp_advect<2>, grid, block, 0, s, D, A, (const float*)c->at<float>(c->L.U),
-                           c->at<int>(c->L.status));
+        hipLaunchKernelGGL((one ? k_interp_advect<2, true> : k_interp_advect<2, false>), grid, block, 0, s, D, A,
+                           U, c->at<int>(c->L.status));
     else
-        hipLaunchKernelGGL(k_interp_advect<3>, grid, block, 0, s, D, A, (const float*)c->at<float>(c->L.U),
-                           c->at<int>(c->L.status));
+        hipLaunchKernelGGL((one ? k_interp_advect<3, true> : k_interp_advect<3, false>), grid, block, 0, s, D, A,
+                           U, c->at<int>(c->L.status));
     if (!last) launch_spread(c, s, p ^ 1, want_dropped);
 }
 
@@ -505,6 +519,13 @@ int read_stamps(iblb_ctx* c, int first, int n, double& ms) {
 
 int check_droplet(const iblb_ctx* c, int d) {
     return c && d >= 0 && d < c->n;
+}
+
+// The vector lattice kernel needs every row to start on a 4-cell boundary.
+bool vector_ok(const iblb_ctx* c) {
+    for (int d = 0; d < c->n; ++d)
+        if (c->params[d].nx % 4) return false;
+    return true;
 }
 
 template <int S>
@@ -589,11 +610,7 @@ void launch_cell_sums(iblb_ctx* c) {
                            c->at<int4>(c->L.tiles_all), f, c->at<float>(c->L.U), c->at<float>(c->L.rho),
                            c->at<float>(c->L.Fout), c->at<double>(c->L.partials));
     };
-    switch (c->variant % kShapes) {
-        case 0: go(k_cell_sums<DIM, S, 256>); break;
-        case 1: go(k_cell_sums<DIM, S, 128>); break;
-        default: go(k_cell_sums<DIM, S, 64>); break;
-    }
+    go(k_cell_sums<DIM, S, 256>);  // tiles of shape 0
 }
 
 template <int DIM>
@@ -1188,7 +1205,9 @@ int iblb_run_to_rest(iblb_ctx* c, double tol, int check_every, int hold, long lo
 int iblb_set_lb_variant(iblb_ctx* c, int variant, int* variant_out) {
     if (!c) return IBLB_EINVAL;
     if (variant >= kVariants || variant < -1)
-        return fail(c, IBLB_EINVAL, "lattice-kernel variant must be -1 or 0..5");
+        return fail(c, IBLB_EINVAL, "lattice-kernel variant must be -1 or 0..7");
+    if (variant >= 0 && vector_variant(variant) && !vector_ok(c))
+        return fail(c, IBLB_EINVAL, "variants 6 and 7 need nx to be a multiple of 4 for every droplet");
     if (variant >= 0 && variant != c->variant) {
         c->variant = variant;
         c->tiles_dirty = true;
@@ -1313,6 +1332,10 @@ int iblb_autotune(iblb_ctx* c, int steps, const char* cache_path, int* chosen, d
     int best = c->variant;
     double best_ms = 1e300;
     for (int v = 0; v < kVariants; ++v) {
+        if (vector_variant(v) && !vector_ok(c)) {
+            if (ms_out) ms_out[v] = -1.0;
+            continue;
+        }
         int rc = iblb_set_lb_variant(c, v, nullptr);
         if (!rc) rc = iblb_step(c, steps);
         if (rc) {

@@ -105,12 +105,24 @@ int mlp_fail(iblb_mlp* c, int code, const std::string& msg) {
             return mlp_fail(ctx, IBLB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// With split_k, K is divided over enough workgroups to give the device at
+// least ~256 of them (at most 16 pieces, each a multiple of the LDS stage);
+// the pieces add into Cf (M x N, leading dimension N), which the caller has
+// zeroed.  Only plain products (no bias, no activation) split.
 void gemm(const iblb_mlp* c, const uint16_t* A, long long sai, long long sak, const uint16_t* B,
           long long sbk, long long sbj, float* Cf, uint16_t* Hb, long long ldc, const float* bias,
-          int M, int N, int K, int act) {
-    const dim3 grid((unsigned)mlp_cdiv(N, 64), (unsigned)mlp_cdiv(M, 64)), block(kMlpBlock);
+          int M, int N, int K, int act, bool split_k = false) {
+    const long long tiles = mlp_cdiv(N, 64) * mlp_cdiv(M, 64);
+    int splits = 1;
+    if (split_k && !bias && !act) {
+        const long long want = mlp_cdiv(256, tiles);
+        splits = (int)std::max(1LL, std::min({want, 16LL, mlp_cdiv(K, 2 * kGemmK)}));
+    }
+    const int kc = (int)(mlp_cdiv(mlp_cdiv(K, splits), kGemmK) * kGemmK);
+    splits = (int)mlp_cdiv(K, kc);
+    const dim3 grid((unsigned)mlp_cdiv(N, 64), (unsigned)mlp_cdiv(M, 64), (unsigned)splits), block(kMlpBlock);
     hipLaunchKernelGGL(k_gemm_bf16, grid, block, 0, c->stream, A, sai, sak, B, sbk, sbj, Cf, Hb, ldc,
-                       bias, M, N, K, act);
+                       bias, M, N, K, act, kc);
 }
 
 // forward pass of `batch` rows from device fp32 input x
@@ -234,11 +246,16 @@ int iblb_mlp_gradients(iblb_mlp* c, const float* d_x, const float* d_t, int batc
                        d_t, dZf, dZb, c->at<double>(Y.partial), ny);
     for (int l = L - 1; l >= 0; --l) {
         const int in = Y.w[l], out = Y.w[l + 1];
-        // bias: column sums of dZ; weights: H^T dZ; input: dZ W^T
-        hipLaunchKernelGGL(k_colsum, dim3((unsigned)mlp_cdiv(out, kMlpBlock)), dim3(kMlpBlock), 0, c->stream,
-                           (const float*)dZf, grad + Y.boff[l], batch, out);
+        // bias: column sums of dZ; weights: H^T dZ; input: dZ W^T.  The
+        // layer's weight and bias gradients (contiguous) are zeroed first:
+        // both are accumulated atomically.
+        const long long nwb = (long long)in * out + out;
+        hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)mlp_cdiv(nwb, kMlpBlock)), dim3(kMlpBlock), 0, c->stream,
+                           grad + Y.woff[l], nwb);
+        hipLaunchKernelGGL(k_colsum, dim3((unsigned)mlp_cdiv(out, 64), (unsigned)mlp_cdiv(batch, kColsumRows)),
+                           dim3(kColsumBlock), 0, c->stream, (const float*)dZf, grad + Y.boff[l], batch, out);
         gemm(c, c->at<uint16_t>(Y.H[l]), 1, in, dZb, out, 1, grad + Y.woff[l], nullptr, out, nullptr, in,
-             out, batch, 0);
+             out, batch, 0, true);
         if (l > 0) {
             gemm(c, dZb, out, 1, c->at<uint16_t>(Y.wb) + Y.woff[l], 1, out, dHf, nullptr, in, nullptr,
                  batch, in, out, 0);

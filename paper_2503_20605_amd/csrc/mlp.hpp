@@ -2,12 +2,18 @@
 // trained and evaluated with bf16 operands on the matrix cores (fp32
 // accumulation), fp32 master weights, Adam.
 //
-//   k_gemm_bf16     C = A B with A, B bf16 in any strides, fp32 result, one
-//                   32x32 tile per wavefront through v_mfma_f32_32x32x8_bf16;
-//                   epilogue: + bias, optional GELU (keeps the fp32
-//                   pre-activation and writes the bf16 activation)
+//   k_gemm_bf16     C = A B with A, B bf16 in any strides, fp32 result: a
+//                   64x64 tile of C per workgroup, operands staged through
+//                   LDS 32 k at a time (loads along whichever index is
+//                   contiguous), one 32x32 tile per wavefront through
+//                   v_mfma_f32_32x32x8_bf16; optional split of K over
+//                   workgroups (fp32 atomic accumulation); epilogue: + bias,
+//                   optional GELU (keeps the fp32 pre-activation and writes
+//                   the bf16 activation)
 //   k_gelu_back     dZ = dH * GELU'(Z), bf16 copy for the next products
-//   k_colsum        bias gradient (column sums of dZ)
+//   k_colsum        bias gradient (column sums of dZ): 64 columns x 256
+//                   rows per workgroup, reduced in LDS, then added
+//                   atomically
 //   k_mse           loss and dY = 2 (Y - T) / (B n)
 //   k_adam          Adam update of the fp32 master weights + bf16 copy
 #pragma once
@@ -36,40 +42,86 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // C(i, j) = sum_k A(i, k) B(k, j) (+ bias[j]); A(i, k) = A[i * sai + k * sak],
 // B(k, j) = B[k * sbk + j * sbj].  act = 0: C fp32 to Cf[i * ldc + j];
 // act = 1: Cf gets the pre-activation and Hb[i * ldc + j] the bf16 GELU.
-// Operands outside M x N x K read as zero.
+// Operands outside M x N x K read as zero.  With gridDim.z = S > 1 the
+// workgroups of z take the k range [z kc, (z + 1) kc) and add their partial
+// products to Cf atomically (Cf zeroed beforehand; no bias, act = 0).
 //
 // Operand and result layout of one 32x32x8 product (lane l of 64):
 //   A: row l % 32, k = 4 (l / 32) + 0..3;  B: column l % 32, same k;
 //   result register r: row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
+constexpr int kGemmK = 32;         // k per LDS stage
+constexpr int kGemmLd = kGemmK + 4;  // padded LDS row (bf16 elements)
+
 __global__ __launch_bounds__(kMlpBlock) void k_gemm_bf16(
     const uint16_t* __restrict__ A, long long sai, long long sak, const uint16_t* __restrict__ B,
     long long sbk, long long sbj, float* __restrict__ Cf, uint16_t* __restrict__ Hb, long long ldc,
-    const float* __restrict__ bias, int M, int N, int K, int act) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i0 = blockIdx.y * 64 + (wave >> 1) * 32;
-    const int j0 = blockIdx.x * 64 + (wave & 1) * 32;
-    const int ra = i0 + (lane & 31);     // row of A this lane feeds
-    const int cb = j0 + (lane & 31);     // column of B this lane feeds
-    const int kq = (lane >> 5) * 4;
+    const float* __restrict__ bias, int M, int N, int K, int act, int kc) {
+    // tiles stored k-contiguous: As[i][k], Bs[j][k]
+    __shared__ uint16_t As[64 * kGemmLd];
+    __shared__ uint16_t Bs[64 * kGemmLd];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int ib = blockIdx.y * 64, jb = blockIdx.x * 64;
+    const int kbeg = blockIdx.z * kc, kend = K < kbeg + kc ? K : kbeg + kc;
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    for (int k0 = 0; k0 < K; k0 += 8) {
-        bf16x4 a, b;
+    // each thread stages 8 elements of each operand per stage, along the
+    // operand's contiguous index so that neighbouring threads read
+    // neighbouring addresses
+    const bool a_kc = sak == 1, b_kc = sbk == 1;
+    for (int k0 = kbeg; k0 < kend; k0 += kGemmK) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int k = k0 + kq + u;
-            a[u] = (ra < M && k < K) ? (short)A[ra * sai + k * sak] : (short)0;
-            b[u] = (cb < N && k < K) ? (short)B[k * sbk + cb * sbj] : (short)0;
+        for (int u = 0; u < 8; ++u) {
+            int ii, kk;
+            if (a_kc) {  // k contiguous: thread -> row t / 4, 8 consecutive k
+                ii = t >> 2;
+                kk = (t & 3) * 8 + u;
+            } else {     // i contiguous: thread -> k t / 8, 8 consecutive rows
+                kk = t >> 3;
+                ii = (t & 7) * 8 + u;
+            }
+            const int gi = ib + ii, gk = k0 + kk;
+            As[ii * kGemmLd + kk] = (gi < M && gk < kend) ? A[gi * sai + gk * sak] : (uint16_t)0;
+            int jj;
+            if (b_kc) {
+                jj = t >> 2;
+                kk = (t & 3) * 8 + u;
+            } else {
+                kk = t >> 3;
+                jj = (t & 7) * 8 + u;
+            }
+            const int gj = jb + jj, gk2 = k0 + kk;
+            Bs[jj * kGemmLd + kk] = (gj < N && gk2 < kend) ? B[gk2 * sbk + gj * sbj] : (uint16_t)0;
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        __syncthreads();
+#pragma unroll
+        for (int s8 = 0; s8 < kGemmK; s8 += 8) {
+            const int kq = s8 + (lane >> 5) * 4;
+            bf16x4 a, b;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = (short)As[(wi + (lane & 31)) * kGemmLd + kq + u];
+                b[u] = (short)Bs[(wj + (lane & 31)) * kGemmLd + kq + u];
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
     }
-    const int j = j0 + (lane & 31);
+    const int j = jb + wj + (lane & 31);
     if (j >= N) return;
+    if (gridDim.z > 1) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = ib + wi + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            if (i < M) unsafeAtomicAdd(Cf + i * ldc + j, acc[r]);
+        }
+        return;
+    }
     const float bj = bias ? bias[j] : 0.f;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const int i = i0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int i = ib + wi + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         if (i >= M) continue;
         const float z = acc[r] + bj;
         Cf[i * ldc + j] = z;
@@ -87,13 +139,34 @@ __global__ void k_gelu_back(const float* __restrict__ dH, const float* __restric
     dZb[i] = f32_to_bf16_rne(g);
 }
 
-// out[j] = sum_i X[i * N + j], one thread per column (columns are few)
-__global__ void k_colsum(const float* __restrict__ X, float* __restrict__ out, int M, int N) {
-    const int j = blockIdx.x * kMlpBlock + threadIdx.x;
-    if (j >= N) return;
+// out[j] += sum_i X[i * N + j] (out zeroed beforehand): workgroup
+// (bx, by) takes 64 columns and rows [by kColsumRows, (by + 1) kColsumRows);
+// its 16 lane groups sum every 16th row, the 16 partial sums are added in
+// LDS and the result atomically to out.
+constexpr int kColsumBlock = 1024;
+constexpr int kColsumRows = 256;
+__global__ __launch_bounds__(kColsumBlock) void k_colsum(const float* __restrict__ X,
+                                                          float* __restrict__ out, int M, int N) {
+    __shared__ float part[16][64];
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + c;
+    const int i0 = blockIdx.y * kColsumRows, i1 = i0 + kColsumRows < M ? i0 + kColsumRows : M;
     float s = 0.f;
-    for (int i = 0; i < M; ++i) s += X[(long long)i * N + j];
-    out[j] = s;
+    if (j < N)
+        for (int i = i0 + g; i < i1; i += 16) s += X[(long long)i * N + j];
+    part[g][c] = s;
+    __syncthreads();
+    if (g == 0 && j < N) {
+        float t = 0.f;
+        for (int k = 0; k < 16; ++k) t += part[k][c];
+        unsafeAtomicAdd(out + j, t);
+    }
+}
+
+// x[i] = 0 for i < n
+__global__ void k_zero_f32(float* __restrict__ x, long long n) {
+    const long long i = (long long)blockIdx.x * kMlpBlock + threadIdx.x;
+    if (i < n) x[i] = 0.f;
 }
 
 // dY = 2 (Y - T) / n (fp32 and bf16), per-block partial sums of (Y - T)^2
