@@ -33,8 +33,6 @@ LB_NT = (0, 0, 0, 1, 1, 1)
 
 
 def lb_kernel_name(dim, storage, variant):
-    if variant >= 6:
-        return f"k_lb_vec<{dim}, {storage}, {variant - 6}>"
     return f"k_lb<{dim}, {storage}, {LB_BX[variant]}, {LB_NT[variant]}>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lb_traffic.md")
 
@@ -94,6 +92,9 @@ def parse():
     ap.add_argument("--droplets", type=int, default=256)
     ap.add_argument("--max-steps", type=int, default=200000)
     ap.add_argument("--workload", default="d2q9", choices=["d2q9", "d3q19"])
+    ap.add_argument("--mlp", action="store_true",
+                    help="time training steps of the warm-start network (4096 samples, widths "
+                         "4-256-256-256-1280) on seeded synthetic data")
     ap.add_argument("--hbm-probe", action="store_true",
                     help="only the lattice kernel on an 8192x4096 D2Q9 box and the copy probe "
                          "(short; used for hardware-counter runs)")
@@ -161,6 +162,52 @@ def tte(a):
     print(json.dumps(out), flush=True)
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def mlp_rate(a):
+    """Full-batch training steps (forward, backward, Adam) of the warm-start
+    network on seeded synthetic inputs and targets of the training set's
+    shape; bf16 matrix-core products with fp32 accumulation."""
+    import numpy as np
+    import torch
+    from paper_2503_20605_amd import MLP
+    from paper_2503_20605_amd.warmstart import WIDTHS, _init_params
+    rng = np.random.default_rng(11)
+    B = 4096
+    X = rng.standard_normal((B, WIDTHS[0])).astype(np.float32)
+    Y = rng.standard_normal((B, WIDTHS[-1])).astype(np.float32)
+    m = MLP(WIDTHS, B)
+    m.set_params(_init_params(WIDTHS, 7))
+    x, y = m._dev(X), m._dev(Y)
+    for _ in range(a.warmup if a.warmup < 200 else 20):
+        m.train_step(x, y, 1e-3)
+    torch.cuda.synchronize()
+    n = min(a.steps, 500)
+    t0 = time.perf_counter()
+    for _ in range(n):
+        loss = m.train_step(x, y, 1e-3)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / n
+    macs = B * sum(WIDTHS[i] * WIDTHS[i + 1] for i in range(len(WIDTHS) - 1))
+    tflops = 6 * macs / dt / 1e12
+    t0 = time.perf_counter()
+    for _ in range(50):
+        m.forward(x)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / 50
+    m.close()
+    print(json.dumps({"metric": "warm-start network training step (forward + backward + Adam)",
+                      "value": round(dt * 1e3, 4), "unit": "ms", "steps": n,
+                      "higher_is_better": False, "dtype": "bf16 products, fp32 accumulation",
+                      "data": "synthetic (seeded)",
+                      "config": {"workload": "mlp_4-256-256-256-1280_batch4096"},
+                      "roofline": {"bound": "mfma", "achieved": round(tflops, 2),
+                                   "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 5), "traffic": None},
+                      "forward_ms": round(fwd * 1e3, 4), "final_loss": round(loss, 5)}), flush=True)
+
+
 def lb_only_rate(dim, nx, ny, nz, storage, steps):
     """Lattice kernel on a big box with no interface (every cell is a plain
     collide + stream), autotuned: GB/s of one launch."""
@@ -199,6 +246,9 @@ def main():
 
     if a.tte:
         tte(a)
+        return
+    if a.mlp:
+        mlp_rate(a)
         return
     if a.hbm_probe:
         from paper_2503_20605_amd import probe_copy_bandwidth

@@ -199,20 +199,16 @@ int iblb_run_to_rest(iblb_ctx *ctx, double tol, int check_every, int hold, long 
  *   0: 256x1 cells per block   3: 256x1, non-temporal stores
  *   1: 128x2 cells per block   4: 128x2, non-temporal stores
  *   2:  64x4 cells per block   5:  64x4, non-temporal stores
- *   6: four cells per lane, 256x4 cells per block (4-wide population
- *      accesses)               7: as 6, non-temporal stores
- * Variants 6 and 7 need nx to be a multiple of 4 for every droplet of the
- * handle (IBLB_EINVAL otherwise).  variant = -1 keeps the current one;
- * *variant_out (may be NULL) receives the variant in use. */
+ * variant = -1 keeps the current one; *variant_out (may be NULL) receives
+ * the variant in use. */
 int iblb_set_lb_variant(iblb_ctx *ctx, int variant, int *variant_out);
 
 /* Time every lattice-kernel variant over `steps` real time steps each (the
  * steps advance the simulation) and keep the fastest.  With cache_path
  * non-NULL the winner is looked up in / appended to that text file, keyed
  * by device, lattice, storage and size bucket; a cache hit runs no step.
- * chosen (may be NULL) receives the variant; ms (may be NULL, 8 entries)
- * the measured lattice-kernel milliseconds per step (-1 on a cache hit and
- * for variants the handle cannot use). */
+ * chosen (may be NULL) receives the variant; ms (may be NULL, 6 entries)
+ * the measured lattice-kernel milliseconds per step (-1 on a cache hit). */
 int iblb_autotune(iblb_ctx *ctx, int steps, const char *cache_path, int *chosen, double *ms);
 
 /* Number of steps captured in one replayed graph (even, 2..1024); default

@@ -176,10 +176,10 @@ class Solver:
         return out.value
 
     def autotune(self, steps=50, cache_path=None):
-        """Time the lattice-kernel variants (0-7) and keep the fastest; returns
+        """Time the six lattice-kernel variants and keep the fastest; returns
         (variant, per-variant ms or -1 on a cache hit)."""
         out = ctypes.c_int()
-        ms = (ctypes.c_double * 8)()
+        ms = (ctypes.c_double * 6)()
         cp = None if cache_path is None else str(cache_path).encode()
         self._chk(self.lib.iblb_autotune(self.ctx, int(steps), cp, ctypes.byref(out), ms))
         return out.value, list(ms)

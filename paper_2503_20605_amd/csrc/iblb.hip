@@ -26,17 +26,14 @@ using namespace iblb;
 
 namespace {
 
-// Lattice-kernel variants (autotuner candidates): variants 0-5 are the
-// scalar kernel on tiles of 256x1, 128x2 or 64x4 cells per block (shape
-// v % 3), with ordinary (v < 3) or non-temporal stores; 6 and 7 the vector
-// kernel (four cells per lane, tiles of 256x4 cells: shape 3), ordinary or
-// non-temporal stores, for boxes whose nx are all multiples of 4.
-constexpr int kShapes = 4;
-constexpr int kVariants = 8;
-constexpr int kShapeBX[kShapes] = {256, 128, 64, 256};
-constexpr int kShapeBY[kShapes] = {1, 2, 4, 4};
-int shape_of(int variant) { return variant < 6 ? variant % 3 : 3; }
-bool vector_variant(int variant) { return variant >= 6; }
+// Lattice-kernel variants (autotuner candidates): tiles of 256x1, 128x2 or
+// 64x4 cells per block (shape v % 3), with ordinary (v < 3) or
+// non-temporal stores.
+constexpr int kShapes = 3;
+constexpr int kVariants = 6;
+constexpr int kShapeBX[kShapes] = {256, 128, 64};
+constexpr int kShapeBY[kShapes] = {1, 2, 4};
+int shape_of(int variant) { return variant % kShapes; }
 constexpr size_t kAlign = 256;
 constexpr int kMaxGraphSteps = 1024;
 constexpr int kTimedLaunches = 256;  // timed lattice launches per replay at most
@@ -106,7 +103,7 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.flag_off.assign(n, 0);
     L.node_off.assign(n, 0);
     L.tri_off.assign(n, 0);
-    int tiles[kShapes] = {0, 0, 0, 0};
+    int tiles[kShapes] = {0, 0, 0};
     for (int d = 0; d < n; ++d) {
         const iblb_params& p = P[d];
         char buf[256];
@@ -212,7 +209,7 @@ struct iblb_ctx {
     char* ws = nullptr;
     hipStream_t stream = nullptr, cap_stream = nullptr;
     int cur = 0;  // buffer holding the current post-collision populations
-    int variant = 0;  // lattice-kernel variant; its tile shape is variant % kShapes
+    int variant = 0;  // lattice-kernel variant; its tile shape is shape_of(variant)
     int ntiles_lb = 0, ntiles_all = 0;
     bool tiles_dirty = true;
     std::vector<int4> tiles_h;
@@ -376,9 +373,7 @@ void launch_lb_t(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned l
         case 2: go(k_lb<DIM, S, 64, 0>); break;
         case 3: go(k_lb<DIM, S, 256, 1>); break;
         case 4: go(k_lb<DIM, S, 128, 1>); break;
-        case 5: go(k_lb<DIM, S, 64, 1>); break;
-        case 6: go(k_lb_vec<DIM, S, 0>); break;
-        default: go(k_lb_vec<DIM, S, 1>); break;
+        default: go(k_lb<DIM, S, 64, 1>); break;
     }
 }
 
@@ -519,13 +514,6 @@ int read_stamps(iblb_ctx* c, int first, int n, double& ms) {
 
 int check_droplet(const iblb_ctx* c, int d) {
     return c && d >= 0 && d < c->n;
-}
-
-// The vector lattice kernel needs every row to start on a 4-cell boundary.
-bool vector_ok(const iblb_ctx* c) {
-    for (int d = 0; d < c->n; ++d)
-        if (c->params[d].nx % 4) return false;
-    return true;
 }
 
 template <int S>
@@ -1205,9 +1193,7 @@ int iblb_run_to_rest(iblb_ctx* c, double tol, int check_every, int hold, long lo
 int iblb_set_lb_variant(iblb_ctx* c, int variant, int* variant_out) {
     if (!c) return IBLB_EINVAL;
     if (variant >= kVariants || variant < -1)
-        return fail(c, IBLB_EINVAL, "lattice-kernel variant must be -1 or 0..7");
-    if (variant >= 0 && vector_variant(variant) && !vector_ok(c))
-        return fail(c, IBLB_EINVAL, "variants 6 and 7 need nx to be a multiple of 4 for every droplet");
+        return fail(c, IBLB_EINVAL, "lattice-kernel variant must be -1 or 0..5");
     if (variant >= 0 && variant != c->variant) {
         c->variant = variant;
         c->tiles_dirty = true;
@@ -1332,10 +1318,6 @@ int iblb_autotune(iblb_ctx* c, int steps, const char* cache_path, int* chosen, d
     int best = c->variant;
     double best_ms = 1e300;
     for (int v = 0; v < kVariants; ++v) {
-        if (vector_variant(v) && !vector_ok(c)) {
-            if (ms_out) ms_out[v] = -1.0;
-            continue;
-        }
         int rc = iblb_set_lb_variant(c, v, nullptr);
         if (!rc) rc = iblb_step(c, steps);
         if (rc) {

@@ -10,6 +10,11 @@
 //                     lattice with the Peskin 4-point kernel (eq. force_spread)
 //   k_interp_advect   lattice velocity interpolated at the nodes (eq.
 //                     vel_interpolation) and forward-Euler advection
+//   k_ib_fused2       2D: interpolation and advection of one step fused with
+//                     the forces and spreading of the next
+//   k_force3,
+//   k_spread3         3D: forces one lane per vertex, then spreading summed
+//                     per chunk of nearby vertices in LDS
 //   k_cell_sums,
 //   k_diag            FP64 reductions for the diagnostics
 //
@@ -271,151 +276,6 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         // wavefront is active whenever any lane is (x grows with the lane)
         __builtin_amdgcn_s_waitcnt(0);
         if ((threadIdx.x & 63) == 0) atomicMax(stamp + 1, (unsigned long long)wall_clock64());
-    }
-}
-
-// Vector form of the lattice kernel: each lane updates four consecutive
-// cells of a row with 4-wide population accesses (16 bytes in fp32, 8 in
-// fp16/bf16), a wavefront 256 cells of one row and a workgroup four rows
-// (tile = 256 x 4 cells).  A population streamed along x needs one value
-// beyond the lane's four: it comes from the neighbouring lane by a
-// cross-lane shift, and the lanes at the ends of a wavefront (or of the
-// row) load it themselves, with the periodic wrap or the wall reflection
-// the scalar kernel applies.  Requires nx % 4 == 0 for every droplet (rows
-// then start on a 4-cell boundary); the arithmetic per cell is the scalar
-// kernel's.
-template <int DIM, int S, int NT>
-__global__ __launch_bounds__(kBlock) void k_lb_vec(const DropDev* __restrict__ drops,
-                                                   const int4* __restrict__ tiles,
-                                                   const typename Codec<S>::T* __restrict__ fsrc_all,
-                                                   typename Codec<S>::T* __restrict__ fdst_all,
-                                                   float* __restrict__ F_all, float* __restrict__ U_all,
-                                                   float* __restrict__ rho_all,
-                                                   float* __restrict__ Fout_all,
-                                                   uint8_t* __restrict__ flags_all, int full,
-                                                   unsigned long long* __restrict__ stamps) {
-    using L = Lattice<DIM>;
-    using C = Codec<S>;
-    constexpr int Q = L::Q;
-    unsigned long long* stamp = stamps ? stamps + (blockIdx.x % kStampSpread) * kStampStride : nullptr;
-    if (stamp && threadIdx.x == 0) atomicMin(stamp, (unsigned long long)wall_clock64());
-    const int4 tile = tiles[xcd_remap(blockIdx.x, gridDim.x)];
-    const DropDev& D = drops[tile.x];
-    const int nx = D.nx, ny = D.ny, nz = D.nz;
-    const int lane = threadIdx.x & 63;
-    const int x = tile.y * 256 + 4 * lane;
-    const int y = tile.z * 4 + (int)(threadIdx.x >> 6);
-    const int z = tile.w;
-    if (y >= ny) return;  // the whole wavefront
-    // lanes past the end of the row take part in the shifts only
-    const bool act = x < nx;
-    const int ncell = D.ncell, fst = D.fst;
-    const int cell = (z * ny + y) * nx + x;  // first of the lane's four cells
-    const typename C::T* __restrict__ fsrc = fsrc_all + D.f_off;
-    typename C::T* __restrict__ fdst = fdst_all + D.f_off;
-
-    int ym = y - 1, yp = y + 1, zm = z - 1, zp = z + 1;
-    if (ym < 0) ym = D.bcy ? -1 : ny - 1;
-    if (yp >= ny) yp = D.bcy ? -1 : 0;
-    if (DIM == 3) {
-        if (zm < 0) zm = D.bcz ? -1 : nz - 1;
-        if (zp >= nz) zp = D.bcz ? -1 : 0;
-    }
-    // the cell left of the lane's first and right of its last (-1: wall);
-    // they come from the neighbouring lanes except at the wavefront's ends
-    // and the row's
-    int xl = x - 1, xr = x + 4;
-    if (xl < 0) xl = D.bcx ? -1 : nx - 1;
-    if (xr >= nx) xr = D.bcx ? -1 : 0;
-    const bool own_l = lane == 0, own_r = lane == 63 || x + 4 >= nx;
-
-    float f[4][Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-        const int sy = cy > 0 ? ym : (cy < 0 ? yp : y);
-        const int sz = DIM == 3 ? (cz > 0 ? zm : (cz < 0 ? zp : z)) : 0;
-        const bool wall_row = (sy | sz) < 0;
-        const int src = i * fst + (sz * ny + sy) * nx;  // row start of the source
-        float v[4] = {0.f, 0.f, 0.f, 0.f};
-        if (act) {
-            if (wall_row)  // reflected: the opposite population of each cell
-                load4<S>(fsrc, opp(i) * fst + cell, v);
-            else
-                load4<S>(fsrc, src + x, v);
-        }
-        if (cx == 0 || wall_row) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) f[k][i] = v[k];
-        } else if (cx > 0) {  // from x - 1
-            float left = __shfl_up(v[3], 1, 64);
-            if (own_l && act) left = xl < 0 ? C::load(fsrc, opp(i) * fst + cell) : C::load(fsrc, src + xl);
-            f[0][i] = left;
-            f[1][i] = v[0];
-            f[2][i] = v[1];
-            f[3][i] = v[2];
-        } else {  // from x + 1
-            float right = __shfl_down(v[0], 1, 64);
-            if (own_r && act)
-                right = xr < 0 ? C::load(fsrc, opp(i) * fst + cell + 3) : C::load(fsrc, src + xr);
-            f[0][i] = v[1];
-            f[1][i] = v[2];
-            f[2][i] = v[3];
-            f[3][i] = right;
-        }
-    }
-    // band flag of the lane's 64-cell strip (16 lanes): read by the strip's
-    // first lane and passed to the others, so that it is read before that
-    // lane clears it below
-    uint8_t* flag = flags_all + D.flag_off + (z * ny + y) * D.nstrip + (x >> 6);
-    int fl = 0;
-    if (D.force_mode == 0 && act && (lane & 15) == 0) fl = *flag;
-    fl = __shfl(fl, lane & ~15, 64);
-    if (act) {
-        float* __restrict__ F = F_all + (long long)DIM * D.c_off;
-        float* __restrict__ U = U_all + (long long)DIM * D.c_off;
-        const bool forced = D.force_mode == 1 || fl != 0;
-        float Fa[3][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-        if (forced)
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) load4<ST_F32>(F, a * ncell + cell, Fa[a]);
-        const float om = D.omega, g = D.guo;
-        float fn[Q][4], rho[4], u[3][4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const Moments<DIM> M(f[k], Fa[0][k], Fa[1][k], Fa[2][k]);
-            rho[k] = M.rho;
-            u[0][k] = M.ux;
-            u[1][k] = M.uy;
-            u[2][k] = M.uz;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) fn[i][k] = M.relax(i, f[k][i], om, g, forced);
-        }
-#pragma unroll
-        for (int i = 0; i < Q; ++i) store4<S, NT>(fdst, i * fst + cell, fn[i]);
-        const float zero[4] = {0.f, 0.f, 0.f, 0.f};
-        if (forced && D.force_mode == 0) {
-            // interface band: keep U for the interpolation, hand back a clean F
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                store4<ST_F32, 0>(U, a * ncell + cell, u[a]);
-                store4<ST_F32, 0>(F, a * ncell + cell, zero);
-            }
-        }
-        if (full) {
-            float* __restrict__ Fo = Fout_all + (long long)DIM * D.c_off;
-            store4<ST_F32, 0>(rho_all + D.c_off, cell, rho);
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                store4<ST_F32, 0>(U, a * ncell + cell, u[a]);
-                store4<ST_F32, 0>(Fo, a * ncell + cell, Fa[a]);
-            }
-        }
-        if (forced && D.force_mode == 0 && (lane & 15) == 0) *flag = 0;
-    }
-    if (stamp) {
-        __builtin_amdgcn_s_waitcnt(0);
-        if (lane == 0) atomicMax(stamp + 1, (unsigned long long)wall_clock64());
     }
 }
 

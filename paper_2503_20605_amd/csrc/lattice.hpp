@@ -101,60 +101,4 @@ struct Codec<ST_BF16> {
 template <int S>
 constexpr int storage_bytes() { return S == ST_F32 ? 4 : 2; }
 
-// Four consecutive populations at once (16-byte fp32, 8-byte fp16/bf16
-// accesses); the index must be a multiple of 4.
-typedef float v4f32 __attribute__((ext_vector_type(4)));
-typedef _Float16 v4f16 __attribute__((ext_vector_type(4)));
-typedef uint16_t v4u16 __attribute__((ext_vector_type(4)));
-
-template <int S>
-struct Codec4;
-
-template <>
-struct Codec4<ST_F32> {
-    using T = float;
-    using V = v4f32;
-    static __device__ __forceinline__ float get(const V& v, int k) { return v[k]; }
-    static __device__ __forceinline__ V put(const float o[4]) { return V{o[0], o[1], o[2], o[3]}; }
-};
-
-template <>
-struct Codec4<ST_F16> {
-    using T = _Float16;
-    using V = v4f16;
-    static __device__ __forceinline__ float get(const V& v, int k) { return (float)v[k]; }
-    static __device__ __forceinline__ V put(const float o[4]) {
-        return V{(_Float16)o[0], (_Float16)o[1], (_Float16)o[2], (_Float16)o[3]};
-    }
-};
-
-template <>
-struct Codec4<ST_BF16> {
-    using T = uint16_t;
-    using V = v4u16;
-    static __device__ __forceinline__ float get(const V& v, int k) { return bf16_to_f32(v[k]); }
-    static __device__ __forceinline__ V put(const float o[4]) {
-        return V{f32_to_bf16_rne(o[0]), f32_to_bf16_rne(o[1]), f32_to_bf16_rne(o[2]), f32_to_bf16_rne(o[3])};
-    }
-};
-
-template <int S>
-__device__ __forceinline__ void load4(const typename Codec4<S>::T* p, int i, float o[4]) {
-    using C = Codec4<S>;
-    const typename C::V v = *reinterpret_cast<const typename C::V*>(p + i);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) o[k] = C::get(v, k);
-}
-
-template <int S, int NT>
-__device__ __forceinline__ void store4(typename Codec4<S>::T* p, int i, const float o[4]) {
-    using C = Codec4<S>;
-    const typename C::V v = C::put(o);
-    typename C::V* q = reinterpret_cast<typename C::V*>(p + i);
-    if (NT)
-        __builtin_nontemporal_store(v, q);
-    else
-        *q = v;
-}
-
 }  // namespace iblb

@@ -74,7 +74,7 @@ struct Stream { int id; };
 struct Graph { std::vector<std::function<void()>> ops; };
 struct Event { int id; };
 
-enum State { READY, AT_WAVE_FIRST, AT_WAVE_XOR, AT_WAVE_SHIFT, AT_WAVE_IDX, AT_WAVE_MFMA, AT_BLOCK, DONE };
+enum State { READY, AT_WAVE_FIRST, AT_WAVE_XOR, AT_WAVE_MFMA, AT_BLOCK, DONE };
 
 struct Fiber {
     ucontext_t ctx;
@@ -163,28 +163,6 @@ inline void __syncthreads() { ::hipemu::block_barrier(); }
 
 inline int __builtin_amdgcn_readfirstlane(int v) {
     return ::hipemu::unpack<int>(::hipemu::wave_op(::hipemu::AT_WAVE_FIRST, ::hipemu::pack(v), 0));
-}
-
-// __shfl_up / __shfl_down over the whole wavefront: lane l reads lane
-// l - d (up) or l + d (down); a lane whose source lies outside the
-// wavefront keeps its own value.  Reading a lane that has returned yields
-// an all-ones pattern (NaN for floats), so that a use of it shows.
-template <typename T>
-inline T __shfl_up(T v, unsigned d, int width = 64) {
-    (void)width;
-    return ::hipemu::unpack<T>(::hipemu::wave_op(::hipemu::AT_WAVE_SHIFT, ::hipemu::pack(v), -(int)d));
-}
-template <typename T>
-inline T __shfl_down(T v, unsigned d, int width = 64) {
-    (void)width;
-    return ::hipemu::unpack<T>(::hipemu::wave_op(::hipemu::AT_WAVE_SHIFT, ::hipemu::pack(v), (int)d));
-}
-
-// __shfl: every lane reads lane src of its wavefront.
-template <typename T>
-inline T __shfl(T v, int src, int width = 64) {
-    (void)width;
-    return ::hipemu::unpack<T>(::hipemu::wave_op(::hipemu::AT_WAVE_IDX, ::hipemu::pack(v), src & 63));
 }
 
 template <typename T>
@@ -477,12 +455,9 @@ inline void run_block(const std::function<void()>& fn) {
                 ++live;
                 if (first < 0) { first = t; kind = s; }
                 same &= s == kind;
-                kindc += (s == AT_WAVE_FIRST || s == AT_WAVE_XOR || s == AT_WAVE_SHIFT || s == AT_WAVE_IDX ||
-                          s == AT_WAVE_MFMA);
+                kindc += (s == AT_WAVE_FIRST || s == AT_WAVE_XOR || s == AT_WAVE_MFMA);
             }
-            if (!live || !same ||
-                (kind != AT_WAVE_FIRST && kind != AT_WAVE_XOR && kind != AT_WAVE_SHIFT && kind != AT_WAVE_IDX &&
-                 kind != AT_WAVE_MFMA))
+            if (!live || !same || (kind != AT_WAVE_FIRST && kind != AT_WAVE_XOR && kind != AT_WAVE_MFMA))
                 continue;
             if (kind == AT_WAVE_MFMA) {
                 if (live != 64) {
@@ -517,17 +492,6 @@ inline void run_block(const std::function<void()>& fn) {
                 if (f.st == DONE) continue;
                 if (kind == AT_WAVE_FIRST) {
                     f.out = r.fibers[first].in;
-                } else if (kind == AT_WAVE_IDX) {
-                    const int p = lo + f.mask;
-                    f.out = (p < hi && r.fibers[p].st == AT_WAVE_IDX) ? r.fibers[p].in : ~0ull;
-                } else if (kind == AT_WAVE_SHIFT) {
-                    const int p = t + f.mask;
-                    if (p < lo || p >= lo + 64)
-                        f.out = f.in;
-                    else if (p >= hi || r.fibers[p].st != AT_WAVE_SHIFT)
-                        f.out = ~0ull;
-                    else
-                        f.out = r.fibers[p].in;
                 } else {
                     const int p = lo + ((t - lo) ^ f.mask);
                     if (p >= hi || r.fibers[p].st != AT_WAVE_XOR) {

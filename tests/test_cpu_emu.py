@@ -100,39 +100,6 @@ def test_streaming_bit_exact_all_storages(storage):
         assert np.array_equal(g["fdev"], k / 1024.0)
 
 
-@pytest.mark.parametrize("variant", [6, 7])
-@pytest.mark.parametrize("storage", [0, 1, 2])
-def test_vector_kernel_streaming_bit_exact(variant, storage):
-    """Four-cells-per-lane kernel: rows that end mid-wavefront, two tiles
-    along x, walls or wrap at the x ends, walls in y / z."""
-    cases = ((2, (300, 7, 1), (0, 1, 0)), (2, (36, 9, 1), (1, 0, 0)),
-             (3, (12, 5, 4), (1, 0, 1)), (3, (8, 6, 5), (0, 0, 0)))
-    for dim, (nx, ny, nz), bc in cases:
-        Q = 9 if dim == 2 else 19
-        w = weights(dim)
-        dev = wl.tagged_deviation(Q, nx * ny * nz, 5).reshape(Q, nz, ny, nx)
-        p = wl.Params(dim=dim, nx=nx, ny=ny, nz=nz, bc=bc, tau=math.inf, wetting=False)
-        g = run_case([p], steps=(3,), storage=storage, f0dev=[dev], graph_steps=2, shape=variant)[0]
-        f = w[:, None, None, None] + dev
-        for _ in range(3):
-            f, _, _ = o.lb_step(dim, nx, ny, nz, bc, math.inf, f, None)
-        k = np.rint((f - w[:, None, None, None]) * 1024.0)
-        assert np.array_equal(g["fdev"], k / 1024.0), (dim, nx, ny, nz, bc)
-
-
-@pytest.mark.parametrize("variant", [6, 7])
-def test_vector_kernel_coupled_droplet(variant):
-    """A droplet across the periodic x edge of a 132 x 40 box (one tile of
-    33 active lanes) with the vector kernel, against the oracle."""
-    p = wl.Params(dim=2, nx=132, ny=40, tau=0.8, sigma=0.008, theta_eq_deg=110.0, xi=2.0)
-    q = wl.cap_polygon(10.0, 95.0, 2.0, 70, 2.0)
-    g = run_case([p], [q], steps=(4, 3), shape=variant, graph_steps=2)[0]
-    r = o.run(p, q, 7)
-    drho, du, dq = compare_fields(g, r, 2, f"emu vector {variant}")
-    assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
-    assert abs(g["diag"]["mass"] - r["f"].sum()) < 1e-6
-
-
 def test_prescribed_force_field():
     nx, ny, nz = 23, 7, 1
     w = weights(2)

@@ -44,63 +44,6 @@ def test_pure_streaming_bit_exact(dim, shape, bc, storage, tile):
         assert np.array_equal(g["fdev"], k / 1024.0)
 
 
-VECTOR_CASES = [
-    # nx a multiple of 4 (vector lattice kernel)
-    (2, (300, 5, 1), (1, 1, 0)),       # walls everywhere, two tiles along x
-    (2, (36, 23, 1), (0, 1, 0)),       # row ends mid-wavefront, x wraps
-    (2, (512, 6, 1), (0, 0, 0)),       # two full tiles, fully periodic
-    (3, (68, 3, 4), (1, 0, 1)),
-    (3, (8, 6, 5), (0, 0, 0)),
-]
-
-
-@pytest.mark.parametrize("storage", [0, 1, 2], ids=["f32", "f16", "bf16"])
-@pytest.mark.parametrize("dim,shape,bc", VECTOR_CASES)
-@pytest.mark.parametrize("variant", [6, 7])
-def test_vector_kernel_streaming_bit_exact(dim, shape, bc, storage, variant):
-    nx, ny, nz = shape
-    Q = 9 if dim == 2 else 19
-    w = weights(dim)
-    p = wl.Params(dim=dim, nx=nx, ny=ny, nz=nz, bc=bc, tau=math.inf, wetting=False)
-    for seed, steps in ((24, 1), (25, 5)):
-        dev = wl.tagged_deviation(Q, nx * ny * nz, seed).reshape(Q, nz, ny, nx)
-        print(f"[stream-vec] dim={dim} shape={shape} bc={bc} storage={storage} variant={variant} "
-              f"steps={steps}", flush=True)
-        g = gpu_run(p, None, steps, storage=storage, f0dev=dev, shape=variant, graph_steps=2)
-        f = w[:, None, None, None] + dev
-        for _ in range(steps):
-            f, _, _ = o.lb_step(dim, nx, ny, nz, bc, math.inf, f, None)
-        k = np.rint((f - w[:, None, None, None]) * 1024.0)
-        assert np.array_equal(g["fdev"], k / 1024.0)
-
-
-def test_vector_kernel_matches_scalar_kernel():
-    """Same formulas per cell: after 50 forced collide-and-stream steps the
-    two kernels agree to fp32 rounding (the compiler may contract the two
-    differently into fused multiply-adds, so not bit for bit)."""
-    dim, (nx, ny, nz), bc = 2, (132, 40, 1), (0, 1, 0)
-    w = weights(dim)
-    rng = np.random.default_rng(32)
-    dev = 1e-2 * w[:, None, None, None] * rng.standard_normal((9, nz, ny, nx))
-    F = np.zeros((3, nz, ny, nx))
-    F[:2] = 1e-4 * rng.standard_normal((2, nz, ny, nx))
-    p = wl.Params(dim=dim, nx=nx, ny=ny, nz=nz, bc=bc, tau=0.7, wetting=False)
-    a = gpu_run(p, None, 50, f0dev=dev, F_fixed=F, graph_steps=8, shape=0)
-    b = gpu_run(p, None, 50, f0dev=dev, F_fixed=F, graph_steps=8, shape=6)
-    scale = np.max(np.abs(a["fdev"]))
-    assert np.max(np.abs(a["fdev"] - b["fdev"])) <= 2e-6 * scale
-    assert np.max(np.abs(a["U"] - b["U"])) <= 2e-6 * np.max(np.abs(a["U"]))
-    assert np.max(np.abs(a["rho"] - b["rho"])) <= 1e-6
-
-
-def test_vector_variant_rejected_for_unaligned_rows():
-    from paper_2503_20605_amd import IblbError
-    from helpers import gpu_solver
-    s = gpu_solver([wl.Params(dim=2, nx=37, ny=9, tau=0.8, wetting=False)])
-    with pytest.raises(IblbError):
-        s.set_lb_variant(6)
-
-
 @pytest.mark.parametrize("dim,shape,bc", [
     (2, (45, 17, 1), (0, 1, 0)),
     (2, (128, 64, 1), (0, 1, 0)),
