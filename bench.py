@@ -158,8 +158,24 @@ def tte(a):
                                   "converged_in_both": len(both),
                                   "both_max": round(float(dth_both.max()), 4),
                                   "both_within_1deg": int((dth_both < 1.0).sum())},
+           "paired_at_rest": paired_work(draws, res["f32"]["steps"], res["f16"]["steps"]),
            "max_steps": a.max_steps}
     print(json.dumps(out), flush=True)
+
+
+def paired_work(draws, steps_ref, steps_new):
+    """Droplets at rest in both runs: median per-droplet step ratio (new /
+    reference) and the ratio of lattice work (cells x steps) summed over
+    them."""
+    import numpy as np
+    both = [i for i in range(len(draws)) if steps_ref[i] > 0 and steps_new[i] > 0]
+    if not both:
+        return {"droplets": 0}
+    cells = np.array([draws[i].params.nx * draws[i].params.ny for i in both], dtype=np.float64)
+    r = np.array([steps_ref[i] for i in both], dtype=np.float64)
+    n = np.array([steps_new[i] for i in both], dtype=np.float64)
+    return {"droplets": len(both), "median_step_ratio": round(float(np.median(n / r)), 4),
+            "work_ratio": round(float((cells * n).sum() / (cells * r).sum()), 4)}
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0

@@ -377,6 +377,15 @@ def main(argv):
                  "theta_vs_plain_within_1deg": int((dth < 1.0).sum()),
                  "theta_vs_plain_compared": len(both),
                  "theta_vs_plain_max_deg": round(float(dth.max()), 3) if len(dth) else None}
+            both_rest = [i for i in conv if plain["steps"][i] > 0]
+            if both_rest:
+                ratio = [r["steps"][i] / plain["steps"][i] for i in both_rest]
+                cells = [draws[i].params.nx * draws[i].params.ny for i in both_rest]
+                e["paired_at_rest"] = len(both_rest)
+                e["paired_median_step_ratio"] = round(float(np.median(ratio)), 4)
+                e["paired_work_ratio"] = round(
+                    sum(c * r["steps"][i] for c, i in zip(cells, both_rest))
+                    / sum(c * plain["steps"][i] for c, i in zip(cells, both_rest)), 4)
             if r["starts"] is not None:
                 errs = []
                 for i, w in enumerate(draws):

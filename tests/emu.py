@@ -6,6 +6,8 @@ import os
 import subprocess
 import sys
 import tempfile
+import threading
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -19,12 +21,23 @@ def _params_struct(p):
     return params_from(p)
 
 
+_build_lock = threading.Lock()
+
+
+def run_cases(jobs):
+    """run_case for each dict of keyword arguments in jobs, as concurrent
+    processes; returns the results in order."""
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
+        return list(ex.map(lambda kw: run_case(**kw), jobs))
+
+
 def run_case(params_list, nodes_list=None, tris_list=None, steps=(1,), storage=0,
              graph_steps=None, shape=None, f0dev=None, forces=None, timing=False,
              inactive=(), rest=None, timeout=600, direct_chunks=False):
     import build as emu_build
     from paper_2503_20605_amd._lib import iblb_diag
-    exe = emu_build.build(direct=direct_chunks)
+    with _build_lock:
+        exe = emu_build.build(direct=direct_chunks)
     n = len(params_list)
     nodes_list = nodes_list or [None] * n
     tris_list = tris_list or [None] * n

@@ -13,16 +13,75 @@ import pytest
 
 import oracle as o
 import workloads as wl
-from emu import run_case
+from emu import run_case, run_cases
 from helpers import compare_fields, oracle_dev, weights
+
+# The longest cases (tens of seconds each under the sanitizers) start as
+# background processes when the module's first test runs; their tests
+# collect the results.
+
+
+def _rest_case():
+    ps = [wl.Params(dim=2, nx=40, ny=24, tau=1.0, sigma=0.004, theta_eq_deg=90.0, xi=2.0),
+          wl.Params(dim=2, nx=48, ny=20, tau=0.8, sigma=0.02, theta_eq_deg=60.0, xi=2.0),
+          wl.Params(dim=2, nx=32, ny=8, tau=0.9, wetting=False)]
+    qs = [wl.cap_polygon(6.0, 90.0, 2.0, 40, 20.0), wl.cap_polygon(6.0, 90.0, 2.0, 40, 24.0), None]
+    return ps, qs
+
+
+def _tiny3d_case():
+    p = wl.Params(dim=3, nx=20, ny=18, nz=12, bc=(0, 0, 1), tau=0.8, sigma=0.005,
+                  theta_eq_deg=70.0, xi=2.0)
+    V, T = wl.cap_mesh(5.0, 90.0, 2.0, 3, (10.0, 9.0))
+    return p, V, T
+
+
+def _coarse3d_case():
+    p = wl.Params(dim=3, nx=24, ny=22, nz=14, bc=(0, 0, 1), tau=0.9, sigma=0.006,
+                  theta_eq_deg=100.0, xi=2.0)
+    V, T = wl.cap_mesh(9.0, 90.0, 2.0, 4, (1.0, 11.0))
+    return p, V, T
+
+
+def _blowup_case():
+    p = wl.Params(dim=2, nx=64, ny=32, tau=1.0, sigma=50.0, theta_eq_deg=60.0, xi=2.0)
+    q = wl.cap_polygon(8.0, 90.0, 2.0, 40, 32.0)
+    return p, q
+
+
+def _background_jobs():
+    ps, qs = _rest_case()
+    p3, V3, T3 = _tiny3d_case()
+    pc, Vc, Tc = _coarse3d_case()
+    pb, qb = _blowup_case()
+    return {
+        "rest": dict(params_list=ps, nodes_list=qs, steps=(0,), rest=(2e-3, 4, 2, 60), graph_steps=2),
+        "tiny3d": dict(params_list=[p3], nodes_list=[V3], tris_list=[T3], steps=(3,), graph_steps=2),
+        "coarse3d": dict(params_list=[pc], nodes_list=[Vc], tris_list=[Tc], steps=(2,), graph_steps=2),
+        "coarse3d_direct": dict(params_list=[pc], nodes_list=[Vc], tris_list=[Tc], steps=(2,),
+                                graph_steps=2, direct_chunks=True),
+        "blowup": dict(params_list=[pb], nodes_list=[qb], steps=(50,)),
+    }
+
+
+@pytest.fixture(scope="module", autouse=True)
+def background():
+    from concurrent.futures import ThreadPoolExecutor
+    jobs = _background_jobs()
+    with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        yield {k: ex.submit(run_case, **kw) for k, kw in jobs.items()}
 
 
 def test_droplet_2d_graph_and_tiles():
+    """Three tile shapes; graph replays of 2 steps plus direct launches, the
+    timed schedule, and no graphs."""
     W = wl.droplet_2d_small()
-    for shape, gs in ((0, 4), (4, 2), (2, 0)):
-        g = run_case([W.params], [W.nodes], steps=(5, 4), shape=shape, graph_steps=gs,
-                     timing=(shape == 4))[0]
-        r = o.run(W.params, W.nodes, 9)
+    cases = ((0, 2), (4, 2), (2, 0))
+    outs = run_cases([dict(params_list=[W.params], nodes_list=[W.nodes], steps=(5, 4), shape=shape,
+                           graph_steps=gs, timing=(shape == 4)) for shape, gs in cases])
+    r = o.run(W.params, W.nodes, 9)
+    for (shape, gs), out in zip(cases, outs):
+        g = out[0]
         drho, du, dq = compare_fields(g, r, 2, f"emu tile{shape}")
         assert g["status"] == 0
         assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
@@ -44,45 +103,43 @@ def test_batch_with_fluid_only_member():
           wl.Params(dim=2, nx=64, ny=8, tau=0.9, wetting=False)]
     qs = [wl.cap_polygon(12.0, 90.0, 2.0, 94, 48.0), wl.cap_polygon(9.0, 90.0, 2.0, 71, 35.0),
           None]
-    out = run_case(ps, qs, steps=(6,), graph_steps=2)
+    # plain, then timed direct launches with a frozen member that must not move
+    out, out_t = run_cases([dict(params_list=ps, nodes_list=qs, steps=(6,), graph_steps=2),
+                            dict(params_list=ps, nodes_list=qs, steps=(3, 3), timing=True,
+                                 inactive=(1,))])
     for d in range(2):
         r = o.run(ps[d], qs[d], 6)
         drho, du, dq = compare_fields(out[d], r, 2, f"emu batch{d}")
         assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
     assert np.all(out[2]["fdev"] == 0)
-    # timed direct launches, and a frozen member that must not move
-    out = run_case(ps, qs, steps=(3, 3), timing=True, inactive=(1,))
+    out = out_t
     r = o.run(ps[0], qs[0], 6)
     drho, du, dq = compare_fields(out[0], r, 2, "emu batch timed")
     assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
     assert np.array_equal(out[1]["q"], qs[1]) and np.all(out[1]["fdev"] == 0)
 
 
-def test_droplet_3d_tiny():
-    p = wl.Params(dim=3, nx=20, ny=18, nz=12, bc=(0, 0, 1), tau=0.8, sigma=0.005,
-                  theta_eq_deg=70.0, xi=2.0)
-    V, T = wl.cap_mesh(5.0, 90.0, 2.0, 3, (10.0, 9.0))
-    g = run_case([p], [V], [T], steps=(3,), graph_steps=2)[0]
+def test_droplet_3d_tiny(background):
+    p, V, T = _tiny3d_case()
+    g = background["tiny3d"].result()[0]
     r = o.run(p, V, 3, tris=T)
     drho, du, dq = compare_fields(g, r, 3, "emu 3d")
     assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
     assert abs(g["diag"]["volume"] - o.volume_3d(r["q"], T)) < 1e-9 * abs(g["diag"]["volume"])
 
 
-@pytest.mark.parametrize("direct", [False, True])
-def test_droplet_3d_coarse_mesh_across_periodic_edge(direct):
+def test_droplet_3d_coarse_mesh_across_periodic_edge(background):
     """Coarse cap centred on the periodic x edge, spreading boxes that wrap
-    around the periodic axis.  With `direct`, the host cuts plain runs of 64
-    vertices, so some chunks overflow the LDS box and add straight to
+    around the periodic axis.  The second build has the host cut plain runs
+    of 64 vertices, so some chunks overflow the LDS box and add straight to
     global memory next to chunks that fit."""
-    p = wl.Params(dim=3, nx=24, ny=22, nz=14, bc=(0, 0, 1), tau=0.9, sigma=0.006,
-                  theta_eq_deg=100.0, xi=2.0)
-    V, T = wl.cap_mesh(9.0, 90.0, 2.0, 4, (1.0, 11.0))
-    g = run_case([p], [V], [T], steps=(2,), graph_steps=2, direct_chunks=direct)[0]
+    p, V, T = _coarse3d_case()
     r = o.run(p, V, 2, tris=T)
-    drho, du, dq = compare_fields(g, r, 3, "emu 3d periodic")
-    assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
     assert np.min(r["q"][:, 0]) < 0.0
+    for key in ("coarse3d", "coarse3d_direct"):
+        out = background[key].result()
+        drho, du, dq = compare_fields(out[0], r, 3, f"emu 3d periodic {key}")
+        assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
 
 
 @pytest.mark.parametrize("storage", [0, 1, 2])
@@ -114,26 +171,21 @@ def test_prescribed_force_field():
     assert np.max(np.abs(g["U"] - r["U"][:2])) <= 1e-8
 
 
-def test_blow_up_is_reported_without_undefined_behaviour():
+def test_blow_up_is_reported_without_undefined_behaviour(background):
     """Huge surface tension: speeds and then positions become non-finite.
     The step reports IBLB_EUNSTABLE and no tap index is formed from a
     non-finite coordinate."""
-    p = wl.Params(dim=2, nx=64, ny=32, tau=1.0, sigma=50.0, theta_eq_deg=60.0, xi=2.0)
-    q = wl.cap_polygon(8.0, 90.0, 2.0, 40, 32.0)
-    g = run_case([p], [q], steps=(50,))[0]
+    g = background["blowup"].result()[0]
     assert g["status"] == -4
     assert g["diag"]["status"] == -4
 
 
-def test_run_to_rest_freezes_settled_droplets():
+def test_run_to_rest_freezes_settled_droplets(background):
     """A loose tolerance so that the tiny cases settle within a few checks:
     each droplet's frozen state equals the oracle after its reported step
     count; the fluid-only member is ignored."""
-    ps = [wl.Params(dim=2, nx=40, ny=24, tau=1.0, sigma=0.004, theta_eq_deg=90.0, xi=2.0),
-          wl.Params(dim=2, nx=48, ny=20, tau=0.8, sigma=0.02, theta_eq_deg=60.0, xi=2.0),
-          wl.Params(dim=2, nx=32, ny=8, tau=0.9, wetting=False)]
-    qs = [wl.cap_polygon(6.0, 90.0, 2.0, 40, 20.0), wl.cap_polygon(6.0, 90.0, 2.0, 40, 24.0), None]
-    out = run_case(ps, qs, steps=(0,), rest=(2e-3, 4, 2, 60), graph_steps=2)
+    ps, qs = _rest_case()
+    out = background["rest"].result()
     assert out[2]["rest_steps"] == 0
     for d in range(2):
         n = out[d]["rest_steps"]
