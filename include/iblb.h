@@ -117,7 +117,8 @@ typedef struct iblb_ctx iblb_ctx;
 
 /* Size in bytes of the device workspace for n_droplets droplets with the
  * given parameters, node counts and triangle counts (n_tris may be NULL in
- * 2D, where the interface is a closed polygon).  Returns 0 on bad input. */
+ * 2D, where the interface is a closed polygon).  Returns 0 on bad input,
+ * with the reason in iblb_last_error(NULL).  Host only: touches no device. */
 size_t iblb_workspace_bytes(int n_droplets, const iblb_params *params,
                             const int *n_nodes, const int *n_tris, int storage);
 
@@ -134,7 +135,8 @@ int iblb_create(int n_droplets, const iblb_params *params, const int *n_nodes,
 int iblb_destroy(iblb_ctx *ctx);
 
 /* Message for the handle's last failure ("" if none).  Valid until the next
- * call on the handle.  ctx may be NULL for failures of iblb_create(). */
+ * call on the handle.  ctx may be NULL for failures of iblb_create() and
+ * iblb_workspace_bytes() (kept per calling thread). */
 const char *iblb_last_error(const iblb_ctx *ctx);
 
 /* Upload droplet d's interface: h_pos [dim][N] node positions (host,

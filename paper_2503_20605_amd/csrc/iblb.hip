@@ -627,7 +627,10 @@ size_t iblb_workspace_bytes(int n_droplets, const iblb_params* params, const int
                             const int* n_tris, int storage) {
     Layout L;
     std::string err;
-    if (!plan(n_droplets, params, n_nodes, n_tris, storage, L, err)) return 0;
+    if (!plan(n_droplets, params, n_nodes, n_tris, storage, L, err)) {
+        fail(nullptr, IBLB_EINVAL, err);
+        return 0;
+    }
     return L.total;
 }
 

@@ -80,3 +80,42 @@ def test_workspace_size_and_validation_on_host(lib):
     pinf = (iblb_params * 1)(_params(dim=2, nx=4, ny=4, tau=math.inf))
     z = (ctypes.c_int * 1)(0)
     assert lib.iblb_workspace_bytes(1, pinf, z, None, 0) > 0       # pure streaming is legal
+
+
+@pytest.mark.parametrize("case,words", [
+    ("no droplets", b"n_droplets"),
+    ("empty box", b"sizes"),
+    ("dim 4", b"dim"),
+    ("mixed dims", b"dim"),
+    ("too many cells", b"2^31"),
+    ("negative node count", b"nodes"),
+    ("bad boundary code", b"boundary"),
+    ("wetting without xi", b"xi"),
+])
+def test_degenerate_inputs_rejected_on_host(lib, case, words):
+    """Sizing refuses degenerate batches and says why (iblb_last_error(NULL))."""
+    from paper_2503_20605_amd._lib import iblb_params
+    n, ps, nn = 1, [_params(dim=2, nx=64, ny=32)], [0]
+    if case == "no droplets":
+        n, ps, nn = 0, [_params(dim=2, nx=64, ny=32)], [0]
+    elif case == "empty box":
+        ps = [_params(dim=2, nx=0, ny=32)]
+    elif case == "dim 4":
+        ps = [_params(dim=2, nx=64, ny=32)]
+        ps[0].dim = 4
+    elif case == "mixed dims":
+        n, ps, nn = 2, [_params(dim=2, nx=64, ny=32), _params(dim=3, nx=8, ny=8, nz=8)], [0, 0]
+    elif case == "too many cells":
+        ps = [_params(dim=2, nx=65536, ny=8192)]          # 9 * 2^29 elements
+    elif case == "negative node count":
+        nn = [-5]
+    elif case == "bad boundary code":
+        ps = [_params(dim=2, nx=64, ny=32)]
+        ps[0].bc[0] = 7
+    elif case == "wetting without xi":
+        ps, nn = [_params(dim=2, nx=64, ny=32, xi=0.0)], [40]
+    P = (iblb_params * len(ps))(*ps)
+    NN = (ctypes.c_int * len(nn))(*nn)
+    assert lib.iblb_workspace_bytes(n, P, NN, None, 0) == 0
+    assert words in lib.iblb_last_error(None), lib.iblb_last_error(None)
+

@@ -212,6 +212,52 @@ def test_time_lattice_replays_plain_lattice_steps():
     assert np.array_equal(a.read_populations(0).cpu().numpy(), b.read_populations(0).cpu().numpy())
 
 
+def test_zero_steps_and_frozen_handle_change_nothing():
+    W = wl.droplet_2d_small()
+    s = gpu_solver([W.params], [W.nodes])
+    s.step(3)
+    a = collect(s, 0, 2)
+    s.step(0)
+    s.set_active(0, False)
+    s.step(10)
+    b = collect(s, 0, 2)
+    assert np.array_equal(a["fdev"], b["fdev"]) and np.array_equal(a["q"], b["q"])
+    s.set_active(0, True)
+    s.step(2)
+    r = o.run(W.params, W.nodes, 5)
+    drho, du, dq = compare_fields(collect(s, 0, 2), r, 2, "frozen-resumed")
+    assert drho <= 1e-5 and du <= 1e-5 and dq <= 1e-5
+
+
+def test_full_size_3d_droplet_two_steps():
+    """256x256x128 D3Q19, R = 40 hemisphere of 20252 vertices (the 3D
+    benchmark workload, lattice variant 4 as the autotuner picks there): two
+    coupled steps compared with the oracle over the whole box and every
+    vertex."""
+    W = wl.droplet_3d(theta_eq_deg=90.0, small=False)
+    print("[ib] full-size 3D, 2 steps", flush=True)
+    g = gpu_run(W.params, W.nodes, 2, tris=W.tris, shape=4)
+    r = o.run(W.params, W.nodes, 2, tris=W.tris)
+    drho, du, dq = compare_fields(g, r, 3, "3d-full")
+    assert drho <= 1e-5 and du <= 1e-5 and dq <= 1e-5
+    assert np.max(np.abs(g["phi"] - r["phi"])) <= 1e-6 * np.max(np.abs(r["phi"]))
+
+
+def test_full_batch_of_256_sampled_droplets():
+    """The 256-droplet batch (fp32 storage here), 40 steps with graph
+    replays; three sampled droplets compared one by one with the oracle."""
+    draws = wl.batch_draws(256, seed=3)
+    s = gpu_solver([w.params for w in draws], [w.nodes for w in draws])
+    s.set_graph_steps(16)
+    print("[ib] 256-droplet batch, 40 steps", flush=True)
+    s.step(40)
+    for d in (0, 117, 255):
+        g = collect(s, d, 2)
+        r = o.run(draws[d].params, draws[d].nodes, 40)
+        drho, du, dq = compare_fields(g, r, 2, f"batch256-{d}")
+        assert drho <= 1e-5 and du <= 1e-5 and dq <= 1e-5
+
+
 @pytest.mark.parametrize("storage,name", [(1, "f16"), (2, "bf16")])
 def test_shifted_low_precision_storage_error(storage, name):
     """Report the error of fp16 / bf16 storage of f - w against the oracle.
