@@ -150,6 +150,14 @@ int iblb_set_interface(iblb_ctx *ctx, int droplet, const double *h_pos,
 /* Reset droplet d (or every droplet for d = -1) to rest: f_i = w_i. */
 int iblb_init_rest(iblb_ctx *ctx, int droplet);
 
+/* Initialise droplet d's populations to the equilibrium (eq. f^eq of Sec.
+ * IB-LB, second order in U) of a density field d_rho [nz][ny][nx] (device
+ * float32; NULL: rho = 1 everywhere) and a velocity field d_u
+ * [dim][nz][ny][nx] (device float32; NULL: at rest).  Clears the droplet's
+ * force and velocity fields first.  The arrays are read by a kernel queued
+ * on the handle's stream: keep them alive until that stream has passed it. */
+int iblb_init_fields(iblb_ctx *ctx, int droplet, const float *d_rho, const float *d_u);
+
 /* Overwrite / read droplet d's post-collision populations, exchanged as
  * deviations f_i - w_i in a device float64 array [Q][nz][ny][nx].  Writing
  * narrows through fp32 to the storage format, nearest even at each step. */

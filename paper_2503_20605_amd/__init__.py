@@ -141,6 +141,27 @@ class Solver:
         p = self.params[d]
         return (p.nz if self.dim == 3 else 1, p.ny, p.nx)
 
+    def init_fields(self, d, rho=None, U=None):
+        """Equilibrium populations of droplet d from a density field
+        (nz, ny, nx) and a velocity field (dim, nz, ny, nx); None means 1 and
+        at rest."""
+        torch = self._torch
+        sh = self.cells(d)
+
+        def dev(a, shape):
+            if a is None:
+                return None
+            t = torch.as_tensor(np.asarray(a) if not torch.is_tensor(a) else a)
+            t = t.to(device=self.device, dtype=torch.float32).contiguous()
+            assert tuple(t.shape) == shape, (tuple(t.shape), shape)
+            return t
+
+        r = dev(rho, sh)
+        u = dev(U, (self.dim,) + sh)
+        self._chk(self.lib.iblb_init_fields(self.ctx, d, None if r is None else ctypes.c_void_p(r.data_ptr()),
+                                            None if u is None else ctypes.c_void_p(u.data_ptr())))
+        self.stream.synchronize()  # the kernel has read r and u
+
     def write_populations(self, d, fdev):
         """fdev: deviations f - w, shape (Q, nz, ny, nx), any float dtype."""
         t = self._torch.as_tensor(np.asarray(fdev) if not self._torch.is_tensor(fdev) else fdev)

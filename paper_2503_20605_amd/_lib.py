@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "IBLB_OK", -1: "IBLB_EINVAL", -2: "IBLB_ENOMEM", -3: "IBLB_ED
 
 EXPORTED = (
     "iblb_workspace_bytes", "iblb_create", "iblb_destroy", "iblb_last_error",
-    "iblb_set_interface", "iblb_init_rest", "iblb_write_populations",
+    "iblb_set_interface", "iblb_init_rest", "iblb_init_fields", "iblb_write_populations",
     "iblb_read_populations", "iblb_set_force_field", "iblb_step", "iblb_read_fields",
     "iblb_read_nodes", "iblb_diagnostics", "iblb_set_lb_variant", "iblb_autotune",
     "iblb_set_graph_steps", "iblb_set_active", "iblb_set_timing", "iblb_last_timing", "iblb_time_lattice",
@@ -92,6 +92,7 @@ def load() -> ctypes.CDLL:
     lib.iblb_last_error.restype = ctypes.c_char_p
     lib.iblb_set_interface.argtypes = [c_void_p, c_int, c_void_p, c_void_p]
     lib.iblb_init_rest.argtypes = [c_void_p, c_int]
+    lib.iblb_init_fields.argtypes = [c_void_p, c_int, c_void_p, c_void_p]
     lib.iblb_write_populations.argtypes = [c_void_p, c_int, c_void_p]
     lib.iblb_read_populations.argtypes = [c_void_p, c_int, c_void_p]
     lib.iblb_set_force_field.argtypes = [c_void_p, c_int, c_void_p]

@@ -934,6 +934,40 @@ int iblb_init_rest(iblb_ctx* c, int d) {
     return reset_droplet(c, d);
 }
 
+}  // extern "C"
+
+namespace {
+
+template <int S>
+void launch_init_eq(iblb_ctx* c, int d, const float* rho, const float* u) {
+    using T = typename Codec<S>::T;
+    const DropDev& D = c->drops[d];
+    T* f = c->at<T>(c->cur ? c->L.f1 : c->L.f0) + D.f_off;
+    const dim3 grid(ceil_div(D.ncell, kBlock)), block(kBlock);
+    if (c->dim == 2)
+        hipLaunchKernelGGL((k_init_eq<2, S>), grid, block, 0, c->stream, f, D.ncell, D.fst, rho, u);
+    else
+        hipLaunchKernelGGL((k_init_eq<3, S>), grid, block, 0, c->stream, f, D.ncell, D.fst, rho, u);
+}
+
+}  // namespace
+
+extern "C" {
+
+int iblb_init_fields(iblb_ctx* c, int d, const float* d_rho, const float* d_u) {
+    if (!c) return IBLB_EINVAL;
+    if (!check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
+    int rc = reset_droplet(c, d);  // clears F, U, the band flags and both population buffers
+    if (rc) return rc;
+    switch (c->storage) {
+        case ST_F32: launch_init_eq<ST_F32>(c, d, d_rho, d_u); break;
+        case ST_F16: launch_init_eq<ST_F16>(c, d, d_rho, d_u); break;
+        default: launch_init_eq<ST_BF16>(c, d, d_rho, d_u); break;
+    }
+    HIPCHK(c, hipGetLastError());
+    return IBLB_OK;
+}
+
 int iblb_write_populations(iblb_ctx* c, int d, const double* d_fdev) {
     return pop_io(c, d, d_fdev, nullptr);
 }

@@ -861,6 +861,29 @@ __global__ __launch_bounds__(kBlock) void k_ib_fused2(const DropDev* __restrict_
 // ---------------------------------------------------------------------------
 // Population I/O and initialisation
 // ---------------------------------------------------------------------------
+// Equilibrium populations (eq. f^eq, deviation form f_eq - w =
+// w (rho - 1) + w rho (3 c.u + 4.5 (c.u)^2 - 1.5 u^2)) from a density field
+// (null: 1) and a velocity field [dim][ncell] (null: 0), one lane per cell.
+template <int DIM, int S>
+__global__ void k_init_eq(typename Codec<S>::T* __restrict__ f, int ncell, int fst,
+                          const float* __restrict__ rho_in, const float* __restrict__ u_in) {
+    using L = Lattice<DIM>;
+    const int cell = blockIdx.x * kBlock + threadIdx.x;
+    if (cell >= ncell) return;
+    const float rho = rho_in ? rho_in[cell] : 1.f;
+    float u[3] = {0.f, 0.f, 0.f};
+    if (u_in)
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) u[a] = u_in[a * ncell + cell];
+    const float usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const float cu = L::c[i][0] * u[0] + L::c[i][1] * u[1] + (DIM == 3 ? L::c[i][2] * u[2] : 0.f);
+        const float v = L::w[i] * ((rho - 1.f) + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * usq));
+        Codec<S>::store(f, i * fst + cell, v);
+    }
+}
+
 // Dense [Q][ncell] doubles on the caller's side, population arrays fst
 // elements apart in the workspace.
 template <int S>

@@ -94,3 +94,32 @@ def test_rest_state_stays_at_rest_and_mass_exact():
     assert np.all(g["rho"] == 1.0) and np.all(g["U"] == 0.0)
     d = g["solver"].diagnostics(0)
     assert d["mass"] == 96 * 40
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (45, 17, 1)), (3, (13, 9, 6))])
+@pytest.mark.parametrize("storage", [0, 1, 2], ids=["f32", "f16", "bf16"])
+def test_init_fields_is_the_equilibrium(dim, shape, storage):
+    """iblb_init_fields against the oracle's equilibrium cell by cell, for a
+    random density and velocity field; within one rounding of the storage
+    format (relative to the largest deviation)."""
+    from helpers import gpu_solver
+    nx, ny, nz = shape
+    rng = np.random.default_rng(40 + dim)
+    rho = (1.0 + 1e-3 * rng.standard_normal((nz, ny, nx))).astype(np.float32)
+    U = (1e-2 * rng.standard_normal((dim, nz, ny, nx))).astype(np.float32)
+    p = wl.Params(dim=dim, nx=nx, ny=ny, nz=nz, tau=0.8, wetting=False)
+    s = gpu_solver([p], storage=storage)
+    s.init_fields(0, rho, U)
+    got = s.read_populations(0).cpu().numpy()
+    w = weights(dim)
+    want = np.empty_like(got)
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                want[:, z, y, x] = o.equilibrium(dim, float(rho[z, y, x]), U[:, z, y, x].astype(np.float64)) - w
+    u = {0: 2.0 ** -23, 1: 2.0 ** -10, 2: 2.0 ** -7}[storage]
+    assert np.max(np.abs(got - want)) <= 4 * u * np.max(np.abs(want))
+    # null fields: the rest state
+    s.init_fields(0)
+    assert np.max(np.abs(s.read_populations(0).cpu().numpy())) == 0.0
+

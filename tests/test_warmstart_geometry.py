@@ -51,19 +51,6 @@ def test_velocity_grid_round_trip():
     assert np.allclose(ws.coarse_velocity(U), Uc)
 
 
-def test_initial_populations_are_the_equilibrium():
-    rng = np.random.default_rng(1)
-    U = 1e-3 * rng.standard_normal((2, 6, 5))
-    inside = rng.random((6, 5)) < 0.5
-    f = ws.initial_populations(U, inside, 2e-3)
-    _, w = o.lattice(2)
-    for j in range(6):
-        for i in range(5):
-            rho = 1.0 + 2e-3 * inside[j, i]
-            want = o.equilibrium(2, rho, U[:, j, i]) - w
-            assert np.allclose(f[:, j, i], want, atol=1e-16)
-
-
 def test_inside_mask_of_circle():
     q = wl.circle_polygon(8.0, 400, (16.0, 12.0))
     m = ws.inside_mask(q, 24, 32)
