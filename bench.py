@@ -27,13 +27,15 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-# lattice-kernel variants: block width along x and non-temporal stores
-LB_BX = (256, 128, 64, 256, 128, 64)
-LB_NT = (0, 0, 0, 1, 1, 1)
+# lattice-kernel variants: block width along x, non-temporal stores,
+# non-temporal loads
+LB_BX = (256, 128, 64) * 4
+LB_NT = (0, 0, 0, 1, 1, 1) * 2
+LB_NTL = (0,) * 6 + (1,) * 6
 
 
 def lb_kernel_name(dim, storage, variant):
-    return f"k_lb<{dim}, {storage}, {LB_BX[variant]}, {LB_NT[variant]}>"
+    return f"k_lb<{dim}, {storage}, {LB_BX[variant]}, {LB_NT[variant]}, {LB_NTL[variant]}>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lb_traffic.md")
 
 
@@ -80,7 +82,7 @@ def parse():
     ap.add_argument("--run", type=int, default=1, help="sweep point 0..9 of the 1024x512 set")
     ap.add_argument("--graph-steps", type=int, default=64)
     ap.add_argument("--variant", type=int, default=-1,
-                    help="lattice-kernel variant 0..5; -1 autotunes")
+                    help="lattice-kernel variant 0..11; -1 autotunes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--extra", action="store_true",

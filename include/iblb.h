@@ -209,6 +209,7 @@ int iblb_run_to_rest(iblb_ctx *ctx, double tol, int check_every, int hold, long 
  *   0: 256x1 cells per block   3: 256x1, non-temporal stores
  *   1: 128x2 cells per block   4: 128x2, non-temporal stores
  *   2:  64x4 cells per block   5:  64x4, non-temporal stores
+ *   6-11: as 0-5 with non-temporal population loads
  * variant = -1 keeps the current one; *variant_out (may be NULL) receives
  * the variant in use. */
 int iblb_set_lb_variant(iblb_ctx *ctx, int variant, int *variant_out);
@@ -217,7 +218,7 @@ int iblb_set_lb_variant(iblb_ctx *ctx, int variant, int *variant_out);
  * steps advance the simulation) and keep the fastest.  With cache_path
  * non-NULL the winner is looked up in / appended to that text file, keyed
  * by device, lattice, storage and size bucket; a cache hit runs no step.
- * chosen (may be NULL) receives the variant; ms (may be NULL, 6 entries)
+ * chosen (may be NULL) receives the variant; ms (may be NULL, 12 entries)
  * the measured lattice-kernel milliseconds per step (-1 on a cache hit). */
 int iblb_autotune(iblb_ctx *ctx, int steps, const char *cache_path, int *chosen, double *ms);
 

@@ -27,10 +27,10 @@ using namespace iblb;
 namespace {
 
 // Lattice-kernel variants (autotuner candidates): tiles of 256x1, 128x2 or
-// 64x4 cells per block (shape v % 3), with ordinary (v < 3) or
-// non-temporal stores.
+// 64x4 cells per block (shape v % 3), ordinary or non-temporal stores
+// ((v / 3) % 2), ordinary or non-temporal loads (v / 6).
 constexpr int kShapes = 3;
-constexpr int kVariants = 6;
+constexpr int kVariants = 12;
 constexpr int kShapeBX[kShapes] = {256, 128, 64};
 constexpr int kShapeBY[kShapes] = {1, 2, 4};
 int shape_of(int variant) { return variant % kShapes; }
@@ -368,12 +368,18 @@ void launch_lb_t(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned l
                            c->at<float>(c->L.Fout), c->at<uint8_t>(c->L.flags), full, stamps);
     };
     switch (c->variant) {
-        case 0: go(k_lb<DIM, S, 256, 0>); break;
-        case 1: go(k_lb<DIM, S, 128, 0>); break;
-        case 2: go(k_lb<DIM, S, 64, 0>); break;
-        case 3: go(k_lb<DIM, S, 256, 1>); break;
-        case 4: go(k_lb<DIM, S, 128, 1>); break;
-        default: go(k_lb<DIM, S, 64, 1>); break;
+        case 0: go(k_lb<DIM, S, 256, 0, 0>); break;
+        case 1: go(k_lb<DIM, S, 128, 0, 0>); break;
+        case 2: go(k_lb<DIM, S, 64, 0, 0>); break;
+        case 3: go(k_lb<DIM, S, 256, 1, 0>); break;
+        case 4: go(k_lb<DIM, S, 128, 1, 0>); break;
+        case 5: go(k_lb<DIM, S, 64, 1, 0>); break;
+        case 6: go(k_lb<DIM, S, 256, 0, 1>); break;
+        case 7: go(k_lb<DIM, S, 128, 0, 1>); break;
+        case 8: go(k_lb<DIM, S, 64, 0, 1>); break;
+        case 9: go(k_lb<DIM, S, 256, 1, 1>); break;
+        case 10: go(k_lb<DIM, S, 128, 1, 1>); break;
+        default: go(k_lb<DIM, S, 64, 1, 1>); break;
     }
 }
 
@@ -1230,7 +1236,7 @@ int iblb_run_to_rest(iblb_ctx* c, double tol, int check_every, int hold, long lo
 int iblb_set_lb_variant(iblb_ctx* c, int variant, int* variant_out) {
     if (!c) return IBLB_EINVAL;
     if (variant >= kVariants || variant < -1)
-        return fail(c, IBLB_EINVAL, "lattice-kernel variant must be -1 or 0..5");
+        return fail(c, IBLB_EINVAL, "lattice-kernel variant must be -1 or 0..11");
     if (variant >= 0 && variant != c->variant) {
         c->variant = variant;
         c->tiles_dirty = true;

@@ -164,7 +164,10 @@ struct Moments {
 // ---------------------------------------------------------------------------
 // NT = 1 writes the new populations with non-temporal stores: they are not
 // read again before the next launch, so they need not displace cached lines.
-template <int DIM, int S, int BX, int NT>
+// NTL = 1 reads the populations with non-temporal loads: each is read once
+// per launch (neighbouring wavefronts share only the edges of the lines
+// that x-streamed populations straddle).
+template <int DIM, int S, int BX, int NT, int NTL>
 __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops,
                                                const int4* __restrict__ tiles,
                                                const typename Codec<S>::T* __restrict__ fsrc_all,
@@ -217,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         // take the opposite population of this cell (half-way bounce-back)
         const bool wall = (sx | sy | sz) < 0;
         const int idx = wall ? opp(i) * fst + cell : i * fst + (sz * ny + sy) * nx + sx;
-        f[i] = C::load(fsrc, idx);
+        f[i] = NTL ? C::load_nt(fsrc, idx) : C::load(fsrc, idx);
     }
 
     float* __restrict__ F = F_all + (long long)DIM * D.c_off;

@@ -53,6 +53,7 @@ template <>
 struct Codec<ST_F32> {
     using T = float;
     static __device__ __forceinline__ float load(const T* p, int i) { return p[i]; }
+    static __device__ __forceinline__ float load_nt(const T* p, int i) { return __builtin_nontemporal_load(p + i); }
     static __device__ __forceinline__ void store(T* p, int i, float v) { p[i] = v; }
     static __device__ __forceinline__ void store_nt(T* p, int i, float v) {
         __builtin_nontemporal_store(v, p + i);
@@ -65,6 +66,9 @@ template <>
 struct Codec<ST_F16> {
     using T = _Float16;
     static __device__ __forceinline__ float load(const T* p, int i) { return (float)p[i]; }
+    static __device__ __forceinline__ float load_nt(const T* p, int i) {
+        return (float)__builtin_nontemporal_load(p + i);
+    }
     static __device__ __forceinline__ void store(T* p, int i, float v) { p[i] = (_Float16)v; }
     static __device__ __forceinline__ void store_nt(T* p, int i, float v) {
         __builtin_nontemporal_store((_Float16)v, p + i);
@@ -89,6 +93,9 @@ template <>
 struct Codec<ST_BF16> {
     using T = uint16_t;
     static __device__ __forceinline__ float load(const T* p, int i) { return bf16_to_f32(p[i]); }
+    static __device__ __forceinline__ float load_nt(const T* p, int i) {
+        return bf16_to_f32(__builtin_nontemporal_load(p + i));
+    }
     static __device__ __forceinline__ void store(T* p, int i, float v) { p[i] = f32_to_bf16_rne(v); }
     static __device__ __forceinline__ void store_nt(T* p, int i, float v) {
         __builtin_nontemporal_store(f32_to_bf16_rne(v), p + i);

@@ -73,10 +73,10 @@ def background():
 
 
 def test_droplet_2d_graph_and_tiles():
-    """Three tile shapes; graph replays of 2 steps plus direct launches, the
-    timed schedule, and no graphs."""
+    """Three tile shapes and a non-temporal-load variant; graph replays of 2
+    steps plus direct launches, the timed schedule, and no graphs."""
     W = wl.droplet_2d_small()
-    cases = ((0, 2), (4, 2), (2, 0))
+    cases = ((0, 2), (4, 2), (2, 0), (10, 2))
     outs = run_cases([dict(params_list=[W.params], nodes_list=[W.nodes], steps=(5, 4), shape=shape,
                            graph_steps=gs, timing=(shape == 4)) for shape, gs in cases])
     r = o.run(W.params, W.nodes, 9)
