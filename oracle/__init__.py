@@ -44,7 +44,7 @@ def _load():
     lib.orc_lattice.argtypes = [c_int, I, D]
     lib.orc_equilibrium.argtypes = [c_int, c_double, D, D]
     lib.orc_guo_source.argtypes = [c_int, c_double, D, D, D]
-    lib.orc_lb_step.argtypes = [c_int, c_int, c_int, c_int, I, c_double, D, D, D, D, D]
+    lib.orc_lb_step.argtypes = [c_int, c_int, c_int, c_int, I, c_double, D, D, D, D, D, D]
     lib.orc_psi.argtypes = [c_double]
     lib.orc_psi.restype = c_double
     lib.orc_spread.argtypes = [c_int, c_int, c_int, c_int, I, c_int, D, D, D, D]
@@ -57,7 +57,8 @@ def _load():
                                   c_int, D, D]
     lib.orc_forces_3d.argtypes = [c_int, D, c_int, I, c_double, c_double, c_double,
                                   c_int, c_int, c_int, D, D]
-    lib.orc_run.argtypes = [c_int, c_int, c_int, c_int, I, c_double,
+    lib.orc_inside.argtypes = [c_int, c_int, c_int, c_int, I, c_int, D, c_int, I, D, I]
+    lib.orc_run.argtypes = [c_int, c_int, c_int, c_int, I, c_double, c_double, D,
                             c_double, c_double, c_double, c_int, c_int, c_int,
                             c_int, D, c_int, I, c_int,
                             D, D, D, D, D, D, D, D]
@@ -124,8 +125,9 @@ def rest_populations(dim, nx, ny, nz=1):
                                                 (len(w), nz, ny, nx)).astype(np.float64))
 
 
-def lb_step(dim, nx, ny, nz, bc, tau, f, F=None):
-    """One pull-form LB step (eq. LBE).  Returns (f_new, rho, U)."""
+def lb_step(dim, nx, ny, nz, bc, tau, f, F=None, tau_cell=None):
+    """One pull-form LB step (eq. LBE).  tau_cell (nz, ny, nx), if given, is
+    the relaxation time of every cell.  Returns (f_new, rho, U)."""
     lib = _load()
     Q = 9 if dim == 2 else 19
     f = np.ascontiguousarray(f, dtype=np.float64).reshape(Q, nz, ny, nx)
@@ -133,7 +135,8 @@ def lb_step(dim, nx, ny, nz, bc, tau, f, F=None):
     rho = np.empty((nz, ny, nx))
     U = np.empty((3, nz, ny, nx))
     Fa = None if F is None else np.ascontiguousarray(F, dtype=np.float64).reshape(3, nz, ny, nx)
-    lib.orc_lb_step(dim, nx, ny, nz, _i(_bc(bc)), float(tau), _d(f), _d(Fa), _d(out),
+    tc = None if tau_cell is None else np.ascontiguousarray(tau_cell, dtype=np.float64).reshape(nz, ny, nx)
+    lib.orc_lb_step(dim, nx, ny, nz, _i(_bc(bc)), float(tau), _d(tc), _d(f), _d(Fa), _d(out),
                     _d(rho), _d(U))
     return out, rho, U
 
@@ -208,6 +211,43 @@ def forces_3d(q, tris, sigma, A, xi, n=6, m=3, wetting=True):
 
 
 # --------------------------------------------------------------------------
+# two viscosities (Sec. IB-LB, last paragraph; eq. def_lambda)
+# --------------------------------------------------------------------------
+
+def tau_inside(tau_out, lam):
+    """Relaxation time inside the droplet for viscosity ratio lam:
+    mu = rho cs^2 (tau - 1/2) on both sides and lam = mu_in / mu_out (eq.
+    def_lambda), so tau_in - 1/2 = lam (tau_out - 1/2)."""
+    return 0.5 + lam * (tau_out - 0.5)
+
+
+def reference_point(q0):
+    """Centre of the classification window of a droplet: the mean of its
+    node positions (N, dim) as first set, padded to three components."""
+    r = np.zeros(3)
+    q0 = np.asarray(q0, dtype=np.float64)
+    r[:q0.shape[1]] = q0.mean(axis=0)
+    return r
+
+
+def inside_mask(params, q, tris=None, ref=None):
+    """(nz, ny, nx) int array: 1 where the cell centre is enclosed by the
+    interface (winding number, see orc_inside), 0 elsewhere.  ref: window
+    centre (default: mean of q)."""
+    p = params
+    dim = p.dim
+    nz = p.nz if dim == 3 else 1
+    qa = np.ascontiguousarray(np.asarray(q, dtype=np.float64).T)
+    T = (np.zeros((0, 3), dtype=np.int32) if tris is None
+         else np.ascontiguousarray(tris, dtype=np.int32))
+    r = reference_point(q) if ref is None else np.ascontiguousarray(ref, dtype=np.float64)
+    out = np.zeros((nz, p.ny, p.nx), dtype=np.int32)
+    _load().orc_inside(dim, p.nx, p.ny, nz, _i(_bc(p.bc)), qa.shape[1], _d(qa), T.shape[0],
+                       _i(T), _d(r), _i(out))
+    return out
+
+
+# --------------------------------------------------------------------------
 # time loop
 # --------------------------------------------------------------------------
 
@@ -217,8 +257,10 @@ def run(params, q0, nsteps, tris=None, f0=None, F_fixed=None):
     for the fluid alone, optionally driven by F_fixed (3,nz,ny,nx)).
 
     `params` is any object with attributes dim, nx, ny, nz, bc, tau, sigma,
-    theta_eq_deg, xi, n_exp, m_exp, wetting.  Returns a dict with the final
-    f, q, and the last step's rho, U, F, phi, qdot, dropped, status."""
+    theta_eq_deg, xi, n_exp, m_exp, wetting, and optionally lam (viscosity
+    ratio, default 1; the classification window is centred on the mean of
+    q0).  Returns a dict with the final f, q, and the last step's rho, U, F,
+    phi, qdot, dropped, status."""
     p = params
     lib = _load()
     dim = p.dim
@@ -239,7 +281,10 @@ def run(params, q0, nsteps, tris=None, f0=None, F_fixed=None):
     qdot = np.zeros((dim, max(N, 1)))
     dropped = np.zeros(3)
     qa = q if N > 0 else np.zeros((dim, 1))
-    status = lib.orc_run(dim, p.nx, p.ny, nz, _i(_bc(p.bc)), float(p.tau),
+    lam = float(getattr(p, "lam", 1.0))
+    tau_in = tau_inside(float(p.tau), lam) if lam != 1.0 else float(p.tau)
+    ref = reference_point(q0) if N > 0 else np.zeros(3)
+    status = lib.orc_run(dim, p.nx, p.ny, nz, _i(_bc(p.bc)), float(p.tau), tau_in, _d(ref),
                          float(p.sigma), math.radians(p.theta_eq_deg), float(p.xi),
                          int(p.n_exp), int(p.m_exp), int(bool(p.wetting)),
                          N, _d(qa), T.shape[0], _i(T), int(nsteps),

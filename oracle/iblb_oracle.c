@@ -26,6 +26,9 @@
  *                           -(chi_j/3) Pi n_j; strength A from eq. (A_choice)
  *   boundaries              periodic sides, bounce-back walls (Sec. "Numerical
  *                           results", set-up paragraph)
+ *   two viscosities         tau = tau_in at cells enclosed by the interface,
+ *                           tau_out elsewhere, reclassified every step (Sec.
+ *                           IB-LB, last paragraph; eq. def_lambda)
  *
  * Conventions shared with every other implementation of the model (an
  * interface, not code): populations are stored [i][z][y][x] with x fastest;
@@ -66,6 +69,7 @@ static const double W3[19] = {
     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
 static const double CS2 = 1.0 / 3.0; /* c_s^2 = dx^2 / (3 dt^2) */
+static const double PI = 3.14159265358979323846;
 
 static int nq(int dim) { return dim == 2 ? 9 : 19; }
 static const int *cvec(int dim, int i) { return dim == 2 ? C2[i] : C3[i]; }
@@ -130,10 +134,12 @@ void orc_guo_source(int dim, double tau, const double *U, const double *F, doubl
 /* half a step earlier: it is the opposite population of the same cell       */
 /* (half-way bounce-back, resting wall).                                     */
 /* fin, fout: [Q][ncell]; F, U: [3][ncell] (unused components zero);        */
-/* rho: [ncell].  F may be NULL (no force).                                  */
+/* rho: [ncell].  F may be NULL (no force).  tau_cell: [ncell] relaxation     */
+/* time of every cell, or NULL for tau everywhere; a cell's own tau enters   */
+/* both the BGK term and the Guo prefactor.                                  */
 /* ------------------------------------------------------------------------ */
 void orc_lb_step(int dim, int nx, int ny, int nz, const int *bc, double tau,
-                 const double *fin, const double *F, double *fout,
+                 const double *tau_cell, const double *fin, const double *F, double *fout,
                  double *rho_out, double *U_out)
 {
     const int Q = nq(dim);
@@ -175,10 +181,11 @@ void orc_lb_step(int dim, int nx, int ny, int nz, const int *bc, double tau,
                 }
                 double U[3];
                 for (int a = 0; a < 3; ++a) U[a] = (mom[a] + 0.5 * Fx[a]) / rho;
+                const double t = tau_cell ? tau_cell[cell] : tau;
                 orc_equilibrium(dim, rho, U, feq);
-                orc_guo_source(dim, tau, U, Fx, S);
+                orc_guo_source(dim, t, U, Fx, S);
                 for (int i = 0; i < Q; ++i)
-                    fout[(long)i * ncell + cell] = f[i] - (f[i] - feq[i]) / tau + S[i];
+                    fout[(long)i * ncell + cell] = f[i] - (f[i] - feq[i]) / t + S[i];
                 if (rho_out) rho_out[cell] = rho;
                 if (U_out)
                     for (int a = 0; a < 3; ++a) U_out[(long)a * ncell + cell] = U[a];
@@ -430,12 +437,91 @@ void orc_forces_3d(int N, const double *q, int T, const int *tri, double sigma,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Cells enclosed by the interface (Sec. IB-LB, last paragraph)              */
+/* ------------------------------------------------------------------------ */
+/* The paper finds the cells inside the closed interface by ray tracing.     */
+/* Here the plain definition of "enclosed" is used instead: the winding      */
+/* number of the interface around the cell centre, which is +-1 inside a    */
+/* closed, non-self-intersecting interface and 0 outside.                    */
+/*   2D: the sum over the polygon's edges of the signed angle under which    */
+/*       the edge is seen from the point, over 2 pi;                         */
+/*   3D: the sum over the triangles of the signed solid angle under which    */
+/*       the triangle is seen from the point (van Oosterom and Strackee,     */
+/*       IEEE Trans. Biomed. Eng. 30 (1983) 125), over 4 pi.                */
+/* The interface is never wrapped across a periodic boundary; a cell centre  */
+/* is taken at its periodic image in the window [ref - n/2, ref + n/2) of    */
+/* each periodic axis, ref a point of the droplet.  The image the interface  */
+/* can enclose is that one as long as the droplet stays inside the window.   */
+static double image_in_window(double c, double ref, int n, int periodic)
+{
+    if (!periodic) return c;
+    double lo = ref - 0.5 * n;
+    return c + n * ceil((lo - c) / n);
+}
+
+static double winding_2d(int N, const double *q, const double *p)
+{
+    const double *x = q, *y = q + N;
+    double w = 0.0;
+    for (int j = 0; j < N; ++j) {
+        int jp = (j + 1) % N;
+        double ax = x[j] - p[0], ay = y[j] - p[1];
+        double bx = x[jp] - p[0], by = y[jp] - p[1];
+        w += atan2(ax * by - ay * bx, ax * bx + ay * by);
+    }
+    return w / (2.0 * PI);
+}
+
+static double norm3(const double *a) { return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static double winding_3d(int N, const double *q, int T, const int *tri, const double *p)
+{
+    double w = 0.0;
+    for (int t = 0; t < T; ++t) {
+        double a[3], b[3], c[3], bc_[3];
+        for (int k = 0; k < 3; ++k) {
+            a[k] = q[(long)k * N + tri[3 * t]] - p[k];
+            b[k] = q[(long)k * N + tri[3 * t + 1]] - p[k];
+            c[k] = q[(long)k * N + tri[3 * t + 2]] - p[k];
+        }
+        cross3(b, c, bc_);
+        double la = norm3(a), lb = norm3(b), lc = norm3(c);
+        double num = dot3(a, bc_);
+        double den = la * lb * lc + dot3(a, b) * lc + dot3(a, c) * lb + dot3(b, c) * la;
+        w += 2.0 * atan2(num, den);
+    }
+    return w / (4.0 * PI);
+}
+
+/* inside[cell] = 1 for cells enclosed by the interface (q: [dim][N]; tri:
+ * [T][3], 3D only), 0 otherwise.  ref: [3] window centre (see above). */
+void orc_inside(int dim, int nx, int ny, int nz, const int *bc, int N, const double *q,
+                int T, const int *tri, const double *ref, int *inside)
+{
+    const int n[3] = {nx, ny, nz};
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int pos[3] = {x, y, z};
+                double p[3] = {0.0, 0.0, 0.0};
+                for (int a = 0; a < dim; ++a)
+                    p[a] = image_in_window(pos[a] + 0.5, ref[a], n[a], bc[a] == ORC_PERIODIC);
+                double w = dim == 2 ? winding_2d(N, q, p) : winding_3d(N, q, T, tri, p);
+                inside[((long)z * ny + y) * nx + x] = fabs(w) > 0.5;
+            }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Time loop                                                                 */
 /* ------------------------------------------------------------------------ */
 
 /* Run nsteps of the coupled method.  Order inside a step: nodal forces at
  * q(t) -> spread to F(t) -> LB step with F(t) (in the Guo source and the
  * half-force velocity alike) -> interpolate U(t) at q(t) -> q(t+1).
+ * With tau_in != tau the cells enclosed by the interface at q(t) relax with
+ * tau_in in the LB step of step t and the others with tau (classification
+ * window centred on ref[3]; see orc_inside).
  *
  * f: [Q][ncell] post-collision populations, updated in place.
  * q: [dim][N] node positions, updated in place.
@@ -443,8 +529,9 @@ void orc_forces_3d(int N, const double *q, int T, const int *tri, double sigma,
  * phi, qdot: outputs of the last step ([dim][N]).  dropped: [3].
  * N = 0 runs the fluid alone with the prescribed force field F_fixed
  * (may be NULL).  Returns 0, or -4 if a node reached h <= 0 (wetting on). */
-int orc_run(int dim, int nx, int ny, int nz, const int *bc, double tau,
-            double sigma, double theta, double xi, int n_exp, int m_exp, int wetting,
+int orc_run(int dim, int nx, int ny, int nz, const int *bc, double tau, double tau_in,
+            const double *ref, double sigma, double theta, double xi, int n_exp, int m_exp,
+            int wetting,
             int N, double *q, int T, const int *tri, int nsteps,
             double *f, double *rho, double *U, double *F, const double *F_fixed,
             double *phi, double *qdot, double *dropped)
@@ -453,6 +540,9 @@ int orc_run(int dim, int nx, int ny, int nz, const int *bc, double tau,
     const long ncell = (long)nx * ny * nz;
     double *g = (double *)malloc(sizeof(double) * Q * ncell);
     double A = orc_wetting_strength(sigma, theta, xi, n_exp, m_exp);
+    const int two_tau = N > 0 && tau_in != tau;
+    double *tau_cell = two_tau ? (double *)malloc(sizeof(double) * ncell) : NULL;
+    int *inside = two_tau ? (int *)malloc(sizeof(int) * ncell) : NULL;
     int status = 0;
     for (int t = 0; t < nsteps; ++t) {
         if (N > 0) {
@@ -465,12 +555,16 @@ int orc_run(int dim, int nx, int ny, int nz, const int *bc, double tau,
             else
                 orc_forces_3d(N, q, T, tri, sigma, A, xi, n_exp, m_exp, wetting, phi, NULL);
             orc_spread(dim, nx, ny, nz, bc, N, q, phi, F, dropped);
+            if (two_tau) {
+                orc_inside(dim, nx, ny, nz, bc, N, q, T, tri, ref, inside);
+                for (long k = 0; k < ncell; ++k) tau_cell[k] = inside[k] ? tau_in : tau;
+            }
         } else if (F_fixed) {
             memcpy(F, F_fixed, sizeof(double) * 3 * ncell);
         } else {
             memset(F, 0, sizeof(double) * 3 * ncell);
         }
-        orc_lb_step(dim, nx, ny, nz, bc, tau, f, F, g, rho, U);
+        orc_lb_step(dim, nx, ny, nz, bc, tau, tau_cell, f, F, g, rho, U);
         memcpy(f, g, sizeof(double) * Q * ncell);
         if (N > 0) {
             orc_interp(dim, nx, ny, nz, bc, U, N, q, qdot);
@@ -478,5 +572,7 @@ int orc_run(int dim, int nx, int ny, int nz, const int *bc, double tau,
         }
     }
     free(g);
+    free(tau_cell);
+    free(inside);
     return status;
 }

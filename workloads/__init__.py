@@ -46,6 +46,9 @@ class Params:
     # whether the wetting interaction acts (substrate at the low end of the
     # last axis); off for a free droplet in a periodic box
     wetting: bool = True
+    # viscosity ratio mu_in / mu_out of the fluid inside the interface to the
+    # fluid outside (tau is the outside relaxation time); 1: one fluid
+    lam: float = 1.0
 
     def to_dict(self):
         return asdict(self)
