@@ -34,8 +34,9 @@ LB_NT = (0, 0, 0, 1, 1, 1) * 2
 LB_NTL = (0,) * 6 + (1,) * 6
 
 
-def lb_kernel_name(dim, storage, variant):
-    return f"k_lb<{dim}, {storage}, {LB_BX[variant]}, {LB_NT[variant]}, {LB_NTL[variant]}>"
+def lb_kernel_name(dim, storage, variant, vis=0):
+    return (f"k_lb<{dim}, {storage}, {LB_BX[variant]}, {LB_NT[variant]}, {LB_NTL[variant]}, "
+            f"{vis}>")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lb_traffic.md")
 
 
@@ -93,7 +94,9 @@ def parse():
                     help="time to equilibrium of the 256-droplet batch instead of the step rate")
     ap.add_argument("--droplets", type=int, default=256)
     ap.add_argument("--max-steps", type=int, default=200000)
-    ap.add_argument("--workload", default="d2q9", choices=["d2q9", "d3q19"])
+    ap.add_argument("--workload", default="d2q9", choices=["d2q9", "d3q19", "d3q19_spreading"])
+    ap.add_argument("--lam", type=float, default=None,
+                    help="viscosity ratio mu_in / mu_out (default: the workload's own)")
     ap.add_argument("--mlp", action="store_true",
                     help="time training steps of the warm-start network (4096 samples, widths "
                          "4-256-256-256-1280) on seeded synthetic data")
@@ -277,12 +280,20 @@ def main():
     storage = STORAGE[a.storage]
     if a.workload == "d3q19":
         W = wl.droplet_3d(theta_eq_deg=90.0, small=False)
+    elif a.workload == "d3q19_spreading":
+        W = wl.droplet_3d_spreading(lam=10.0 if a.lam is None else a.lam)
     else:
         W = wl.droplet_2d_large(run=a.run)
+    if a.lam is not None and a.lam != W.params.lam:
+        W.params.lam = a.lam
+        W.name += f"_lam{a.lam:g}"
     p = W.params
+    lam = float(p.lam)
     dim = p.dim
     cells = p.nx * p.ny * (p.nz if dim == 3 else 1)
     s = Solver([params_from(p)], [W.nodes], None if W.tris is None else [W.tris], storage=storage)
+    if lam != 1.0:
+        s.set_viscosity_ratio(0, lam)
     s.set_graph_steps(a.graph_steps)
     steps, warm = a.steps, a.warmup
     if a.profile_only:
@@ -317,7 +328,7 @@ def main():
     lb_ms = s.time_lattice(256)
     bpc = bytes_per_cell(dim, storage)
     achieved = bpc * cells / (lb_ms * 1e-3) / 1e9
-    lb_name = lb_kernel_name(dim, storage, variant)
+    lb_name = lb_kernel_name(dim, storage, variant, vis=int(lam != 1.0))
     traffic = measured_traffic(lb_name, W.name)
 
     out = {
@@ -334,8 +345,9 @@ def main():
         "dtype": "f32" if storage == 0 else f"f32 compute, {a.storage} storage",
         "data": "synthetic (seeded droplet workload)",
         "config": {"workload": W.name,
-                   "lattice": "D2Q9 1024x512" if dim == 2 else "D3Q19 256x256x128",
-                   "nodes": len(W.nodes),
+                   "lattice": (f"D2Q9 {p.nx}x{p.ny}" if dim == 2
+                               else f"D3Q19 {p.nx}x{p.ny}x{p.nz}"),
+                   "nodes": len(W.nodes), "viscosity_ratio": lam,
                    "tau": p.tau, "theta_eq_deg": p.theta_eq_deg, "sigma": p.sigma, "xi": p.xi,
                    "storage": a.storage, "graph_steps": a.graph_steps,
                    "lb_variant": variant},

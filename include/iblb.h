@@ -63,10 +63,14 @@ typedef enum {
     IBLB_EINVAL = -1,     /* bad argument: see iblb_last_error()            */
     IBLB_ENOMEM = -2,     /* workspace smaller than iblb_workspace_bytes()  */
     IBLB_EDEVICE = -3,    /* a HIP runtime call failed                      */
-    IBLB_EUNSTABLE = -4   /* a node reached h <= 0 with wetting on, a node
+    IBLB_EUNSTABLE = -4,  /* a node reached h <= 0 with wetting on, a node
                              speed became non-finite or above 0.3, or a node
                              position became non-finite (such nodes are
                              then left out of spreading and interpolation) */
+    IBLB_ELIMIT = -5      /* a fixed capacity was exceeded: more than 16
+                             interface crossings on one lattice row in the
+                             inside/outside classification (the extra
+                             crossings are dropped)                        */
 } iblb_status;
 
 typedef enum { IBLB_PERIODIC = 0, IBLB_WALL = 1 } iblb_bc;
@@ -230,6 +234,32 @@ int iblb_set_graph_steps(iblb_ctx *ctx, int steps);
  * every kernel until re-activated; their state is kept. */
 int iblb_set_active(iblb_ctx *ctx, int droplet, int active);
 
+/* Viscosity ratio lambda = mu_in / mu_out of droplet d (Sec. "Immersed-
+ * boundary lattice Boltzmann (IB-LB) method", last paragraph; eq.
+ * def_lambda).  With mu = rho cs^2 (tau - 1/2) on both sides, the cells
+ * enclosed by the interface relax with tau_in = 1/2 + lambda (tau - 1/2)
+ * (in the BGK term and the Guo prefactor) and the others with the droplet's
+ * tau.  Every step first classifies the cells at the node positions of
+ * that step: a ray along +x through each lattice row counts the
+ * interface's crossings beyond the cell centre (odd: inside).  Along a
+ * periodic axis the interface is not wrapped; cell centres are taken at
+ * their periodic image in the window [r - n/2, r + n/2) around the mean r
+ * of the node positions given to the last iblb_set_interface(), which is
+ * exact while every node stays inside that window.  lambda = 1 (the
+ * default) turns the classification off.  lambda must be positive and
+ * finite, tau finite, and the droplet must have an interface (EINVAL
+ * otherwise).  More than 16 crossings on one row fail the step with
+ * IBLB_ELIMIT.  Synchronises the stream. */
+int iblb_set_viscosity_ratio(iblb_ctx *ctx, int droplet, double lambda);
+
+/* Inside/outside classification of droplet d's cells at its current node
+ * positions (the rule of iblb_set_viscosity_ratio, for any lambda):
+ * d_mask (device, uint8, ncell = nx*ny*nz, [z][y][x]) receives 1 for cells
+ * enclosed by the interface and 0 for the others.  The droplet must have
+ * an interface.  IBLB_ELIMIT if a row has more than 16 crossings,
+ * IBLB_EUNSTABLE for a non-finite node.  Synchronises the stream. */
+int iblb_inside_mask(iblb_ctx *ctx, int droplet, uint8_t *d_mask);
+
 /* With timing on, iblb_step() runs the same schedule (graph replays plus
  * direct launches) while the lattice kernel stamps its first block start
  * and its last wavefront end (after that wavefront's stores complete) on
@@ -249,7 +279,9 @@ int iblb_last_timing(const iblb_ctx *ctx, double *lb_ms_per_step, double *step_m
  * including dispatch, the quantity a kernel-trace profiler reports).  The
  * populations advance by 2 * launches force-free lattice steps and the
  * nodes stay where they are, so the handle no longer holds a coupled
- * solution afterwards. */
+ * solution afterwards.  Droplets with two viscosities keep the inside/
+ * outside classification of their current node positions for every
+ * launch. */
 int iblb_time_lattice(iblb_ctx *ctx, int launches, double *ms_per_launch);
 
 /* Measurement aid: copy `bytes` (a multiple of 16) from d_src to d_dst on

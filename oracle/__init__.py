@@ -58,6 +58,8 @@ def _load():
     lib.orc_forces_3d.argtypes = [c_int, D, c_int, I, c_double, c_double, c_double,
                                   c_int, c_int, c_int, D, D]
     lib.orc_inside.argtypes = [c_int, c_int, c_int, c_int, I, c_int, D, c_int, I, D, I]
+    lib.orc_inside_cells.argtypes = [c_int, c_int, c_int, c_int, I, c_int, D, c_int, I, D,
+                                     ctypes.c_long, ctypes.POINTER(ctypes.c_long), I]
     lib.orc_run.argtypes = [c_int, c_int, c_int, c_int, I, c_double, c_double, D,
                             c_double, c_double, c_double, c_int, c_int, c_int,
                             c_int, D, c_int, I, c_int,
@@ -244,6 +246,23 @@ def inside_mask(params, q, tris=None, ref=None):
     out = np.zeros((nz, p.ny, p.nx), dtype=np.int32)
     _load().orc_inside(dim, p.nx, p.ny, nz, _i(_bc(p.bc)), qa.shape[1], _d(qa), T.shape[0],
                        _i(T), _d(r), _i(out))
+    return out
+
+
+def inside_cells(params, q, cells, tris=None, ref=None):
+    """inside_mask at the listed flat cell indices ([z][y][x] order) only."""
+    p = params
+    dim = p.dim
+    nz = p.nz if dim == 3 else 1
+    qa = np.ascontiguousarray(np.asarray(q, dtype=np.float64).T)
+    T = (np.zeros((0, 3), dtype=np.int32) if tris is None
+         else np.ascontiguousarray(tris, dtype=np.int32))
+    r = reference_point(q) if ref is None else np.ascontiguousarray(ref, dtype=np.float64)
+    cl = np.ascontiguousarray(cells, dtype=np.int64)
+    out = np.zeros(cl.shape[0], dtype=np.int32)
+    _load().orc_inside_cells(dim, p.nx, p.ny, nz, _i(_bc(p.bc)), qa.shape[1], _d(qa), T.shape[0],
+                             _i(T), _d(r), cl.shape[0],
+                             cl.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _i(out))
     return out
 
 

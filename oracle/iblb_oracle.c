@@ -512,6 +512,23 @@ void orc_inside(int dim, int nx, int ny, int nz, const int *bc, int N, const dou
             }
 }
 
+/* orc_inside for the listed cells only (cells: flat indices [z][y][x]). */
+void orc_inside_cells(int dim, int nx, int ny, int nz, const int *bc, int N, const double *q,
+                      int T, const int *tri, const double *ref, long ncells, const long *cells,
+                      int *inside)
+{
+    const int n[3] = {nx, ny, nz};
+    for (long k = 0; k < ncells; ++k) {
+        const long cell = cells[k];
+        const int pos[3] = {(int)(cell % nx), (int)((cell / nx) % ny), (int)(cell / ((long)nx * ny))};
+        double p[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < dim; ++a)
+            p[a] = image_in_window(pos[a] + 0.5, ref[a], n[a], bc[a] == ORC_PERIODIC);
+        double w = dim == 2 ? winding_2d(N, q, p) : winding_3d(N, q, T, tri, p);
+        inside[k] = fabs(w) > 0.5;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Time loop                                                                 */
 /* ------------------------------------------------------------------------ */

@@ -219,6 +219,18 @@ class Solver:
     def set_active(self, d, on):
         self._chk(self.lib.iblb_set_active(self.ctx, d, int(bool(on))))
 
+    def set_viscosity_ratio(self, d, lam):
+        """Viscosity ratio mu_in / mu_out of droplet d (1: one fluid)."""
+        self._chk(self.lib.iblb_set_viscosity_ratio(self.ctx, d, float(lam)))
+
+    def inside_mask(self, d):
+        """uint8 device tensor (nz, ny, nx): 1 for the cells of droplet d
+        enclosed by its interface at the current node positions."""
+        m = self._torch.empty(self.cells(d), dtype=self._torch.uint8, device=self.device)
+        self.stream.synchronize()
+        self._chk(self.lib.iblb_inside_mask(self.ctx, d, ctypes.c_void_p(m.data_ptr())))
+        return m
+
     def set_timing(self, on):
         self._chk(self.lib.iblb_set_timing(self.ctx, int(bool(on))))
 

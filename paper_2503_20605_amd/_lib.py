@@ -16,6 +16,7 @@ IBLB_EINVAL = -1
 IBLB_ENOMEM = -2
 IBLB_EDEVICE = -3
 IBLB_EUNSTABLE = -4
+IBLB_ELIMIT = -5
 IBLB_PERIODIC = 0
 IBLB_WALL = 1
 IBLB_F32 = 0
@@ -23,7 +24,7 @@ IBLB_F16 = 1
 IBLB_BF16 = 2
 
 STATUS_NAMES = {0: "IBLB_OK", -1: "IBLB_EINVAL", -2: "IBLB_ENOMEM", -3: "IBLB_EDEVICE",
-                -4: "IBLB_EUNSTABLE"}
+                -4: "IBLB_EUNSTABLE", -5: "IBLB_ELIMIT"}
 
 EXPORTED = (
     "iblb_workspace_bytes", "iblb_create", "iblb_destroy", "iblb_last_error",
@@ -31,7 +32,7 @@ EXPORTED = (
     "iblb_read_populations", "iblb_set_force_field", "iblb_step", "iblb_read_fields",
     "iblb_read_nodes", "iblb_diagnostics", "iblb_set_lb_variant", "iblb_autotune",
     "iblb_set_graph_steps", "iblb_set_active", "iblb_set_timing", "iblb_last_timing", "iblb_time_lattice",
-    "iblb_probe_copy", "iblb_run_to_rest",
+    "iblb_probe_copy", "iblb_run_to_rest", "iblb_set_viscosity_ratio", "iblb_inside_mask",
     "iblb_mlp_workspace_bytes", "iblb_mlp_create", "iblb_mlp_destroy", "iblb_mlp_last_error",
     "iblb_mlp_param_count", "iblb_mlp_set_params", "iblb_mlp_get_params", "iblb_mlp_forward",
     "iblb_mlp_gradients", "iblb_mlp_adam_step",
@@ -107,6 +108,8 @@ def load() -> ctypes.CDLL:
                                      P(ctypes.c_longlong)]
     lib.iblb_set_graph_steps.argtypes = [c_void_p, c_int]
     lib.iblb_set_active.argtypes = [c_void_p, c_int, c_int]
+    lib.iblb_set_viscosity_ratio.argtypes = [c_void_p, c_int, c_double]
+    lib.iblb_inside_mask.argtypes = [c_void_p, c_int, c_void_p]
     lib.iblb_set_timing.argtypes = [c_void_p, c_int]
     lib.iblb_last_timing.argtypes = [c_void_p, P(c_double), P(c_double)]
     lib.iblb_time_lattice.argtypes = [c_void_p, c_int, P(c_double)]

@@ -45,7 +45,7 @@ struct Layout {
     // byte offsets into the workspace
     size_t drops, tiles_lb, tiles_all, f0, f1, F, U, Fout, rho, flags, pos0, pos1, phi, qdot, dropped,
         node_drop, tri, inc, inc_beg, inc_end, perm, chunks, status, partials, diag, stamps, stamps_out,
-        total;
+        xcnt0, xcnt1, xpos0, xpos1, total;
     int nchunks;           // capacity of the 3D spreading chunk table
     long long cells;       // sum of cells
     long long flag_bytes;  // sum of band flags
@@ -54,6 +54,8 @@ struct Layout {
     std::vector<long long> c_off, flag_off, f_off;
     std::vector<int> fst;
     std::vector<int> node_off, tri_off;
+    std::vector<int> row_off;  // first row of each droplet in the crossing tables
+    long long rows = 0;        // lattice rows (z, y) of all droplets
 };
 
 // Element stride between the Q population arrays of a droplet: the cell
@@ -103,6 +105,8 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.flag_off.assign(n, 0);
     L.node_off.assign(n, 0);
     L.tri_off.assign(n, 0);
+    L.row_off.assign(n, 0);
+    L.rows = 0;
     int tiles[kShapes] = {0, 0, 0};
     for (int d = 0; d < n; ++d) {
         const iblb_params& p = P[d];
@@ -160,6 +164,9 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
         if (dim == 3) L.nchunks += nn[d];  // capacity: at worst one vertex per chunk
         L.tri_off[d] = L.ttot;
         L.ttot += T;
+        L.row_off[d] = (int)L.rows;
+        L.rows += (long long)p.ny * nz;
+        if (L.rows >= (1LL << 31) / kCrossCap) { err = "too many lattice rows"; return false; }
         for (int s = 0; s < kShapes; ++s) tiles[s] += tiles_of(p, s);
     }
     for (int s = 0; s < kShapes; ++s) L.max_tiles = std::max(L.max_tiles, tiles[s]);
@@ -194,6 +201,11 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.diag = take(sizeof(DiagDev) * n);
     L.stamps = take(sizeof(unsigned long long) * (size_t)kStampWords * kTimedLaunches);
     L.stamps_out = take(sizeof(unsigned long long) * 2 * kTimedLaunches);
+    // interface crossings of the lattice rows, one table pair per step parity
+    L.xcnt0 = take(sizeof(int) * L.rows);
+    L.xcnt1 = take(sizeof(int) * L.rows);
+    L.xpos0 = take(sizeof(double) * kCrossCap * L.rows);
+    L.xpos1 = take(sizeof(double) * kCrossCap * L.rows);
     L.total = o;
     return true;
 }
@@ -209,6 +221,7 @@ struct iblb_ctx {
     char* ws = nullptr;
     hipStream_t stream = nullptr, cap_stream = nullptr;
     int cur = 0;  // buffer holding the current post-collision populations
+    bool any_visc = false;  // some droplet has two viscosities
     int variant = 0;  // lattice-kernel variant; its tile shape is shape_of(variant)
     int ntiles_lb = 0, ntiles_all = 0;
     bool tiles_dirty = true;
@@ -273,6 +286,43 @@ NodeArrays node_arrays(const iblb_ctx* c, int p) {
     A.tstride = std::max(c->L.ttot, 1);
     A.ntot = c->L.ntot;
     return A;
+}
+
+// Classification window of a droplet centred on ref: [ref - n/2, ref + n/2)
+// along a periodic axis, [0, n) along a wall axis; and the x image rule
+// of the lattice kernel (cell centre c maps to c + img_base, plus nx when
+// c < img_r, which lands in the window).
+void set_window(DropDev& D, const int* bc, const double* ref) {
+    const int n[3] = {D.nx, D.ny, D.nz};
+    for (int a = 0; a < 3; ++a) D.win[a] = bc[a] == IBLB_PERIODIC ? ref[a] - 0.5 * n[a] : 0.0;
+    const double k0 = floor(D.win[0] / D.nx);
+    D.img_base = k0 * D.nx;
+    D.img_r = D.win[0] - D.img_base;
+}
+
+// Crossing tables of step parity p (see cell_inside).
+int* cross_count(const iblb_ctx* c, int p) { return c->at<int>(p ? c->L.xcnt1 : c->L.xcnt0); }
+double* cross_x(const iblb_ctx* c, int p) { return c->at<double>(p ? c->L.xpos1 : c->L.xpos0); }
+
+// Record the interface crossings of the lattice rows at the positions of
+// parity p into the tables of parity tp (every droplet with an interface
+// when all != 0, else the active ones with two viscosities).  The tables
+// must hold no crossings of these droplets yet.
+void launch_cross(const iblb_ctx* c, hipStream_t s, int p, int tp, int all) {
+    const NodeArrays A = node_arrays(c, p);
+    const DropDev* D = c->at<DropDev>(c->L.drops);
+    const bool one = c->n == 1;
+    int* st = c->at<int>(c->L.status);
+    if (c->dim == 2) {
+        if (c->L.ntot == 0) return;
+        hipLaunchKernelGGL(one ? k_cross2<true> : k_cross2<false>, dim3(ceil_div(c->L.ntot, kBlock)),
+                           dim3(kBlock), 0, s, D, A, cross_count(c, tp), cross_x(c, tp), st, all);
+    } else {
+        if (c->L.ttot == 0) return;
+        hipLaunchKernelGGL(one ? k_cross3<true> : k_cross3<false>, dim3(ceil_div(c->L.ttot, kBlock)),
+                           dim3(kBlock), 0, s, D, A, c->L.ttot, cross_count(c, tp), cross_x(c, tp),
+                           st, all);
+    }
 }
 
 void drop_graphs(iblb_ctx* c) {
@@ -356,8 +406,9 @@ int rebuild_tiles(iblb_ctx* c) {
 
 // ---- kernel dispatch -------------------------------------------------------
 
-template <int DIM, int S>
-void launch_lb_t(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned long long* stamps) {
+template <int DIM, int S, int VIS>
+void launch_lb_v(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned long long* stamps,
+                 bool clear) {
     using T = typename Codec<S>::T;
     T* f[2] = {c->at<T>(c->L.f0), c->at<T>(c->L.f1)};
     const dim3 grid(c->ntiles_lb), block(kBlock);
@@ -365,42 +416,61 @@ void launch_lb_t(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned l
         hipLaunchKernelGGL(kern, grid, block, 0, s, c->at<DropDev>(c->L.drops),
                            c->at<int4>(c->L.tiles_lb), (const T*)f[src], f[src ^ 1],
                            c->at<float>(c->L.F), c->at<float>(c->L.U), c->at<float>(c->L.rho),
-                           c->at<float>(c->L.Fout), c->at<uint8_t>(c->L.flags), full, stamps);
+                           c->at<float>(c->L.Fout), c->at<uint8_t>(c->L.flags), full, stamps,
+                           (const int*)cross_count(c, src), (const double*)cross_x(c, src),
+                           clear ? cross_count(c, src ^ 1) : nullptr);
     };
     switch (c->variant) {
-        case 0: go(k_lb<DIM, S, 256, 0, 0>); break;
-        case 1: go(k_lb<DIM, S, 128, 0, 0>); break;
-        case 2: go(k_lb<DIM, S, 64, 0, 0>); break;
-        case 3: go(k_lb<DIM, S, 256, 1, 0>); break;
-        case 4: go(k_lb<DIM, S, 128, 1, 0>); break;
-        case 5: go(k_lb<DIM, S, 64, 1, 0>); break;
-        case 6: go(k_lb<DIM, S, 256, 0, 1>); break;
-        case 7: go(k_lb<DIM, S, 128, 0, 1>); break;
-        case 8: go(k_lb<DIM, S, 64, 0, 1>); break;
-        case 9: go(k_lb<DIM, S, 256, 1, 1>); break;
-        case 10: go(k_lb<DIM, S, 128, 1, 1>); break;
-        default: go(k_lb<DIM, S, 64, 1, 1>); break;
+        case 0: go(k_lb<DIM, S, 256, 0, 0, VIS>); break;
+        case 1: go(k_lb<DIM, S, 128, 0, 0, VIS>); break;
+        case 2: go(k_lb<DIM, S, 64, 0, 0, VIS>); break;
+        case 3: go(k_lb<DIM, S, 256, 1, 0, VIS>); break;
+        case 4: go(k_lb<DIM, S, 128, 1, 0, VIS>); break;
+        case 5: go(k_lb<DIM, S, 64, 1, 0, VIS>); break;
+        case 6: go(k_lb<DIM, S, 256, 0, 1, VIS>); break;
+        case 7: go(k_lb<DIM, S, 128, 0, 1, VIS>); break;
+        case 8: go(k_lb<DIM, S, 64, 0, 1, VIS>); break;
+        case 9: go(k_lb<DIM, S, 256, 1, 1, VIS>); break;
+        case 10: go(k_lb<DIM, S, 128, 1, 1, VIS>); break;
+        default: go(k_lb<DIM, S, 64, 1, 1, VIS>); break;
     }
+}
+
+// The two-viscosity form of the lattice kernel runs only while some droplet
+// needs it (graphs are dropped when that changes).
+template <int DIM, int S>
+void launch_lb_t(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned long long* stamps,
+                 bool clear) {
+    if (c->any_visc)
+        launch_lb_v<DIM, S, 1>(c, s, src, full, stamps, clear);
+    else
+        launch_lb_v<DIM, S, 0>(c, s, src, full, stamps, clear);
 }
 
 template <int DIM>
-void launch_lb_d(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned long long* stamps) {
+void launch_lb_d(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned long long* stamps,
+                 bool clear) {
     switch (c->storage) {
-        case ST_F32: launch_lb_t<DIM, ST_F32>(c, s, src, full, stamps); break;
-        case ST_F16: launch_lb_t<DIM, ST_F16>(c, s, src, full, stamps); break;
-        default: launch_lb_t<DIM, ST_BF16>(c, s, src, full, stamps); break;
+        case ST_F32: launch_lb_t<DIM, ST_F32>(c, s, src, full, stamps, clear); break;
+        case ST_F16: launch_lb_t<DIM, ST_F16>(c, s, src, full, stamps, clear); break;
+        default: launch_lb_t<DIM, ST_BF16>(c, s, src, full, stamps, clear); break;
     }
 }
 
-void launch_lb(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned long long* stamps) {
+// Lattice update of parity src.  With two viscosities the kernel reads the
+// crossing tables of parity src and, with clear, empties those of the other
+// parity for the next step's crossings.
+void launch_lb(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned long long* stamps,
+               bool clear = true) {
     if (c->ntiles_lb == 0) return;
-    if (c->dim == 2) launch_lb_d<2>(c, s, src, full, stamps);
-    else launch_lb_d<3>(c, s, src, full, stamps);
+    if (c->dim == 2) launch_lb_d<2>(c, s, src, full, stamps, clear);
+    else launch_lb_d<3>(c, s, src, full, stamps, clear);
 }
 
 // Forces at the positions of parity p, spread for the step of parity p.
 void launch_spread(const iblb_ctx* c, hipStream_t s, int p, int want_dropped) {
     if (c->L.ntot == 0) return;
+    if (c->any_visc) launch_cross(c, s, p, p, 0);
     const NodeArrays A = node_arrays(c, p);
     const int lanes = c->L.ntot * (c->dim == 2 ? Taps<2>::n : Taps<3>::n);
     const dim3 grid(ceil_div(lanes, kBlock)), block(kBlock);
@@ -435,7 +505,7 @@ void launch_after(const iblb_ctx* c, hipStream_t s, int p, bool last, int want_d
     if (c->dim == 2 && !last) {
         hipLaunchKernelGGL(one ? k_ib_fused2<true> : k_ib_fused2<false>, grid, block, 0, s, D, A, U,
                            c->at<float>(c->L.F), c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status),
-                           want_dropped);
+                           want_dropped, cross_count(c, p ^ 1), cross_x(c, p ^ 1));
         return;
     }
     if (c->dim == 2)
@@ -689,6 +759,10 @@ int iblb_create(int n, const iblb_params* P, const int* nn, const int* nt, int s
         D.flag_off = L.flag_off[d];
         D.omega = (float)(1.0 / p.tau);
         D.guo = (float)(1.0 - 0.5 / p.tau);
+        D.visc = 0;
+        D.omega_in = D.omega;
+        D.guo_in = D.guo;
+        D.row_off = L.row_off[d];
         D.force_mode = 0;
         D.active = 1;
         D.node_off = L.node_off[d];
@@ -707,6 +781,8 @@ int iblb_create(int n, const iblb_params* P, const int* nn, const int* nt, int s
         // minimum of Pi(h): h* = xi (n/m)^(1/(n-m))
         D.zcut = p.wetting ? p.xi * pow((double)p.n_exp / p.m_exp, 1.0 / (p.n_exp - p.m_exp))
                            : p.xi;
+        const double centre[3] = {0.5 * p.nx, 0.5 * p.ny, 0.5 * D.nz};
+        set_window(D, p.bc, centre);
     }
     {
         int dev = 0, khz = 0;
@@ -869,6 +945,17 @@ int iblb_set_interface(iblb_ctx* c, int d, const double* h_pos, const int32_t* h
             if (!(h_pos[(size_t)(c->dim - 1) * N + k] > 0.0))
                 return fail(c, IBLB_EINVAL, "a node lies at or below the substrate (h <= 0)");
     std::vector<double> pos(h_pos, h_pos + (size_t)c->dim * N);
+    {
+        // window of the inside/outside classification: centred on the mean
+        // of the nodes
+        double ref[3] = {0.5 * D.nx, 0.5 * D.ny, 0.5 * D.nz};
+        for (int a = 0; a < c->dim; ++a) {
+            double sum = 0.0;
+            for (int k = 0; k < N; ++k) sum += pos[(size_t)a * N + k];
+            ref[a] = sum / N;
+        }
+        set_window(c->drops[d], c->params[d].bc, ref);
+    }
     for (int a = 0; a < c->dim; ++a)
         HIPCHK(c, hipMemcpyAsync(positions(c, c->cur) + (size_t)a * st + D.node_off,
                                  pos.data() + (size_t)a * N, sizeof(double) * N,
@@ -922,9 +1009,8 @@ int iblb_set_interface(iblb_ctx* c, int d, const double* h_pos, const int32_t* h
         if (rc) return rc;
     }
     HIPCHK(c, hipMemsetAsync(c->at<int>(c->L.status) + d, 0, sizeof(int), c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));  // host staging vectors go out of scope
     c->iface_set[d] = 1;
-    return IBLB_OK;
+    return upload_drops(c);  // synchronises: host staging vectors go out of scope
 }
 
 int iblb_init_rest(iblb_ctx* c, int d) {
@@ -1008,6 +1094,12 @@ int iblb_step(iblb_ctx* c, int n_steps) {
         int rc = rebuild_tiles(c);
         if (rc) return rc;
     }
+    if (c->any_visc) {
+        // the first step's crossings are recorded by launch_spread into the
+        // current tables; later steps find theirs cleared by the lattice
+        // kernel of the step before
+        HIPCHK(c, hipMemsetAsync(cross_count(c, c->cur), 0, sizeof(int) * c->L.rows, c->stream));
+    }
     if (c->timing) {
         // Same schedule as below (graph replays + direct launches), with the
         // lattice kernel stamping its own first block start and last store
@@ -1079,6 +1171,20 @@ int iblb_step(iblb_ctx* c, int n_steps) {
         c->step++;
         HIPCHK(c, hipGetLastError());
     }
+    if (n_steps & 1) {
+        // a frozen droplet's populations stay in the buffer that was current
+        // when the call began; after an odd number of steps the other buffer
+        // is current, so carry them over
+        const size_t sb = c->storage == ST_F32 ? 4 : 2;
+        char* now = c->ws + (c->cur ? c->L.f1 : c->L.f0);
+        const char* was = c->ws + (c->cur ? c->L.f0 : c->L.f1);
+        for (int d = 0; d < c->n; ++d) {
+            const DropDev& D = c->drops[d];
+            if (D.active) continue;
+            const size_t off = (size_t)D.f_off * sb, bytes = (size_t)c->Q * D.fst * sb;
+            HIPCHK(c, hipMemcpyAsync(now + off, was + off, bytes, hipMemcpyDeviceToDevice, c->stream));
+        }
+    }
     HIPCHK(c, hipMemcpyAsync(c->status_h.data(), c->at<int>(c->L.status), sizeof(int) * c->n,
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1086,12 +1192,14 @@ int iblb_step(iblb_ctx* c, int n_steps) {
         if (c->status_h[d] && c->drops[d].active) {
             char buf[256];
             const int code = c->status_h[d];
-            snprintf(buf, sizeof buf, "droplet %d unstable (code %d:%s%s%s) by step %lld", d, code,
+            snprintf(buf, sizeof buf, "droplet %d %s (code %d:%s%s%s%s) by step %lld", d,
+                     (code & 7) ? "unstable" : "over a fixed limit", code,
                      (code & 1) ? " node at or below the substrate" : "",
                      (code & 2) ? " node speed above 0.3 or not finite" : "",
                      (code & 4) ? " node position not finite or far outside the box" : "",
+                     (code & 8) ? " more than 16 interface crossings on one lattice row" : "",
                      (long long)c->step);
-            return fail(c, IBLB_EUNSTABLE, buf);
+            return fail(c, (code & 7) ? IBLB_EUNSTABLE : IBLB_ELIMIT, buf);
         }
     return IBLB_OK;
 }
@@ -1202,7 +1310,7 @@ int iblb_run_to_rest(iblb_ctx* c, double tol, int check_every, int hold, long lo
     while (live > 0 && c->step - start < max_steps) {
         const int n = (int)std::min<long long>(check_every, max_steps - (c->step - start));
         int rc = iblb_step(c, n);
-        if (rc == IBLB_EUNSTABLE) {
+        if (rc == IBLB_EUNSTABLE || rc == IBLB_ELIMIT) {
             // freeze the droplets that failed; the others carry on
             for (int d = 0; d < c->n; ++d)
                 if (c->status_h[d] && c->drops[d].active) {
@@ -1266,6 +1374,52 @@ int iblb_set_active(iblb_ctx* c, int d, int active) {
     return IBLB_OK;
 }
 
+int iblb_set_viscosity_ratio(iblb_ctx* c, int d, double lambda) {
+    if (!check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
+    if (!(lambda > 0.0) || !std::isfinite(lambda))
+        return fail(c, IBLB_EINVAL, "viscosity ratio must be positive and finite");
+    if (c->n_nodes[d] == 0) return fail(c, IBLB_EINVAL, "droplet has no interface");
+    const double tau = c->params[d].tau;
+    if (!std::isfinite(tau)) return fail(c, IBLB_EINVAL, "viscosity ratio needs a finite tau");
+    // mu = rho cs^2 (tau - 1/2) on both sides, lambda = mu_in / mu_out
+    const double tau_in = 0.5 + lambda * (tau - 0.5);
+    DropDev& D = c->drops[d];
+    D.visc = lambda != 1.0;
+    D.omega_in = (float)(1.0 / tau_in);
+    D.guo_in = (float)(1.0 - 0.5 / tau_in);
+    bool any = false;
+    for (int k = 0; k < c->n; ++k) any = any || c->drops[k].visc;
+    if (any != c->any_visc) {
+        c->any_visc = any;
+        drop_graphs(c);  // whether the crossing launches run is baked into them
+    }
+    return upload_drops(c);
+}
+
+int iblb_inside_mask(iblb_ctx* c, int d, uint8_t* d_mask) {
+    if (!check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
+    if (!d_mask) return fail(c, IBLB_EINVAL, "NULL mask");
+    if (c->n_nodes[d] == 0 || !c->iface_set[d] || c->drops[d].force_mode != 0)
+        return fail(c, IBLB_EINVAL, "droplet has no interface");
+    int before = 0, code = 0;
+    HIPCHK(c, hipMemcpyAsync(&before, c->at<int>(c->L.status) + d, sizeof(int), hipMemcpyDeviceToHost,
+                             c->stream));
+    // the current tables are rebuilt at the start of the next step call
+    HIPCHK(c, hipMemsetAsync(cross_count(c, c->cur), 0, sizeof(int) * c->L.rows, c->stream));
+    launch_cross(c, c->stream, c->cur, c->cur, 1);
+    hipLaunchKernelGGL(k_inside_mask, dim3(ceil_div(c->drops[d].ncell, kBlock)), dim3(kBlock), 0,
+                       c->stream, c->at<DropDev>(c->L.drops), d, (const int*)cross_count(c, c->cur),
+                       (const double*)cross_x(c, c->cur), d_mask);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(&code, c->at<int>(c->L.status) + d, sizeof(int), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    code &= ~before;
+    if (code & 4) return fail(c, IBLB_EUNSTABLE, "inside mask: node position not finite");
+    if (code & 8) return fail(c, IBLB_ELIMIT, "inside mask: more than 16 crossings on one lattice row");
+    return IBLB_OK;
+}
+
 int iblb_set_timing(iblb_ctx* c, int on) {
     if (!c) return IBLB_EINVAL;
     c->timing = on != 0;
@@ -1294,7 +1448,8 @@ int iblb_time_lattice(iblb_ctx* c, int launches, double* ms_per_launch) {
     if (!c->lexec) {
         hipGraph_t g = nullptr;
         HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < launches; ++k) launch_lb(c, c->cap_stream, c->cur ^ (k & 1), 0, nullptr);
+        for (int k = 0; k < launches; ++k)
+            launch_lb(c, c->cap_stream, c->cur ^ (k & 1), 0, nullptr, false);
         hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
         if (e != hipSuccess) return fail(c, IBLB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
         e = hipGraphInstantiate(&c->lexec, g, nullptr, nullptr, 0);
@@ -1305,6 +1460,15 @@ int iblb_time_lattice(iblb_ctx* c, int launches, double* ms_per_launch) {
         }
         c->lexec_n = launches;
         c->lexec_p = c->cur;
+    }
+    if (c->any_visc) {
+        // every launch classifies the cells at the current node positions:
+        // both parities' tables hold those crossings and are not cleared
+        // (the next step call rebuilds its own)
+        for (int tp = 0; tp < 2; ++tp) {
+            HIPCHK(c, hipMemsetAsync(cross_count(c, tp), 0, sizeof(int) * c->L.rows, c->stream));
+            launch_cross(c, c->stream, c->cur, tp, 0);
+        }
     }
     int rc = ensure_events(c, 2);
     if (rc) return rc;

@@ -54,6 +54,13 @@ struct DropDev {
     int wetting, n_exp, m_exp;
     int fst;              // element stride between population arrays (>= ncell)
     double sigma, A, xi, zcut;
+    // two viscosities (viscosity ratio != 1): cells enclosed by the
+    // interface relax with omega_in / guo_in
+    int visc;
+    int row_off;          // first lattice row (z * ny + y) of this droplet in the crossing tables
+    float omega_in, guo_in;
+    double win[3];        // classification window [win, win + n) of each axis
+    double img_base, img_r;  // x image of cell centre c: c + img_base (+ nx if c < img_r)
 };
 
 struct DiagDev {
@@ -160,6 +167,33 @@ struct Moments {
 };
 
 // ---------------------------------------------------------------------------
+// Cells enclosed by the interface (viscosity ratio != 1)
+// ---------------------------------------------------------------------------
+// The cells inside the closed interface relax with their own tau (Sec.
+// IB-LB, last paragraph).  They are found by casting a ray along +x through
+// every lattice row (the cell centres of one y, z): the node kernels record,
+// per row, the x at which the interface crosses the row's line, and a cell
+// is inside when an odd number of crossings lies beyond its centre.  The
+// interface is not wrapped across periodic boundaries: rows and cell
+// centres are taken at their periodic image inside the droplet's window
+// [win, win + n) of each axis, centred on the mean of the node positions.
+// Crossing tables: a count per row and kCrossCap x values per row, one pair
+// of tables per step parity.
+constexpr int kCrossCap = 16;
+
+__device__ __forceinline__ bool cell_inside(const DropDev& D, const int* __restrict__ cnt,
+                                            const double* __restrict__ xs, int x, int row) {
+    const long long r = (long long)D.row_off + row;
+    int n = cnt[r];
+    n = n < kCrossCap ? n : kCrossCap;
+    const double c = (double)x + 0.5;
+    const double xi = c + D.img_base + (c < D.img_r ? (double)D.nx : 0.0);
+    bool in = false;
+    for (int k = 0; k < n; ++k) in ^= xs[r * kCrossCap + k] > xi;
+    return in;
+}
+
+// ---------------------------------------------------------------------------
 // Lattice kernel
 // ---------------------------------------------------------------------------
 // NT = 1 writes the new populations with non-temporal stores: they are not
@@ -167,7 +201,9 @@ struct Moments {
 // NTL = 1 reads the populations with non-temporal loads: each is read once
 // per launch (neighbouring wavefronts share only the edges of the lines
 // that x-streamed populations straddle).
-template <int DIM, int S, int BX, int NT, int NTL>
+// VIS = 1 (instantiated only while some droplet of the handle has two
+// viscosities) takes each cell's relaxation time from the classification.
+template <int DIM, int S, int BX, int NT, int NTL, int VIS>
 __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops,
                                                const int4* __restrict__ tiles,
                                                const typename Codec<S>::T* __restrict__ fsrc_all,
@@ -176,7 +212,10 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
                                                float* __restrict__ rho_all,
                                                float* __restrict__ Fout_all,
                                                uint8_t* __restrict__ flags_all, int full,
-                                               unsigned long long* __restrict__ stamps) {
+                                               unsigned long long* __restrict__ stamps,
+                                               const int* __restrict__ xcnt,
+                                               const double* __restrict__ xpos,
+                                               int* __restrict__ xclr) {
     using L = Lattice<DIM>;
     using C = Codec<S>;
     constexpr int Q = L::Q;
@@ -242,7 +281,18 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
     }
     const Moments<DIM> M(f, Fx, Fy, Fz);
     const float rho = M.rho, ux = M.ux, uy = M.uy, uz = M.uz;
-    const float om = D.omega, g = D.guo;
+    float om = D.omega, g = D.guo;
+    if (VIS && D.visc) {
+        // every lane of a wavefront lies in the same row (BX >= 64)
+        const int row = __builtin_amdgcn_readfirstlane(z * ny + y);
+        if (cell_inside(D, xcnt, xpos, x, row)) {
+            om = D.omega_in;
+            g = D.guo_in;
+        }
+        // the other parity's table was read by the previous step: clear it
+        // for the crossings of the next step
+        if (x == 0 && xclr) xclr[D.row_off + row] = 0;
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const float fn = M.relax(i, f[i], om, g, forced);
@@ -570,6 +620,162 @@ __device__ __forceinline__ void hold_position(const NodeArrays& A, int j, int k)
 }
 
 // ---------------------------------------------------------------------------
+// Crossings of the interface with the lattice rows (see cell_inside)
+// ---------------------------------------------------------------------------
+// Record a crossing of droplet row r (z * ny + y) at x.  More than
+// kCrossCap crossings on one row set status bit 8.
+__device__ __forceinline__ void add_crossing(const DropDev& D, int* __restrict__ cnt,
+                                             double* __restrict__ xs, int r, double x,
+                                             int* __restrict__ status, int d) {
+    const long long rr = (long long)D.row_off + r;
+    const int slot = atomicAdd(cnt + rr, 1);
+    if (slot < kCrossCap)
+        xs[rr * kCrossCap + slot] = x;
+    else
+        atomicOr(status + d, 8);
+}
+
+// Row index of the image j of a row coordinate along an axis of n rows.
+__device__ __forceinline__ int wrap_row(int j, int n) {
+    j %= n;
+    return j < 0 ? j + n : j;
+}
+
+// Edge a -> b of a 2D polygon: crossings with the row lines y = j + 1/2
+// inside the window, each edge taken half-open in y so that a line through
+// a vertex is crossed once by the two edges that share it.  Coordinates
+// have passed coord_ok.
+__device__ __forceinline__ void cross_edge_2d(const DropDev& D, int* __restrict__ cnt,
+                                              double* __restrict__ xs, const double a[2],
+                                              const double b[2], int* __restrict__ status, int d) {
+    const double wlo = D.win[1], whi = D.win[1] + D.ny;
+    const double lo = fmax(fmin(a[1], b[1]), wlo), hi = fmin(fmax(a[1], b[1]), whi);
+    if (!(lo <= hi)) return;
+    const int j0 = (int)ceil(lo - 0.5), j1 = (int)floor(hi - 0.5);
+    for (int j = j0; j <= j1; ++j) {
+        const double Y = j + 0.5;
+        if ((a[1] <= Y) == (b[1] <= Y) || Y < wlo || Y >= whi) continue;
+        const double x = a[0] + (Y - a[1]) * (b[0] - a[0]) / (b[1] - a[1]);
+        add_crossing(D, cnt, xs, wrap_row(j, D.ny), x, status, d);
+    }
+}
+
+// Side of the point (y, z) relative to the directed edge P -> Q of a
+// triangle projected onto the y-z plane: the sign of the orientation,
+// computed from the edge's endpoints in the order of their node ids so that
+// the two triangles sharing an edge evaluate the same number; a zero is
+// resolved as for the point moved by (eps, eps^2).  val receives the
+// orientation itself (for barycentric weights).
+__device__ __forceinline__ int edge_side(const double P[3], int ip, const double Q[3], int iq,
+                                         double y, double z, double& val) {
+    const bool flip = ip > iq;
+    const double* A = flip ? Q : P;
+    const double* B = flip ? P : Q;
+    const double dy = B[1] - A[1], dz = B[2] - A[2];
+    const double o = dy * (z - A[2]) - dz * (y - A[1]);
+    int sg = o > 0.0 ? 1 : (o < 0.0 ? -1 : 0);
+    if (sg == 0) sg = dz != 0.0 ? (dz > 0.0 ? -1 : 1) : (dy > 0.0 ? 1 : (dy < 0.0 ? -1 : 0));
+    val = flip ? -o : o;
+    return flip ? -sg : sg;
+}
+
+// Triangle (node ids i[3], positions P[3][3]): crossings with the row lines
+// (y, z) = (j + 1/2, k + 1/2) inside the window whose projection the
+// triangle covers; x by barycentric interpolation.
+__device__ __forceinline__ void cross_tri_3d(const DropDev& D, int* __restrict__ cnt,
+                                             double* __restrict__ xs, const double P[3][3],
+                                             const int id[3], int* __restrict__ status, int d) {
+    const double ylo = D.win[1], yhi = D.win[1] + D.ny, zlo = D.win[2], zhi = D.win[2] + D.nz;
+    const double y0 = fmax(fmin(fmin(P[0][1], P[1][1]), P[2][1]), ylo);
+    const double y1 = fmin(fmax(fmax(P[0][1], P[1][1]), P[2][1]), yhi);
+    const double z0 = fmax(fmin(fmin(P[0][2], P[1][2]), P[2][2]), zlo);
+    const double z1 = fmin(fmax(fmax(P[0][2], P[1][2]), P[2][2]), zhi);
+    if (!(y0 <= y1 && z0 <= z1)) return;
+    const int j0 = (int)ceil(y0 - 0.5), j1 = (int)floor(y1 - 0.5);
+    const int k0 = (int)ceil(z0 - 0.5), k1 = (int)floor(z1 - 0.5);
+    for (int k = k0; k <= k1; ++k) {
+        const double Z = k + 0.5;
+        if (Z < zlo || Z >= zhi) continue;
+        for (int j = j0; j <= j1; ++j) {
+            const double Y = j + 0.5;
+            if (Y < ylo || Y >= yhi) continue;
+            double e0, e1, e2;
+            const int s0 = edge_side(P[1], id[1], P[2], id[2], Y, Z, e0);
+            const int s1 = edge_side(P[2], id[2], P[0], id[0], Y, Z, e1);
+            const int s2 = edge_side(P[0], id[0], P[1], id[1], Y, Z, e2);
+            if (s0 == 0 || s0 != s1 || s1 != s2) continue;
+            const double x = (e0 * P[0][0] + e1 * P[1][0] + e2 * P[2][0]) / (e0 + e1 + e2);
+            add_crossing(D, cnt, xs, wrap_row(k, D.nz) * D.ny + wrap_row(j, D.ny), x, status, d);
+        }
+    }
+}
+
+// Crossings of the interfaces at the positions A.pos: of the active
+// droplets with two viscosities, or of every droplet with an interface when
+// all != 0.  2D: one lane per polygon edge (node j to its ring successor).
+template <bool ONE>
+__global__ __launch_bounds__(kBlock) void k_cross2(const DropDev* __restrict__ drops, NodeArrays A,
+                                                   int* __restrict__ cnt, double* __restrict__ xs,
+                                                   int* __restrict__ status, int all) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= A.ntot) return;
+    const int d = node_droplet<ONE>(A, j);
+    const DropDev& D = drops[d];
+    if (D.force_mode != 0 || !(all || (D.active && D.visc))) return;
+    int jm, jp;
+    ring_2d(D, j, jm, jp);
+    const int st = A.stride;
+    const double a[2] = {A.pos[j], A.pos[st + j]}, b[2] = {A.pos[jp], A.pos[st + jp]};
+    if (!(coord_ok(a[0]) && coord_ok(a[1]) && coord_ok(b[0]) && coord_ok(b[1]))) {
+        atomicOr(status + d, 4);
+        return;
+    }
+    cross_edge_2d(D, cnt, xs, a, b, status, d);
+}
+
+// 3D: one lane per triangle.
+template <bool ONE>
+__global__ __launch_bounds__(kBlock) void k_cross3(const DropDev* __restrict__ drops, NodeArrays A,
+                                                   int ttot, int* __restrict__ cnt,
+                                                   double* __restrict__ xs, int* __restrict__ status,
+                                                   int all) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= ttot) return;
+    const int ts = A.tstride, st = A.stride;
+    const int id[3] = {A.tri[t], A.tri[ts + t], A.tri[2 * ts + t]};
+    const int d = node_droplet<ONE>(A, id[0]);
+    const DropDev& D = drops[d];
+    if (D.force_mode != 0 || !(all || (D.active && D.visc))) return;
+    double P[3][3];
+    bool ok = true;
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            P[m][a] = A.pos[a * st + id[m]];
+            ok = ok && coord_ok(P[m][a]);
+        }
+    if (!ok) {
+        atomicOr(status + d, 4);
+        return;
+    }
+    cross_tri_3d(D, cnt, xs, P, id, status, d);
+}
+
+// Inside (1) / outside (0) of every cell of droplet d from the crossing
+// tables, one lane per cell.
+__global__ __launch_bounds__(kBlock) void k_inside_mask(const DropDev* __restrict__ drops, int d,
+                                                        const int* __restrict__ cnt,
+                                                        const double* __restrict__ xs,
+                                                        uint8_t* __restrict__ mask) {
+    const DropDev& D = drops[d];
+    const int cell = blockIdx.x * kBlock + threadIdx.x;
+    if (cell >= D.ncell) return;
+    const int x = cell % D.nx, row = cell / D.nx;
+    mask[cell] = cell_inside(D, cnt, xs, x, row) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
 // Interpolation (eq. vel_interpolation) + forward-Euler advection
 // ---------------------------------------------------------------------------
 template <int DIM, bool ONE>
@@ -778,7 +984,9 @@ __global__ __launch_bounds__(kBlock) void k_ib_fused2(const DropDev* __restrict_
                                                       const float* __restrict__ U_all,
                                                       float* __restrict__ F_all,
                                                       uint8_t* __restrict__ flags_all,
-                                                      int* __restrict__ status, int want_dropped) {
+                                                      int* __restrict__ status, int want_dropped,
+                                                      int* __restrict__ xcnt,
+                                                      double* __restrict__ xpos) {
     constexpr int T = Taps<2>::n;
     const int gid = blockIdx.x * kBlock + threadIdx.x;
     const int j = gid / T, k = gid % T;
@@ -846,6 +1054,8 @@ __global__ __launch_bounds__(kBlock) void k_ib_fused2(const DropDev* __restrict_
         if (k == 0) atomicOr(status + d, 4);
         return;
     }
+    // crossings of edge j -> j+1 at the new positions, for the next step
+    if (D.visc && k == 1) cross_edge_2d(D, xcnt, xpos, qn[1], qn[2], status, d);
     double fs[2], n[2], chi;
     geom_2d(D.sigma, qn[0], qn[1], qn[2], fs, n, chi);
     if (D.wetting) {

@@ -165,6 +165,29 @@ int main(int argc, char** argv) {
     if (cfg.count("timing")) iblb_set_timing(ctx, geti("timing", 0));
     for (int d = 0; d < n; ++d)
         if (geti("inactive_" + std::to_string(d), 0)) iblb_set_active(ctx, d, 0);
+    for (int d = 0; d < n; ++d) {
+        const std::string key = "lambda_" + std::to_string(d);
+        if (cfg.count(key) && iblb_set_viscosity_ratio(ctx, d, atof(cfg[key].c_str()))) {
+            fprintf(stderr, "viscosity ratio: %s\n", iblb_last_error(ctx));
+            return 13;
+        }
+    }
+    // inside/outside classification at the initial positions
+    auto save_masks = [&](const char* tag) -> int {
+        for (int d = 0; d < n; ++d) {
+            if (nn[d] == 0) continue;
+            const long cells = (long)P[d].nx * P[d].ny * (dim == 3 ? P[d].nz : 1);
+            uint8_t* m = buf<uint8_t>(cells);
+            if (iblb_inside_mask(ctx, d, m)) {
+                fprintf(stderr, "inside mask: %s\n", iblb_last_error(ctx));
+                return 14;
+            }
+            save(std::string(tag) + std::to_string(d) + ".bin", m, cells);
+            free(m);
+        }
+        return 0;
+    };
+    if (geti("mask", 0) && (rc = save_masks("inside0_"))) return rc;
     int step_rc = 0;
     {
         std::stringstream ss(cfg.count("steps") ? cfg["steps"] : "1");
@@ -183,6 +206,7 @@ int main(int argc, char** argv) {
         step_rc = iblb_run_to_rest(ctx, tol, check, hold, mx, so.data());
         save("rest_steps.bin", so.data(), n);
     }
+    if (geti("mask", 0) && step_rc == 0 && (rc = save_masks("inside1_"))) return rc;
     FILE* st = fopen((dir + "/status.txt").c_str(), "w");
     fprintf(st, "%d\n%s\n", step_rc, iblb_last_error(ctx));
     fclose(st);

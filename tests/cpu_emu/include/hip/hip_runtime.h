@@ -215,6 +215,11 @@ inline int atomicMax(int* p, int v) {
     if (v > old) *p = v;
     return old;
 }
+inline int atomicAdd(int* p, int v) {
+    int old = *p;
+    *p = old + v;
+    return old;
+}
 inline float atomicAdd(float* p, float v) {
     float old = *p;
     *p = old + v;

@@ -33,7 +33,7 @@ def run_cases(jobs):
 
 def run_case(params_list, nodes_list=None, tris_list=None, steps=(1,), storage=0,
              graph_steps=None, shape=None, f0dev=None, forces=None, timing=False,
-             inactive=(), rest=None, timeout=600, direct_chunks=False):
+             inactive=(), rest=None, timeout=600, direct_chunks=False, masks=False):
     import build as emu_build
     from paper_2503_20605_amd._lib import iblb_diag
     with _build_lock:
@@ -59,7 +59,12 @@ def run_case(params_list, nodes_list=None, tris_list=None, steps=(1,), storage=0
             cfg.append(f"inactive_{k} 1")
         if rest is not None:
             cfg.append("rest " + ",".join(str(v) for v in rest))
+        if masks:
+            cfg.append("mask 1")
         for k in range(n):
+            lam = float(getattr(params_list[k], "lam", 1.0))
+            if lam != 1.0:
+                cfg.append(f"lambda_{k} {lam!r}")
             q = nodes_list[k]
             if q is not None:
                 q = np.asarray(q, dtype=np.float64)
@@ -101,6 +106,11 @@ def run_case(params_list, nodes_list=None, tris_list=None, steps=(1,), storage=0
                      U=ld("U", np.float32, (dim,) + sh).astype(np.float64),
                      F=ld("F", np.float32, (dim,) + sh).astype(np.float64),
                      fdev=ld("fdev", np.float64, (Q,) + sh))
+            if masks and nodes_list[k] is not None:
+                for tag in ("inside0", "inside1"):
+                    fn = os.path.join(d, f"{tag}_{k}.bin")
+                    if os.path.exists(fn):
+                        o[tag] = np.fromfile(fn, dtype=np.uint8).reshape(sh)
             if nodes_list[k] is not None:
                 N = np.asarray(nodes_list[k]).shape[0]
                 o["q"] = ld("q", np.float64, (dim, N)).T.copy()

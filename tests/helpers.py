@@ -16,7 +16,12 @@ def weights(dim):
 def gpu_solver(params_list, nodes_list=None, tris_list=None, storage=0):
     from paper_2503_20605_amd import Solver, params_from
     P = [params_from(p) for p in params_list]
-    return Solver(P, nodes_list, tris_list, storage=storage)
+    s = Solver(P, nodes_list, tris_list, storage=storage)
+    for d, p in enumerate(params_list):
+        lam = float(getattr(p, "lam", 1.0))
+        if lam != 1.0:
+            s.set_viscosity_ratio(d, lam)
+    return s
 
 
 def gpu_run(p, q0, steps, tris=None, storage=0, f0dev=None, F_fixed=None, graph_steps=None,

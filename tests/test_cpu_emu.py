@@ -43,6 +43,14 @@ def _coarse3d_case():
     return p, V, T
 
 
+def _visc3d_case():
+    """Coarse cap across the periodic x edge, viscosity ratio 4."""
+    p = wl.Params(dim=3, nx=24, ny=22, nz=14, bc=(0, 0, 1), tau=0.7, sigma=0.006,
+                  theta_eq_deg=80.0, xi=2.0, lam=4.0)
+    V, T = wl.cap_mesh(7.0, 90.0, 2.0, 4, (1.5, 10.3))
+    return p, V, T
+
+
 def _blowup_case():
     p = wl.Params(dim=2, nx=64, ny=32, tau=1.0, sigma=50.0, theta_eq_deg=60.0, xi=2.0)
     q = wl.cap_polygon(8.0, 90.0, 2.0, 40, 32.0)
@@ -54,7 +62,10 @@ def _background_jobs():
     p3, V3, T3 = _tiny3d_case()
     pc, Vc, Tc = _coarse3d_case()
     pb, qb = _blowup_case()
+    pv, Vv, Tv = _visc3d_case()
     return {
+        "visc3d": dict(params_list=[pv], nodes_list=[Vv], tris_list=[Tv], steps=(1, 2), graph_steps=2,
+                       masks=True),
         "rest": dict(params_list=ps, nodes_list=qs, steps=(0,), rest=(2e-3, 4, 2, 60), graph_steps=2),
         "tiny3d": dict(params_list=[p3], nodes_list=[V3], tris_list=[T3], steps=(3,), graph_steps=2),
         "coarse3d": dict(params_list=[pc], nodes_list=[Vc], tris_list=[Tc], steps=(2,), graph_steps=2),
@@ -117,6 +128,72 @@ def test_batch_with_fluid_only_member():
     drho, du, dq = compare_fields(out[0], r, 2, "emu batch timed")
     assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
     assert np.array_equal(out[1]["q"], qs[1]) and np.all(out[1]["fdev"] == 0)
+
+
+def test_two_viscosities_2d_across_periodic_edge():
+    """Viscosity ratio 10, ragged box, droplet across the periodic x edge:
+    the classification at the initial and the final node positions equals
+    the oracle's, and 7 steps (graph replays and direct launches) match the
+    oracle's run."""
+    p = wl.Params(dim=2, nx=101, ny=37, tau=0.7, sigma=0.008, theta_eq_deg=110.0, xi=2.0, lam=10.0)
+    q = wl.cap_polygon(10.0, 95.0, 2.0, 70, 2.0)
+    g = run_case([p], [q], steps=(3, 4), graph_steps=2, masks=True)[0]
+    assert g["status"] == 0, g["message"]
+    ref = o.reference_point(q)
+    m0 = o.inside_mask(p, q, ref=ref)
+    assert np.array_equal(g["inside0"], m0) and m0.sum() > 150
+    assert np.array_equal(g["inside1"], o.inside_mask(p, g["q"], ref=ref))
+    r = o.run(p, q, 7)
+    drho, du, dq = compare_fields(g, r, 2, "emu two viscosities 2d")
+    assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
+    # the ratio matters at this tolerance
+    p1 = wl.Params(**{**p.to_dict(), "lam": 1.0})
+    r1 = o.run(p1, q, 7)
+    assert np.max(np.abs(r1["U"] - r["U"])) > 1e-4
+
+
+def test_two_viscosities_batch_mixed():
+    """A batch with a one-fluid droplet, a droplet with ratio 0.2 and a
+    frozen droplet with ratio 5, stepped an odd number of steps per call."""
+    ps = [wl.Params(dim=2, nx=60, ny=30, tau=0.8, sigma=0.006, theta_eq_deg=50.0, xi=2.0),
+          wl.Params(dim=2, nx=50, ny=28, tau=1.1, sigma=0.009, theta_eq_deg=120.0, xi=2.0, lam=0.2),
+          wl.Params(dim=2, nx=40, ny=24, tau=0.9, sigma=0.007, theta_eq_deg=90.0, xi=2.0, lam=5.0)]
+    qs = [wl.cap_polygon(8.0, 90.0, 2.0, 50, 30.0), wl.cap_polygon(7.0, 90.0, 2.0, 44, 25.0),
+          wl.cap_polygon(6.0, 90.0, 2.0, 40, 20.0)]
+    out = run_case(ps, qs, steps=(3, 2), graph_steps=2, inactive=(2,), masks=True)
+    for d in range(2):
+        r = o.run(ps[d], qs[d], 5)
+        drho, du, dq = compare_fields(out[d], r, 2, f"emu mixed{d}")
+        assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
+        assert np.array_equal(out[d]["inside0"], o.inside_mask(ps[d], qs[d]))
+    assert np.array_equal(out[2]["q"], qs[2]) and np.all(out[2]["fdev"] == 0)
+    assert np.array_equal(out[2]["inside1"], o.inside_mask(ps[2], qs[2]))
+
+
+def test_too_many_crossings_on_a_row_is_reported():
+    """A comb-shaped outline crosses some rows 24 times: the step reports
+    IBLB_ELIMIT and drops the extra crossings (no access beyond the
+    tables)."""
+    pts = [(2.0, 2.0), (56.0, 2.0), (56.0, 4.0)]
+    for k in range(11, -1, -1):
+        pts += [(6.0 + 4 * k, 4.0), (6.0 + 4 * k, 20.0), (4.0 + 4 * k, 20.0), (4.0 + 4 * k, 4.0)]
+    q = np.array(pts + [(2.0, 4.0)]) + np.array([0.25, 0.125])
+    p = wl.Params(dim=2, nx=64, ny=32, tau=0.8, sigma=0.005, wetting=False, lam=3.0)
+    g = run_case([p], [q], steps=(2,), graph_steps=0)[0]
+    assert g["status"] == -5 and "crossings" in g["message"]
+
+
+def test_two_viscosities_3d(background):
+    p, V, T = _visc3d_case()
+    g = background["visc3d"].result()[0]
+    assert g["status"] == 0, g["message"]
+    ref = o.reference_point(V)
+    m0 = o.inside_mask(p, V, T, ref=ref)
+    assert np.array_equal(g["inside0"], m0) and m0.sum() > 300
+    assert np.array_equal(g["inside1"], o.inside_mask(p, g["q"], T, ref=ref))
+    r = o.run(p, V, 3, tris=T)
+    drho, du, dq = compare_fields(g, r, 3, "emu two viscosities 3d")
+    assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
 
 
 def test_droplet_3d_tiny(background):

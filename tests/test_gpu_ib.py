@@ -212,14 +212,17 @@ def test_time_lattice_replays_plain_lattice_steps():
     assert np.array_equal(a.read_populations(0).cpu().numpy(), b.read_populations(0).cpu().numpy())
 
 
-def test_zero_steps_and_frozen_handle_change_nothing():
+@pytest.mark.parametrize("frozen_steps", [10, 9])
+def test_zero_steps_and_frozen_handle_change_nothing(frozen_steps):
+    """A frozen droplet keeps its state through an even or odd number of
+    steps and resumes from it."""
     W = wl.droplet_2d_small()
     s = gpu_solver([W.params], [W.nodes])
     s.step(3)
     a = collect(s, 0, 2)
     s.step(0)
     s.set_active(0, False)
-    s.step(10)
+    s.step(frozen_steps)
     b = collect(s, 0, 2)
     assert np.array_equal(a["fdev"], b["fdev"]) and np.array_equal(a["q"], b["q"])
     s.set_active(0, True)

@@ -219,3 +219,11 @@ def test_run_classifies_at_the_start_of_each_step():
     # and lam changes the result
     p1 = wl.Params(**{**p.to_dict(), "lam": 1.0})
     assert not np.array_equal(o.run(p1, q, 1)["f"], f)
+
+
+def test_inside_cells_matches_the_full_mask():
+    p = wl.Params(dim=3, nx=18, ny=16, nz=16, bc=(wl.BC_PERIODIC, wl.BC_PERIODIC, wl.BC_WALL))
+    V, T = wl.sphere_mesh(5.6, 4, (16.9, 8.2, 8.1))
+    m = o.inside_mask(p, V, T).ravel()
+    cells = np.arange(m.size)[3::5]
+    assert np.array_equal(o.inside_cells(p, V, cells, T), m[cells])

@@ -273,6 +273,20 @@ def droplet_3d(theta_eq_deg: float = 90.0, small: bool = False) -> Workload:
     return Workload(name, p, V, tris=T)
 
 
+def droplet_3d_spreading(lam: float = 10.0, theta_eq_deg: float = 60.0) -> Workload:
+    """Set-up of the paper's spreading runs (Sec. Dynamics): a 240x240x130
+    D3Q19 box (periodic x and y, walls at z = 0 and z = 130), a sphere of
+    radius R0 = 60 whose lowest point sits at h = 1.5 xi above the
+    substrate, xi = 2, viscosity ratio lam.  The sphere is a frequency-64
+    icosphere (81920 triangles, 40962 vertices, edges about 1 lattice unit);
+    tau_out = 0.8, sigma = 0.005 (the paper does not list them)."""
+    p = Params(dim=3, nx=240, ny=240, nz=130, bc=(BC_PERIODIC, BC_PERIODIC, BC_WALL),
+               tau=0.8, sigma=0.005, theta_eq_deg=theta_eq_deg, xi=2.0, lam=lam)
+    R0 = 60.0
+    V, T = sphere_mesh(R0, 64, (120.0, 120.0, R0 + 1.5 * p.xi))
+    return Workload(f"d3q19_240x240x130_R60_lam{lam:g}", p, V, tris=T)
+
+
 # ----------------------------------------------------------------------------
 # Raw arrays for unit and parity tests
 # ----------------------------------------------------------------------------
