@@ -372,6 +372,34 @@ def contact_radius_3d(q, tris, zcut):
     return float(np.mean(np.linalg.norm(p[:, :2] - c, axis=1)))
 
 
+def contact_radius_flat_3d(q, tris, tol):
+    """Protocol (ii) of Sec. Dynamics: the triangles of the lower half of the
+    droplet (all three vertices below the mid-height between the lowest and
+    the highest vertex) whose vertices differ in height by less than tol
+    (= eps R0) form the flat region; its area chi is taken as a circle's,
+    r = sqrt(chi / pi)."""
+    z = q[:, 2]
+    mid = 0.5 * (z.min() + z.max())
+    a, b, c = q[tris[:, 0]], q[tris[:, 1]], q[tris[:, 2]]
+    zt = z[tris]
+    lower = np.all(zt < mid, axis=1)
+    flat = (zt.max(axis=1) - zt.min(axis=1)) < tol
+    area = 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)
+    chi = float(np.sum(area[lower & flat]))
+    return math.sqrt(chi / math.pi)
+
+
+def contact_radius_flat_2d(q, tol):
+    """2D counterpart of protocol (ii): the edges of the lower half whose end
+    points differ in height by less than tol; half their total length."""
+    y = q[:, 1]
+    mid = 0.5 * (y.min() + y.max())
+    yn = np.roll(y, -1)
+    sel = (y < mid) & (yn < mid) & (np.abs(yn - y) < tol)
+    length = np.linalg.norm(np.roll(q, -1, axis=0) - q, axis=1)
+    return 0.5 * float(np.sum(length[sel]))
+
+
 def angle_from_height_3d(ell, volume):
     """eq. (angleh): tan^2(theta/2) = 3 l^3 / (R0^3 - l^3), R0 the radius of
     the sphere of equal volume, l the half-height."""
