@@ -260,6 +260,23 @@ int iblb_set_viscosity_ratio(iblb_ctx *ctx, int droplet, double lambda);
  * IBLB_EUNSTABLE for a non-finite node.  Synchronises the stream. */
 int iblb_inside_mask(iblb_ctx *ctx, int droplet, uint8_t *d_mask);
 
+/* Contact radius of droplet d at its current node positions by the two
+ * protocols of Sec. "Dynamics" (the flat base of the interface stands for
+ * the contact area).  h is the last coordinate (height above the substrate).
+ *   out[0]  protocol (i): the interface cut by the plane h = z_cut; 3D: the
+ *           mean distance of the points where mesh edges cross the plane to
+ *           their centre; 2D: half the distance between the outermost
+ *           crossings of the line.  NaN when the plane does not cut it.
+ *   out[1]  protocol (ii): the elements (3D triangles, 2D edges) whose nodes
+ *           all lie below the mid-height between the lowest and the highest
+ *           node and differ in height by less than flat_tol (eps R0 in the
+ *           paper's notation) form the flat region; 3D: radius of the disc
+ *           of its area, 2D: half its length.
+ *   out[2]  number of crossings found by protocol (i).
+ * out: host, 3 doubles.  EINVAL without an interface, for a non-finite
+ * z_cut or a negative flat_tol.  Synchronises the stream. */
+int iblb_contact_radius(iblb_ctx *ctx, int droplet, double z_cut, double flat_tol, double *out);
+
 /* With timing on, iblb_step() runs the same schedule (graph replays plus
  * direct launches) while the lattice kernel stamps its first block start
  * and its last wavefront end (after that wavefront's stores complete) on

@@ -231,6 +231,13 @@ class Solver:
         self._chk(self.lib.iblb_inside_mask(self.ctx, d, ctypes.c_void_p(m.data_ptr())))
         return m
 
+    def contact_radius(self, d, z_cut, flat_tol):
+        """(protocol (i) radius at z_cut, protocol (ii) radius with flatness
+        tolerance flat_tol, number of protocol (i) crossings) of droplet d."""
+        out = (ctypes.c_double * 3)()
+        self._chk(self.lib.iblb_contact_radius(self.ctx, d, float(z_cut), float(flat_tol), out))
+        return out[0], out[1], int(out[2])
+
     def set_timing(self, on):
         self._chk(self.lib.iblb_set_timing(self.ctx, int(bool(on))))
 

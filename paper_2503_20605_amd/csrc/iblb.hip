@@ -67,6 +67,10 @@ struct Layout {
 #define IBLB_POP_PAD 64
 #endif
 constexpr int kPopPad = IBLB_POP_PAD;
+#ifndef IBLB_POP_ROUND
+#define IBLB_POP_ROUND 64
+#endif
+constexpr long long kPopRound = IBLB_POP_ROUND;
 
 // Cell budget of a 3D spreading chunk's tap box when the host cuts chunks
 // (see morton_order); the kernel's own limit is kBoxCells.
@@ -75,7 +79,7 @@ constexpr int kPopPad = IBLB_POP_PAD;
 #endif
 
 long long pop_stride(long long cells) {
-    return (cells + 63) / 64 * 64 + kPopPad;
+    return (cells + kPopRound - 1) / kPopRound * kPopRound + kPopPad;
 }
 
 int tiles_of(const iblb_params& p, int shape) {
@@ -1417,6 +1421,26 @@ int iblb_inside_mask(iblb_ctx* c, int d, uint8_t* d_mask) {
     code &= ~before;
     if (code & 4) return fail(c, IBLB_EUNSTABLE, "inside mask: node position not finite");
     if (code & 8) return fail(c, IBLB_ELIMIT, "inside mask: more than 16 crossings on one lattice row");
+    return IBLB_OK;
+}
+
+int iblb_contact_radius(iblb_ctx* c, int d, double z_cut, double flat_tol, double* out) {
+    if (!check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
+    if (!out) return fail(c, IBLB_EINVAL, "NULL output");
+    if (c->n_nodes[d] == 0 || !c->iface_set[d]) return fail(c, IBLB_EINVAL, "droplet has no interface");
+    if (!std::isfinite(z_cut) || !(flat_tol >= 0.0))
+        return fail(c, IBLB_EINVAL, "z_cut must be finite and flat_tol >= 0");
+    double* dev = c->at<double>(c->L.partials);
+    const NodeArrays A = node_arrays(c, c->cur);
+    if (c->dim == 2)
+        hipLaunchKernelGGL(k_contact<2>, dim3(1), dim3(kBlock), 0, c->stream, c->at<DropDev>(c->L.drops), d,
+                           A, z_cut, flat_tol, dev);
+    else
+        hipLaunchKernelGGL(k_contact<3>, dim3(1), dim3(kBlock), 0, c->stream, c->at<DropDev>(c->L.drops), d,
+                           A, z_cut, flat_tol, dev);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(out, dev, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return IBLB_OK;
 }
 

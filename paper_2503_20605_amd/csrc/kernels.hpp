@@ -1356,4 +1356,110 @@ __global__ __launch_bounds__(kBlock) void k_diag(const DropDev* __restrict__ dro
     if (threadIdx.x == 0) out[d] = r;
 }
 
+// Contact radius of droplet d at the positions A.pos by the two protocols
+// of Sec. Dynamics, one workgroup.  (i) the interface cut by the plane
+// (2D: line) at height zcut: 2D half the distance between the outermost
+// crossings, 3D the mean distance of the edge crossings to their centre.
+// (ii) the flat lower region: the elements (2D edges, 3D triangles) whose
+// nodes all lie below the mid-height between the lowest and the highest
+// node and differ in height by less than tol; 2D half its length, 3D the
+// radius of the disc of its area.  out: r_i (NaN without crossings), r_ii,
+// number of crossings.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_contact(const DropDev* __restrict__ drops, int d, NodeArrays A,
+                                                    double zcut, double tol, double* __restrict__ out) {
+    __shared__ double sh[kBlock / 64];
+    const DropDev& D = drops[d];
+    const int st = A.stride, N = D.n_nodes, j0 = D.node_off, H = DIM - 1;
+    double hmin = 1e300, hmax = -1e300;
+    for (int l = threadIdx.x; l < N; l += kBlock) {
+        const double h = A.pos[H * st + j0 + l];
+        hmin = fmin(hmin, h);
+        hmax = fmax(hmax, h);
+    }
+    hmin = block_reduce(hmin, 1, sh);
+    hmax = block_reduce(hmax, 2, sh);
+    const double mid = 0.5 * (hmin + hmax);
+    double lo = 1e300, hi = -1e300, cx = 0.0, cy = 0.0, cn = 0.0, flat = 0.0;
+    const int ts = A.tstride;
+    if (DIM == 2) {
+        for (int l = threadIdx.x; l < N; l += kBlock) {
+            const int j = j0 + l, jp = j0 + (l == N - 1 ? 0 : l + 1);
+            const double x0 = A.pos[j], y0 = A.pos[st + j], x1 = A.pos[jp], y1 = A.pos[st + jp];
+            const double a0 = y0 - zcut, a1 = y1 - zcut;
+            if (a0 * a1 < 0.0 || (a0 == 0.0 && a1 != 0.0)) {
+                const double xs = x0 + a0 / (a0 - a1) * (x1 - x0);
+                lo = fmin(lo, xs);
+                hi = fmax(hi, xs);
+                cn += 1.0;
+            }
+            if (y0 < mid && y1 < mid && fabs(y1 - y0) < tol)
+                flat += sqrt((x1 - x0) * (x1 - x0) + (y1 - y0) * (y1 - y0));
+        }
+    } else {
+        for (int t = D.tri_off + threadIdx.x; t < D.tri_off + D.n_tris; t += kBlock) {
+            const int v[3] = {A.tri[t], A.tri[ts + t], A.tri[2 * ts + t]};
+            double P[3][3];
+            for (int m = 0; m < 3; ++m)
+                for (int a = 0; a < 3; ++a) P[m][a] = A.pos[a * st + v[m]];
+            for (int m = 0; m < 3; ++m) {
+                const int m1 = m == 2 ? 0 : m + 1;
+                if (v[m] >= v[m1]) continue;  // each edge once
+                const double a0 = P[m][2] - zcut, a1 = P[m1][2] - zcut;
+                if (a0 * a1 < 0.0) {
+                    const double s = a0 / (a0 - a1);
+                    cx += P[m][0] + s * (P[m1][0] - P[m][0]);
+                    cy += P[m][1] + s * (P[m1][1] - P[m][1]);
+                    cn += 1.0;
+                }
+            }
+            const double zlo = fmin(fmin(P[0][2], P[1][2]), P[2][2]);
+            const double zhi = fmax(fmax(P[0][2], P[1][2]), P[2][2]);
+            if (zhi < mid && zhi - zlo < tol) {
+                const double e1[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+                const double e2[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+                const double nt[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                                      e1[0] * e2[1] - e1[1] * e2[0]};
+                flat += 0.5 * sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+            }
+        }
+    }
+    lo = block_reduce(lo, 1, sh);
+    hi = block_reduce(hi, 2, sh);
+    cn = block_reduce(cn, 0, sh);
+    flat = block_reduce(flat, 0, sh);
+    double ri = __builtin_nan("");
+    if (DIM == 2) {
+        if (cn >= 2.0) ri = 0.5 * (hi - lo);
+    } else {
+        cx = block_reduce(cx, 0, sh);
+        cy = block_reduce(cy, 0, sh);
+        double dsum = 0.0;
+        if (cn > 0.0) {
+            const double mx = cx / cn, my = cy / cn;
+            for (int t = D.tri_off + threadIdx.x; t < D.tri_off + D.n_tris; t += kBlock) {
+                const int v[3] = {A.tri[t], A.tri[ts + t], A.tri[2 * ts + t]};
+                for (int m = 0; m < 3; ++m) {
+                    const int m1 = m == 2 ? 0 : m + 1;
+                    if (v[m] >= v[m1]) continue;
+                    const double z0 = A.pos[2 * st + v[m]] - zcut, z1 = A.pos[2 * st + v[m1]] - zcut;
+                    if (z0 * z1 < 0.0) {
+                        const double s = z0 / (z0 - z1);
+                        const double px = A.pos[v[m]] + s * (A.pos[v[m1]] - A.pos[v[m]]);
+                        const double py = A.pos[st + v[m]] + s * (A.pos[st + v[m1]] - A.pos[st + v[m]]);
+                        dsum += sqrt((px - mx) * (px - mx) + (py - my) * (py - my));
+                    }
+                }
+            }
+        }
+        dsum = block_reduce(dsum, 0, sh);
+        if (cn > 0.0) ri = dsum / cn;
+    }
+    if (threadIdx.x == 0) {
+        out[0] = ri;
+        out[1] = DIM == 2 ? 0.5 * flat : sqrt(flat / 3.14159265358979323846);
+        out[2] = cn;
+    }
+}
+
 }  // namespace iblb

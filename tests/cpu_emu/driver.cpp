@@ -207,6 +207,19 @@ int main(int argc, char** argv) {
         save("rest_steps.bin", so.data(), n);
     }
     if (geti("mask", 0) && step_rc == 0 && (rc = save_masks("inside1_"))) return rc;
+    if (cfg.count("contact")) {  // z_cut,flat_tol
+        double zc = 0, tol = 0;
+        sscanf(cfg["contact"].c_str(), "%lf,%lf", &zc, &tol);
+        for (int d = 0; d < n; ++d) {
+            if (nn[d] == 0) continue;
+            double r[3];
+            if (iblb_contact_radius(ctx, d, zc, tol, r)) {
+                fprintf(stderr, "contact radius: %s\n", iblb_last_error(ctx));
+                return 15;
+            }
+            save("contact_" + std::to_string(d) + ".bin", r, 3);
+        }
+    }
     FILE* st = fopen((dir + "/status.txt").c_str(), "w");
     fprintf(st, "%d\n%s\n", step_rc, iblb_last_error(ctx));
     fclose(st);

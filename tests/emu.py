@@ -33,7 +33,8 @@ def run_cases(jobs):
 
 def run_case(params_list, nodes_list=None, tris_list=None, steps=(1,), storage=0,
              graph_steps=None, shape=None, f0dev=None, forces=None, timing=False,
-             inactive=(), rest=None, timeout=600, direct_chunks=False, masks=False):
+             inactive=(), rest=None, timeout=600, direct_chunks=False, masks=False,
+             contact=None):
     import build as emu_build
     from paper_2503_20605_amd._lib import iblb_diag
     with _build_lock:
@@ -61,6 +62,8 @@ def run_case(params_list, nodes_list=None, tris_list=None, steps=(1,), storage=0
             cfg.append("rest " + ",".join(str(v) for v in rest))
         if masks:
             cfg.append("mask 1")
+        if contact is not None:
+            cfg.append(f"contact {contact[0]!r},{contact[1]!r}")
         for k in range(n):
             lam = float(getattr(params_list[k], "lam", 1.0))
             if lam != 1.0:
@@ -111,6 +114,8 @@ def run_case(params_list, nodes_list=None, tris_list=None, steps=(1,), storage=0
                     fn = os.path.join(d, f"{tag}_{k}.bin")
                     if os.path.exists(fn):
                         o[tag] = np.fromfile(fn, dtype=np.uint8).reshape(sh)
+            if contact is not None and nodes_list[k] is not None:
+                o["contact"] = np.fromfile(os.path.join(d, f"contact_{k}.bin"), dtype=np.float64)
             if nodes_list[k] is not None:
                 N = np.asarray(nodes_list[k]).shape[0]
                 o["q"] = ld("q", np.float64, (dim, N)).T.copy()

@@ -183,6 +183,25 @@ def test_too_many_crossings_on_a_row_is_reported():
     assert g["status"] == -5 and "crossings" in g["message"]
 
 
+def test_contact_radius_protocols():
+    """Both protocols on the device's final positions against the oracle's
+    formulas on the same positions (2D, and the coarse 3D cap)."""
+    p = wl.Params(dim=2, nx=80, ny=40, tau=0.8, sigma=0.006, theta_eq_deg=50.0, xi=2.0)
+    q = wl.cap_polygon(12.0, 90.0, 2.0, 80, 40.0)
+    zc = o.h_star(p.xi)
+    g = run_case([p], [q], steps=(3,), contact=(zc, 0.05 * 12.0))[0]
+    ri, rii, n = g["contact"]
+    assert n == 2
+    assert abs(ri - o.contact_radius_2d(g["q"], zc)) < 1e-12 * ri
+    assert abs(rii - o.contact_radius_flat_2d(g["q"], 0.05 * 12.0)) < 1e-12 * rii
+    p3, V, T = _tiny3d_case()
+    g3 = run_case([p3], [V], [T], steps=(2,), contact=(2.7, 0.02 * 5.0))[0]
+    ri, rii, n = g3["contact"]
+    assert n > 10
+    assert abs(ri - o.contact_radius_3d(g3["q"], T, 2.7)) < 1e-12 * ri
+    assert abs(rii - o.contact_radius_flat_3d(g3["q"], T, 0.02 * 5.0)) < 1e-12 * rii
+
+
 def test_two_viscosities_3d(background):
     p, V, T = _visc3d_case()
     g = background["visc3d"].result()[0]
