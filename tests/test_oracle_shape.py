@@ -1,0 +1,74 @@
+"""Pins of the oracle's equilibrium-shape solver (App. B, eqs. YL, bc,
+volconstr; App. C): the curvature operator on shapes with known curvature,
+the solution's constraints, grid convergence, and the measured angle that
+App. C prints for theta_eq = pi/4, xi/R0 = 0.1."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import shape as sh
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_curvature_of_spheres():
+    u = np.linspace(-1.0, 1.0, 401)
+    du = u[1] - u[0]
+    # unit sphere about the origin: div n = 2
+    g = np.ones_like(u)
+    gd, gdd = sh.derivatives(g, du)
+    assert np.allclose(sh.curvature(u, g, gd, gdd), 2.0, atol=1e-14)
+    # eq. gcap: a sphere of radius c shifted along the axis has k = 2 / c
+    for th, c in [(math.radians(50), 1.3), (math.radians(120), 0.8)]:
+        a = math.cos(th / 2) ** 2
+        g = c * (-a * u + np.sqrt(1.0 - a * a * (1.0 - u * u)))
+        gd, gdd = sh.derivatives(g, du)
+        k = sh.curvature(u, g, gd, gdd)
+        assert np.max(np.abs(k - 2.0 / c)) < 2e-3 * (2.0 / c)
+
+
+def _pi_over_4(N=801):
+    s = sh.solve(math.pi / 2, 0.1, N=N)
+    th = math.pi / 2
+    while th > math.pi / 4 + 1e-12:
+        th = max(math.pi / 4, th - math.pi / 16)
+        s = sh.solve(th, 0.1, N=N, guess=s)
+    return s
+
+
+def test_measured_angle_printed_in_app_c():
+    gold = json.load(open(os.path.join(HERE, "golden", "app_c_measured_angle.json")))
+    case = [c for c in gold["cases"] if c["xi_over_R0"] == 0.1][0]
+    s = _pi_over_4()
+    got = sh.angle_from_half_height(s["ell"]) / math.pi
+    # two printed digits
+    assert abs(got - case["measured_over_pi"]) < 0.005, got
+
+
+@pytest.mark.parametrize("theta", [math.pi / 2, 3 * math.pi / 4])
+def test_solution_constraints_and_grid_convergence(theta):
+    a = sh.solve(theta, 0.1, N=401)
+    b = sh.solve(theta, 0.1, N=801)
+    for s in (a, b):
+        g, u = s["g"], s["u"]
+        assert abs(g[0] - g[-1]) < 1e-10                       # eq. bc
+        du = u[1] - u[0]
+        assert abs(du * (np.sum(g ** 3) - 0.5 * (g[0] ** 3 + g[-1] ** 3)) - 2.0) < 1e-10
+        assert abs(s["delta"] - 0.1) < 0.01                    # delta close to eps
+    ta = sh.angle_from_half_height(a["ell"])
+    tb = sh.angle_from_half_height(b["ell"])
+    assert abs(ta - tb) < 2e-3
+    # agreement with the imposed angle is better for obtuse angles (App. C)
+    assert abs(tb - theta) < 0.1 * theta
+
+
+def test_without_the_wall_term_the_drop_is_a_sphere():
+    u = np.linspace(-1.0, 1.0, 201)
+    x0 = np.concatenate([1.0 + 0.05 * np.cos(3 * np.arccos(u)), [0.1, 1.9]])
+    from oracle.shape import residual
+    r = residual(np.concatenate([np.ones_like(u), [0.1, 2.0]]), u, math.pi / 3, 0.1, wall=False)
+    assert np.max(np.abs(r[:-1])) < 1e-14 and abs(r[-1]) < 1e-12
+    assert np.max(np.abs(residual(x0, u, math.pi / 3, 0.1, wall=False))) > 1e-3
