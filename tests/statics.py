@@ -1,0 +1,57 @@
+"""Shape comparison of a simulated equilibrium droplet with the App. B
+solution (eq. L2-error_equilibrium).  Test infrastructure shared by the GPU
+statics test."""
+import math
+
+import numpy as np
+
+from oracle import shape as sh
+
+
+def volume_centroid(q, tris):
+    """Volume and centroid of the closed mesh (tetrahedra on the origin)."""
+    a, b, c = q[tris[:, 0]], q[tris[:, 1]], q[tris[:, 2]]
+    v = np.einsum("ij,ij->i", a, np.cross(b, c)) / 6.0
+    cen = ((a + b + c) / 4.0 * v[:, None]).sum(axis=0) / v.sum()
+    return float(v.sum()), cen
+
+
+def radial_profile(q, centre, nbins):
+    """Mean distance of the nodes from centre per bin of polar angle (from
+    +z) over [0, pi]."""
+    d = q - centre[None, :]
+    G = np.linalg.norm(d, axis=1)
+    phi = np.arccos(np.clip(d[:, 2] / G, -1.0, 1.0))
+    k = np.minimum((phi / math.pi * nbins).astype(int), nbins - 1)
+    s = np.bincount(k, weights=G, minlength=nbins)
+    n = np.bincount(k, minlength=nbins)
+    return s / np.maximum(n, 1), n
+
+
+def theory(theta, eps):
+    """App. B solution, reached by continuation in the angle from pi/2 for
+    acute angles."""
+    if theta >= math.pi / 2:
+        return sh.solve(theta, eps)
+    s = sh.solve(math.pi / 2, eps)
+    th = math.pi / 2
+    while th > theta + 1e-12:
+        th = max(theta, th - math.pi / 16)
+        s = sh.solve(th, eps, guess=s)
+    return s
+
+
+def l2_error(q, tris, theta, xi, nbins=90):
+    """eq. L2-error_equilibrium: G_sim from the nodes about the droplet's
+    centroid, G_theo about the centroid of the App. B solution of the same
+    volume (R0 from the simulated volume), over phi in [0, pi]."""
+    V, cen = volume_centroid(q, tris)
+    R0 = (3.0 * V / (4.0 * math.pi)) ** (1.0 / 3.0)
+    s = theory(theta, xi / R0)
+    Gs, n = radial_profile(q, cen, nbins)
+    phis = (np.arange(nbins) + 0.5) * math.pi / nbins
+    Gt = R0 * sh.radial_profile_about(s["u"], s["g"], sh.centroid_height(s["u"], s["g"]), phis)
+    sel = n > 0
+    err = math.sqrt(np.sum((Gs[sel] - Gt[sel]) ** 2) / np.sum(Gt[sel] ** 2))
+    return dict(E_L2=err, R0=R0, theta_bar_theory=sh.angle_from_half_height(s["ell"]),
+                ell_theory=s["ell"] * R0, bins_filled=int(sel.sum()))

@@ -287,6 +287,21 @@ def droplet_3d_spreading(lam: float = 10.0, theta_eq_deg: float = 60.0) -> Workl
     return Workload(f"d3q19_240x240x130_R60_lam{lam:g}", p, V, tris=T)
 
 
+def droplet_3d_statics(theta_eq_deg: float, xi_over_R0: float = 0.1, nu: int = 45) -> Workload:
+    """Set-up of the paper's equilibrium runs (Sec. Statics): an 80x80x60
+    D3Q19 box (periodic x and y, walls at z = 0 and 60), a sphere of radius
+    R0 = 20 from a frequency-nu icosphere (nu = 45: 40500 triangles, the
+    paper's N_t = 40 000) with its lowest point at h = 1.5 xi, xi = xi_over_R0
+    R0, viscosity ratio 1; tau = 1 and sigma = 0.01 (the paper does not list
+    them)."""
+    R0 = 20.0
+    p = Params(dim=3, nx=80, ny=80, nz=60, bc=(BC_PERIODIC, BC_PERIODIC, BC_WALL),
+               tau=1.0, sigma=0.01, theta_eq_deg=theta_eq_deg, xi=xi_over_R0 * R0)
+    V, T = sphere_mesh(R0, nu, (40.0, 40.0, R0 + 1.5 * p.xi))
+    return Workload(f"d3q19_80x80x60_R20_theta{theta_eq_deg:g}_xi{xi_over_R0:g}", p, V, tris=T,
+                    meta={"R0": R0})
+
+
 # ----------------------------------------------------------------------------
 # Raw arrays for unit and parity tests
 # ----------------------------------------------------------------------------
