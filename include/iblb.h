@@ -219,7 +219,9 @@ int iblb_run_to_rest(iblb_ctx *ctx, double tol, int check_every, int hold, long 
 int iblb_set_lb_variant(iblb_ctx *ctx, int variant, int *variant_out);
 
 /* Time every lattice-kernel variant over `steps` real time steps each (the
- * steps advance the simulation) and keep the fastest.  With cache_path
+ * steps advance the simulation) and keep the fastest (the lowest-numbered
+ * variant within 2% of the fastest, so that near-ties resolve the same way
+ * from run to run).  With cache_path
  * non-NULL the winner is looked up in / appended to that text file, keyed
  * by device, lattice, storage and size bucket; a cache hit runs no step.
  * chosen (may be NULL) receives the variant; ms (may be NULL, 12 entries)

@@ -1546,7 +1546,7 @@ int iblb_autotune(iblb_ctx* c, int steps, const char* cache_path, int* chosen, d
     }
     const bool was_timing = c->timing;
     c->timing = true;
-    int best = c->variant;
+    double ms[kVariants];
     double best_ms = 1e300;
     for (int v = 0; v < kVariants; ++v) {
         int rc = iblb_set_lb_variant(c, v, nullptr);
@@ -1555,13 +1555,15 @@ int iblb_autotune(iblb_ctx* c, int steps, const char* cache_path, int* chosen, d
             c->timing = was_timing;
             return rc;
         }
+        ms[v] = c->t_lb;
         if (ms_out) ms_out[v] = c->t_lb;
-        if (c->t_lb < best_ms) {
-            best_ms = c->t_lb;
-            best = v;
-        }
+        best_ms = std::min(best_ms, ms[v]);
     }
     c->timing = was_timing;
+    // the lowest-numbered variant within 2% of the fastest: near-ties (run
+    // to run noise) then resolve the same way every time
+    int best = 0;
+    while (ms[best] > 1.02 * best_ms) ++best;
     int rc = iblb_set_lb_variant(c, best, chosen);
     if (rc) return rc;
     if (cache_path) {
