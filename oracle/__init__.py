@@ -60,8 +60,10 @@ def _load():
     lib.orc_inside.argtypes = [c_int, c_int, c_int, c_int, I, c_int, D, c_int, I, D, I]
     lib.orc_inside_cells.argtypes = [c_int, c_int, c_int, c_int, I, c_int, D, c_int, I, D,
                                      ctypes.c_long, ctypes.POINTER(ctypes.c_long), I]
+    lib.orc_forces_3d_elastic.argtypes = [c_int, D, D, c_int, I, c_double, c_double, c_double,
+                                          c_double, c_int, c_int, c_int, D, D]
     lib.orc_run.argtypes = [c_int, c_int, c_int, c_int, I, c_double, c_double, D,
-                            c_double, c_double, c_double, c_int, c_int, c_int,
+                            c_double, c_double, D, c_double, c_double, c_int, c_int, c_int,
                             c_int, D, c_int, I, c_int,
                             D, D, D, D, D, D, D, D]
     lib.orc_run.restype = c_int
@@ -200,15 +202,23 @@ def forces_2d(q, sigma, A, xi, n=6, m=3, wetting=True):
     return phi.T.copy(), nrm.T.copy()
 
 
-def forces_3d(q, tris, sigma, A, xi, n=6, m=3, wetting=True):
-    """Nodal forces of a closed triangle mesh.  Returns (phi (N,3), normals (N,3))."""
+def forces_3d(q, tris, sigma, A, xi, n=6, m=3, wetting=True, mu_s=0.0, qref=None):
+    """Nodal forces of a closed triangle mesh.  With mu_s != 0 the interface
+    is elastic, its shear part measured from the reference positions qref
+    (N, 3).  Returns (phi (N,3), normals (N,3))."""
     qa = np.ascontiguousarray(np.asarray(q, dtype=np.float64).T)
     T = np.ascontiguousarray(tris, dtype=np.int32)
     N = qa.shape[1]
     phi = np.zeros_like(qa)
     nrm = np.zeros_like(qa)
-    _load().orc_forces_3d(N, _d(qa), T.shape[0], _i(T), float(sigma), float(A), float(xi),
-                          n, m, int(wetting), _d(phi), _d(nrm))
+    if mu_s == 0.0:
+        _load().orc_forces_3d(N, _d(qa), T.shape[0], _i(T), float(sigma), float(A), float(xi),
+                              n, m, int(wetting), _d(phi), _d(nrm))
+    else:
+        ra = np.ascontiguousarray(np.asarray(qref, dtype=np.float64).T)
+        _load().orc_forces_3d_elastic(N, _d(qa), _d(ra), T.shape[0], _i(T), float(sigma),
+                                      float(mu_s), float(A), float(xi), n, m, int(wetting),
+                                      _d(phi), _d(nrm))
     return phi.T.copy(), nrm.T.copy()
 
 
@@ -278,7 +288,8 @@ def run(params, q0, nsteps, tris=None, f0=None, F_fixed=None):
     `params` is any object with attributes dim, nx, ny, nz, bc, tau, sigma,
     theta_eq_deg, xi, n_exp, m_exp, wetting, and optionally lam (viscosity
     ratio, default 1; the classification window is centred on the mean of
-    q0).  Returns a dict with the final f, q, and the last step's rho, U, F,
+    q0) and shear (surface shear modulus of an elastic interface, 3D,
+    default 0; the reference mesh is q0).  Returns a dict with the final f, q, and the last step's rho, U, F,
     phi, qdot, dropped, status."""
     p = params
     lib = _load()
@@ -303,8 +314,10 @@ def run(params, q0, nsteps, tris=None, f0=None, F_fixed=None):
     lam = float(getattr(p, "lam", 1.0))
     tau_in = tau_inside(float(p.tau), lam) if lam != 1.0 else float(p.tau)
     ref = reference_point(q0) if N > 0 else np.zeros(3)
+    mu_s = float(getattr(p, "shear", 0.0))
+    qref = q.copy() if N > 0 else np.zeros((dim, 1))
     status = lib.orc_run(dim, p.nx, p.ny, nz, _i(_bc(p.bc)), float(p.tau), tau_in, _d(ref),
-                         float(p.sigma), math.radians(p.theta_eq_deg), float(p.xi),
+                         float(p.sigma), mu_s, _d(qref), math.radians(p.theta_eq_deg), float(p.xi),
                          int(p.n_exp), int(p.m_exp), int(bool(p.wetting)),
                          N, _d(qa), T.shape[0], _i(T), int(nsteps),
                          _d(f), _d(rho), _d(U), _d(F), _d(Ff), _d(phi), _d(qdot), _d(dropped))

@@ -26,6 +26,12 @@
  *                           -(chi_j/3) Pi n_j; strength A from eq. (A_choice)
  *   boundaries              periodic sides, bounce-back walls (Sec. "Numerical
  *                           results", set-up paragraph)
+ *   elastic interface       w(a, b) = sigma e^a + mu_s (b + 1 - e^a) with the
+ *                           strain invariants a, b of eq. strain_inv measured
+ *                           from a stress-free reference mesh (a different
+ *                           strain energy in eq. force_bb, as the outlook
+ *                           proposes); mu_s = 0 is the droplet of eq.
+ *                           energy_drop
  *   two viscosities         tau = tau_in at cells enclosed by the interface,
  *                           tau_out elsewhere, reclassified every step (Sec.
  *                           IB-LB, last paragraph; eq. def_lambda)
@@ -372,6 +378,9 @@ void orc_forces_2d(int N, const double *q, double sigma, double A, double xi,
     }
 }
 
+static double norm3(const double *a) { return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
 static void cross3(const double *a, const double *b, double *c)
 {
     c[0] = a[1] * b[2] - a[2] * b[1];
@@ -437,6 +446,94 @@ void orc_forces_3d(int N, const double *q, int T, const int *tri, double sigma,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Elastic interface: shear part of the strain energy                        */
+/* ------------------------------------------------------------------------ */
+/* On a linear triangle the map from the reference triangle (vertices Q_k)  */
+/* to the current one (q_k) has a constant in-plane deformation gradient.   */
+/* With the reference edges written in an orthonormal frame of their own    */
+/* plane, E0 = [Q1 - Q0, Q2 - Q0] (2 x 2), and the current edges            */
+/* E = [q1 - q0, q2 - q0] (3 x 2), the gradient is F = E E0^-1 (3 x 2).     */
+/* G = F^T F has the nonzero eigenvalues of D D^T, so the invariants of eq.  */
+/* strain_inv are a = (1/2) log det G and b = (1/2) tr G - 1.  For           */
+/*   w_s(a, b) = mu_s (b + 1 - e^a) = mu_s (l1 - l2)^2 / 2                   */
+/* (l1, l2 the principal stretches) the triangle's energy is A0 w_s, A0 the  */
+/* reference area, and with d(a)/dF = F G^-1, d(b)/dF = F:                   */
+/*   dW/dF = A0 mu_s (F - e^a F G^-1),  dW/dE = dW/dF E0^-T,                 */
+/* whose columns are dW/dq1 and dW/dq2; dW/dq0 = -(dW/dq1 + dW/dq2).         */
+/* The force is phi = -dW/dq.  Added to phi (q, qref: [3][N]; tri [T][3]).  */
+static void add_shear_forces(int N, const double *q, const double *qref, int T, const int *tri,
+                             double mu_s, double *phi)
+{
+    for (int t = 0; t < T; ++t) {
+        int v[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
+        double R[3][3], P[3][3];
+        for (int s = 0; s < 3; ++s)
+            for (int k = 0; k < 3; ++k) {
+                R[s][k] = qref[(long)k * N + v[s]];
+                P[s][k] = q[(long)k * N + v[s]];
+            }
+        double r1[3], r2[3], e1[3], e2[3];
+        for (int k = 0; k < 3; ++k) {
+            r1[k] = R[1][k] - R[0][k];
+            r2[k] = R[2][k] - R[0][k];
+            e1[k] = P[1][k] - P[0][k];
+            e2[k] = P[2][k] - P[0][k];
+        }
+        /* reference frame: t1 along r1, t2 in the plane, orthogonal to t1 */
+        double l1 = sqrt(dot3(r1, r1)), nr[3], t1[3], t2[3];
+        for (int k = 0; k < 3; ++k) t1[k] = r1[k] / l1;
+        cross3(r1, r2, nr);
+        double A0 = 0.5 * sqrt(dot3(nr, nr));
+        cross3(nr, t1, t2);
+        double ln = sqrt(dot3(t2, t2));
+        for (int k = 0; k < 3; ++k) t2[k] /= ln;
+        /* E0 = [[r1.t1, r2.t1], [r1.t2, r2.t2]] and its inverse */
+        double E0[2][2] = {{dot3(r1, t1), dot3(r2, t1)}, {dot3(r1, t2), dot3(r2, t2)}};
+        double det0 = E0[0][0] * E0[1][1] - E0[0][1] * E0[1][0];
+        double Ei[2][2] = {{E0[1][1] / det0, -E0[0][1] / det0}, {-E0[1][0] / det0, E0[0][0] / det0}};
+        /* F = E Ei (3 x 2) */
+        double F[3][2];
+        for (int k = 0; k < 3; ++k)
+            for (int c = 0; c < 2; ++c) F[k][c] = e1[k] * Ei[0][c] + e2[k] * Ei[1][c];
+        /* G = F^T F */
+        double G[2][2];
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) {
+                G[r][c] = 0.0;
+                for (int k = 0; k < 3; ++k) G[r][c] += F[k][r] * F[k][c];
+            }
+        double detG = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+        double ea = sqrt(detG); /* e^a */
+        double Gi[2][2] = {{G[1][1] / detG, -G[0][1] / detG}, {-G[1][0] / detG, G[0][0] / detG}};
+        /* dW/dF = A0 mu_s (F - e^a F G^-1) */
+        double dF[3][2];
+        for (int k = 0; k < 3; ++k)
+            for (int c = 0; c < 2; ++c) {
+                double fg = F[k][0] * Gi[0][c] + F[k][1] * Gi[1][c];
+                dF[k][c] = A0 * mu_s * (F[k][c] - ea * fg);
+            }
+        /* dW/dE = dW/dF Ei^T: columns for q1 and q2 */
+        for (int k = 0; k < 3; ++k) {
+            double g1 = dF[k][0] * Ei[0][0] + dF[k][1] * Ei[0][1];
+            double g2 = dF[k][0] * Ei[1][0] + dF[k][1] * Ei[1][1];
+            phi[(long)k * N + v[1]] -= g1;
+            phi[(long)k * N + v[2]] -= g2;
+            phi[(long)k * N + v[0]] += g1 + g2;
+        }
+    }
+}
+
+/* Forces of eq. force_split with the elastic interface: orc_forces_3d plus
+ * the shear part measured from the reference positions qref ([3][N]). */
+void orc_forces_3d_elastic(int N, const double *q, const double *qref, int T, const int *tri,
+                           double sigma, double mu_s, double A, double xi, int n, int m,
+                           int wetting, double *phi, double *normal_out)
+{
+    orc_forces_3d(N, q, T, tri, sigma, A, xi, n, m, wetting, phi, normal_out);
+    if (mu_s != 0.0) add_shear_forces(N, q, qref, T, tri, mu_s, phi);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Cells enclosed by the interface (Sec. IB-LB, last paragraph)              */
 /* ------------------------------------------------------------------------ */
 /* The paper finds the cells inside the closed interface by ray tracing.     */
@@ -472,8 +569,6 @@ static double winding_2d(int N, const double *q, const double *p)
     return w / (2.0 * PI);
 }
 
-static double norm3(const double *a) { return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
-static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
 static double winding_3d(int N, const double *q, int T, const int *tri, const double *p)
 {
@@ -536,6 +631,8 @@ void orc_inside_cells(int dim, int nx, int ny, int nz, const int *bc, int N, con
 /* Run nsteps of the coupled method.  Order inside a step: nodal forces at
  * q(t) -> spread to F(t) -> LB step with F(t) (in the Guo source and the
  * half-force velocity alike) -> interpolate U(t) at q(t) -> q(t+1).
+ * mu_s != 0 (3D) adds the shear part of the elastic interface measured from
+ * the reference positions qref ([3][N]).
  * With tau_in != tau the cells enclosed by the interface at q(t) relax with
  * tau_in in the LB step of step t and the others with tau (classification
  * window centred on ref[3]; see orc_inside).
@@ -547,8 +644,8 @@ void orc_inside_cells(int dim, int nx, int ny, int nz, const int *bc, int N, con
  * N = 0 runs the fluid alone with the prescribed force field F_fixed
  * (may be NULL).  Returns 0, or -4 if a node reached h <= 0 (wetting on). */
 int orc_run(int dim, int nx, int ny, int nz, const int *bc, double tau, double tau_in,
-            const double *ref, double sigma, double theta, double xi, int n_exp, int m_exp,
-            int wetting,
+            const double *ref, double sigma, double mu_s, const double *qref, double theta,
+            double xi, int n_exp, int m_exp, int wetting,
             int N, double *q, int T, const int *tri, int nsteps,
             double *f, double *rho, double *U, double *F, const double *F_fixed,
             double *phi, double *qdot, double *dropped)
@@ -570,7 +667,8 @@ int orc_run(int dim, int nx, int ny, int nz, const int *bc, double tau, double t
             if (dim == 2)
                 orc_forces_2d(N, q, sigma, A, xi, n_exp, m_exp, wetting, phi, NULL);
             else
-                orc_forces_3d(N, q, T, tri, sigma, A, xi, n_exp, m_exp, wetting, phi, NULL);
+                orc_forces_3d_elastic(N, q, qref, T, tri, sigma, mu_s, A, xi, n_exp, m_exp,
+                                      wetting, phi, NULL);
             orc_spread(dim, nx, ny, nz, bc, N, q, phi, F, dropped);
             if (two_tau) {
                 orc_inside(dim, nx, ny, nz, bc, N, q, T, tri, ref, inside);

@@ -49,6 +49,9 @@ class Params:
     # viscosity ratio mu_in / mu_out of the fluid inside the interface to the
     # fluid outside (tau is the outside relaxation time); 1: one fluid
     lam: float = 1.0
+    # surface shear modulus of an elastic interface (3D; the stress-free
+    # reference is the mesh as first set); 0: a liquid droplet
+    shear: float = 0.0
 
     def to_dict(self):
         return asdict(self)
