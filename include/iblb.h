@@ -254,6 +254,18 @@ int iblb_set_active(iblb_ctx *ctx, int droplet, int active);
  * IBLB_ELIMIT.  Synchronises the stream. */
 int iblb_set_viscosity_ratio(iblb_ctx *ctx, int droplet, double lambda);
 
+/* Elastic interface for droplet d (3D): the strain energy of eq. force_bb
+ * becomes w(a, b) = sigma e^a + mu_s (b + 1 - e^a), with a, b the strain
+ * invariants of eq. strain_inv measured from the node positions at the time
+ * of this call (the stress-free reference mesh), instead of eq.
+ * energy_drop; mu_s (>= 0) is the surface shear modulus: the added energy
+ * is mu_s A0 (l1 - l2)^2 / 2 per triangle, l1, l2 its principal stretches
+ * and A0 its reference area (Sec. "Modelling surface tension forces"; the
+ * change of strain energy the paper's conclusions propose for elastic
+ * wetting).  mu_s = 0 restores the liquid droplet.  EINVAL in 2D, without
+ * an interface, or for a negative or non-finite mu_s.  Synchronises. */
+int iblb_set_membrane_shear(iblb_ctx *ctx, int droplet, double mu_s);
+
 /* Inside/outside classification of droplet d's cells at its current node
  * positions (the rule of iblb_set_viscosity_ratio, for any lambda):
  * d_mask (device, uint8, ncell = nx*ny*nz, [z][y][x]) receives 1 for cells

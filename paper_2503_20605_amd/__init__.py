@@ -231,6 +231,11 @@ class Solver:
         self._chk(self.lib.iblb_inside_mask(self.ctx, d, ctypes.c_void_p(m.data_ptr())))
         return m
 
+    def set_membrane_shear(self, d, mu_s):
+        """Elastic interface of droplet d with surface shear modulus mu_s,
+        stress-free at its current node positions (3D; 0: liquid)."""
+        self._chk(self.lib.iblb_set_membrane_shear(self.ctx, d, float(mu_s)))
+
     def contact_radius(self, d, z_cut, flat_tol):
         """(protocol (i) radius at z_cut, protocol (ii) radius with flatness
         tolerance flat_tol, number of protocol (i) crossings) of droplet d."""

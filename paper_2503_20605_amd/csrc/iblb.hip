@@ -45,7 +45,7 @@ struct Layout {
     // byte offsets into the workspace
     size_t drops, tiles_lb, tiles_all, f0, f1, F, U, Fout, rho, flags, pos0, pos1, phi, qdot, dropped,
         node_drop, tri, inc, inc_beg, inc_end, perm, chunks, status, partials, diag, stamps, stamps_out,
-        xcnt0, xcnt1, xpos0, xpos1, total;
+        xcnt0, xcnt1, xpos0, xpos1, tref, total;
     int nchunks;           // capacity of the 3D spreading chunk table
     long long cells;       // sum of cells
     long long flag_bytes;  // sum of band flags
@@ -196,6 +196,7 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.node_drop = take(sizeof(int) * N);
     L.tri = take(sizeof(int) * 3 * T);
     L.inc = take(sizeof(int) * 3 * T);
+    L.tref = take(sizeof(double) * 5 * T);  // reference triangles of elastic interfaces
     L.inc_beg = take(sizeof(int) * N);
     L.inc_end = take(sizeof(int) * N);
     L.perm = take(sizeof(int) * N);
@@ -286,6 +287,7 @@ NodeArrays node_arrays(const iblb_ctx* c, int p) {
     A.inc_beg = c->at<int>(c->L.inc_beg);
     A.inc_end = c->at<int>(c->L.inc_end);
     A.perm = c->at<int>(c->L.perm);
+    A.tref = c->at<double>(c->L.tref);
     A.stride = std::max(c->L.ntot, 1);
     A.tstride = std::max(c->L.ttot, 1);
     A.ntot = c->L.ntot;
@@ -1397,6 +1399,22 @@ int iblb_set_viscosity_ratio(iblb_ctx* c, int d, double lambda) {
         c->any_visc = any;
         drop_graphs(c);  // whether the crossing launches run is baked into them
     }
+    return upload_drops(c);
+}
+
+int iblb_set_membrane_shear(iblb_ctx* c, int d, double mu_s) {
+    if (!check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
+    if (c->dim != 3) return fail(c, IBLB_EINVAL, "an elastic interface needs a 3D triangle mesh");
+    if (!(mu_s >= 0.0) || !std::isfinite(mu_s))
+        return fail(c, IBLB_EINVAL, "shear modulus must be finite and >= 0");
+    if (c->n_nodes[d] == 0 || !c->iface_set[d]) return fail(c, IBLB_EINVAL, "droplet has no interface");
+    DropDev& D = c->drops[d];
+    if (mu_s != 0.0) {
+        hipLaunchKernelGGL(k_tri_ref, dim3(ceil_div(D.n_tris, kBlock)), dim3(kBlock), 0, c->stream,
+                           c->at<DropDev>(c->L.drops), d, node_arrays(c, c->cur), c->at<double>(c->L.tref));
+        HIPCHK(c, hipGetLastError());
+    }
+    D.shear = mu_s;
     return upload_drops(c);
 }
 

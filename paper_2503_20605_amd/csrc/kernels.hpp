@@ -61,6 +61,7 @@ struct DropDev {
     float omega_in, guo_in;
     double win[3];        // classification window [win, win + n) of each axis
     double img_base, img_r;  // x image of cell centre c: c + img_base (+ nx if c < img_r)
+    double shear;         // surface shear modulus of an elastic interface (0: liquid)
 };
 
 struct DiagDev {
@@ -362,6 +363,7 @@ struct NodeArrays {
     const int* inc_beg;
     const int* inc_end;
     const int* perm;     // node ids in spatial (Morton) order, per droplet
+    const double* tref;  // [5][tstride] reference triangles of elastic interfaces
     int stride, tstride, ntot;
 };
 
@@ -415,6 +417,42 @@ __device__ __forceinline__ void node_geom_2d(const DropDev& D, const NodeArrays&
     geom_2d(D.sigma, qm, q, qp, fs, n, chi);
 }
 
+// Elastic interface: the shear part w_s = mu_s (b + 1 - e^a) of the strain
+// energy, with the invariants a = (1/2) log det G, b = (1/2) tr G - 1 of
+// eq. strain_inv (G = F^T F shares the nonzero eigenvalues of D D^T).  The
+// in-plane deformation gradient of triangle t is F = [e1 e2] Ei, Ei the
+// inverse of its reference edges in a frame of the reference plane (stored
+// with the reference area A0 by k_tri_ref).  With d(a)/dF = F G^-1 and
+// d(b)/dF = F the energy gradient is dW/dF = A0 mu_s (F - e^a F G^-1);
+// dW/dF Ei^T holds dW/dq1 and dW/dq2 in its columns and
+// dW/dq0 = -(dW/dq1 + dW/dq2).  Adds -dW/dq of the triangle's slot s to fs.
+__device__ __forceinline__ void shear_force(double mu, const NodeArrays& A, int t, int s,
+                                            const double e1[3], const double e2[3], double fs[3]) {
+    const int ts = A.tstride;
+    const double Ei[2][2] = {{A.tref[t], A.tref[ts + t]}, {A.tref[2 * ts + t], A.tref[3 * ts + t]}};
+    const double A0 = A.tref[4 * ts + t];
+    double F[3][2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        F[k][0] = e1[k] * Ei[0][0] + e2[k] * Ei[1][0];
+        F[k][1] = e1[k] * Ei[0][1] + e2[k] * Ei[1][1];
+    }
+    const double g00 = F[0][0] * F[0][0] + F[1][0] * F[1][0] + F[2][0] * F[2][0];
+    const double g01 = F[0][0] * F[0][1] + F[1][0] * F[1][1] + F[2][0] * F[2][1];
+    const double g11 = F[0][1] * F[0][1] + F[1][1] * F[1][1] + F[2][1] * F[2][1];
+    const double det = g00 * g11 - g01 * g01;
+    const double ea = sqrt(det);
+    const double i00 = g11 / det, i01 = -g01 / det, i11 = g00 / det;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double d0 = A0 * mu * (F[k][0] - ea * (F[k][0] * i00 + F[k][1] * i01));
+        const double d1 = A0 * mu * (F[k][1] - ea * (F[k][0] * i01 + F[k][1] * i11));
+        const double g1 = d0 * Ei[0][0] + d1 * Ei[0][1];
+        const double g2 = d0 * Ei[1][0] + d1 * Ei[1][1];
+        fs[k] += s == 0 ? g1 + g2 : (s == 1 ? -g1 : -g2);
+    }
+}
+
 // Geometry of vertex j of a closed 3D triangle mesh (CCW seen from
 // outside): surface-tension force -sigma d(area)/dq_j summed over the
 // incident triangles, vertex normal (mean of the incident unit normals),
@@ -459,6 +497,7 @@ __device__ __forceinline__ void node_geom_3d(const DropDev& D, const NodeArrays&
         ns[1] += nt[1];
         ns[2] += nt[2];
         chi += 0.5 * len;
+        if (D.shear != 0.0) shear_force(D.shear, A, t, s, e1, e2, fs);
     }
     const double nn = sqrt(ns[0] * ns[0] + ns[1] * ns[1] + ns[2] * ns[2]);
     n[0] = ns[0] / nn;
@@ -760,6 +799,44 @@ __global__ __launch_bounds__(kBlock) void k_cross3(const DropDev* __restrict__ d
         return;
     }
     cross_tri_3d(D, cnt, xs, P, id, status, d);
+}
+
+// Stress-free reference of droplet d's triangles for the elastic interface
+// (see shear_force), from the positions A.pos, one lane per triangle:
+// frame t1 along the first edge, t2 in the triangle's plane; the inverse of
+// the reference edge matrix and the reference area.
+__global__ __launch_bounds__(kBlock) void k_tri_ref(const DropDev* __restrict__ drops, int d, NodeArrays A,
+                                                    double* __restrict__ tref) {
+    const DropDev& D = drops[d];
+    const int l = blockIdx.x * kBlock + threadIdx.x;
+    if (l >= D.n_tris) return;
+    const int t = D.tri_off + l, ts = A.tstride, st = A.stride;
+    const int v[3] = {A.tri[t], A.tri[ts + t], A.tri[2 * ts + t]};
+    double r1[3], r2[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r1[k] = A.pos[k * st + v[1]] - A.pos[k * st + v[0]];
+        r2[k] = A.pos[k * st + v[2]] - A.pos[k * st + v[0]];
+    }
+    const double l1 = sqrt(r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2]);
+    const double t1[3] = {r1[0] / l1, r1[1] / l1, r1[2] / l1};
+    const double n[3] = {r1[1] * r2[2] - r1[2] * r2[1], r1[2] * r2[0] - r1[0] * r2[2],
+                         r1[0] * r2[1] - r1[1] * r2[0]};
+    double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
+    const double l2 = sqrt(t2[0] * t2[0] + t2[1] * t2[1] + t2[2] * t2[2]);
+    t2[0] /= l2;
+    t2[1] /= l2;
+    t2[2] /= l2;
+    const double a = r1[0] * t1[0] + r1[1] * t1[1] + r1[2] * t1[2];
+    const double b = r2[0] * t1[0] + r2[1] * t1[1] + r2[2] * t1[2];
+    const double c = r1[0] * t2[0] + r1[1] * t2[1] + r1[2] * t2[2];
+    const double e = r2[0] * t2[0] + r2[1] * t2[1] + r2[2] * t2[2];
+    const double det = a * e - b * c;
+    tref[t] = e / det;
+    tref[ts + t] = -b / det;
+    tref[2 * ts + t] = -c / det;
+    tref[3 * ts + t] = a / det;
+    tref[4 * ts + t] = 0.5 * sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
 }
 
 // Inside (1) / outside (0) of every cell of droplet d from the crossing

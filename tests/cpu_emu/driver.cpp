@@ -166,6 +166,13 @@ int main(int argc, char** argv) {
     for (int d = 0; d < n; ++d)
         if (geti("inactive_" + std::to_string(d), 0)) iblb_set_active(ctx, d, 0);
     for (int d = 0; d < n; ++d) {
+        const std::string key = "shear_" + std::to_string(d);
+        if (cfg.count(key) && iblb_set_membrane_shear(ctx, d, atof(cfg[key].c_str()))) {
+            fprintf(stderr, "membrane shear: %s\n", iblb_last_error(ctx));
+            return 16;
+        }
+    }
+    for (int d = 0; d < n; ++d) {
         const std::string key = "lambda_" + std::to_string(d);
         if (cfg.count(key) && iblb_set_viscosity_ratio(ctx, d, atof(cfg[key].c_str()))) {
             fprintf(stderr, "viscosity ratio: %s\n", iblb_last_error(ctx));

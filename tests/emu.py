@@ -68,6 +68,9 @@ def run_case(params_list, nodes_list=None, tris_list=None, steps=(1,), storage=0
             lam = float(getattr(params_list[k], "lam", 1.0))
             if lam != 1.0:
                 cfg.append(f"lambda_{k} {lam!r}")
+            mu_s = float(getattr(params_list[k], "shear", 0.0))
+            if mu_s != 0.0:
+                cfg.append(f"shear_{k} {mu_s!r}")
             q = nodes_list[k]
             if q is not None:
                 q = np.asarray(q, dtype=np.float64)

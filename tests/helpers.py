@@ -21,6 +21,9 @@ def gpu_solver(params_list, nodes_list=None, tris_list=None, storage=0):
         lam = float(getattr(p, "lam", 1.0))
         if lam != 1.0:
             s.set_viscosity_ratio(d, lam)
+        mu_s = float(getattr(p, "shear", 0.0))
+        if mu_s != 0.0:
+            s.set_membrane_shear(d, mu_s)
     return s
 
 

@@ -202,6 +202,25 @@ def test_contact_radius_protocols():
     assert abs(rii - o.contact_radius_flat_3d(g3["q"], T, 0.02 * 5.0)) < 1e-12 * rii
 
 
+def test_elastic_interface_3d():
+    """Coarse cap with an elastic interface (shear modulus 0.02, reference
+    = the initial mesh): 4 steps (graph replays and direct launches) against
+    the oracle."""
+    p = wl.Params(dim=3, nx=20, ny=18, nz=12, bc=(0, 0, 1), tau=0.8, sigma=0.005,
+                  theta_eq_deg=60.0, xi=2.0, shear=0.02)
+    V, T = wl.cap_mesh(5.0, 90.0, 2.0, 3, (10.0, 9.0))
+    g = run_case([p], [V], [T], steps=(1, 3), graph_steps=2)[0]
+    assert g["status"] == 0, g["message"]
+    r = o.run(p, V, 4, tris=T)
+    drho, du, dq = compare_fields(g, r, 3, "emu elastic 3d")
+    assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
+    assert np.max(np.abs(g["phi"] - r["phi"])) <= 1e-6 * np.max(np.abs(r["phi"]))
+    # the shear term matters at this tolerance
+    p0 = wl.Params(**{**p.to_dict(), "shear": 0.0})
+    r0 = o.run(p0, V, 4, tris=T)
+    assert np.max(np.abs(r0["phi"] - r["phi"])) > 1e-3 * np.max(np.abs(r["phi"]))
+
+
 def test_two_viscosities_3d(background):
     p, V, T = _visc3d_case()
     g = background["visc3d"].result()[0]
