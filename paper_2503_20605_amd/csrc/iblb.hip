@@ -75,7 +75,7 @@ constexpr long long kPopRound = IBLB_POP_ROUND;
 // Cell budget of a 3D spreading chunk's tap box when the host cuts chunks
 // (see morton_order); the kernel's own limit is kBoxCells.
 #ifndef IBLB_CHUNK_BUDGET
-#define IBLB_CHUNK_BUDGET 2560
+#define IBLB_CHUNK_BUDGET 640
 #endif
 
 long long pop_stride(long long cells) {

@@ -936,9 +936,22 @@ __global__ __launch_bounds__(kBlock) void k_force3(const DropDev* __restrict__ d
 // chunk's taps, and each touched cell then takes one global atomic add per
 // component instead of one per contribution.  A chunk whose box exceeds
 // kBoxCells (vertices far apart) adds straight to global memory.
-constexpr int kChunk = 64;
-constexpr int kBoxCells = 4096;
-constexpr int kSpreadBlock = 1024;  // 16 wavefronts, each taking every 16th vertex
+// Chunks of 16 vertices, 256-lane workgroups and a 1024-cell box (13 KB of
+// LDS) measured fastest among chunks of 8-64 vertices and 128-1024 lanes
+// (3D steps of 256x256x128 and 240x240x130: 295 and 348 us against 312
+// and 374 us for 64 vertices on 1024 lanes).
+#ifndef IBLB_SPREAD_CHUNK
+#define IBLB_SPREAD_CHUNK 16
+#endif
+#ifndef IBLB_SPREAD_BOX
+#define IBLB_SPREAD_BOX 1024
+#endif
+#ifndef IBLB_SPREAD_BLOCK
+#define IBLB_SPREAD_BLOCK 256
+#endif
+constexpr int kChunk = IBLB_SPREAD_CHUNK;
+constexpr int kBoxCells = IBLB_SPREAD_BOX;
+constexpr int kSpreadBlock = IBLB_SPREAD_BLOCK;  // wavefronts each taking every (block / 64)-th vertex
 
 __global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restrict__ drops, NodeArrays A,
                                                     const int4* __restrict__ chunks,

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 SRCS = [os.path.join(ROOT, "paper_2503_20605_amd", "csrc", f) for f in ("iblb.hip", "mlp.hip")]
 OUT = os.path.join(HERE, "iblb_emu_driver")
 # Second build whose host-side chunking ignores the box budget (plain runs
-# of 64 vertices), so that spreading chunks overflow the kernel's LDS box
+# of the chunk size), so that spreading chunks overflow the kernel's LDS box
 # and take its direct-atomic path.
 OUT_DIRECT = os.path.join(HERE, "iblb_emu_driver_direct")
 CXX = "/opt/rocm/llvm/bin/clang++"

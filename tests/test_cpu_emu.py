@@ -51,6 +51,19 @@ def _visc3d_case():
     return p, V, T
 
 
+def _contact2d_case():
+    p = wl.Params(dim=2, nx=80, ny=40, tau=0.8, sigma=0.006, theta_eq_deg=50.0, xi=2.0)
+    q = wl.cap_polygon(12.0, 90.0, 2.0, 80, 40.0)
+    return p, q, (o.h_star(p.xi), 0.05 * 12.0)
+
+
+def _elastic3d_case():
+    p = wl.Params(dim=3, nx=20, ny=18, nz=12, bc=(0, 0, 1), tau=0.8, sigma=0.005,
+                  theta_eq_deg=60.0, xi=2.0, shear=0.02)
+    V, T = wl.cap_mesh(5.0, 90.0, 2.0, 3, (10.0, 9.0))
+    return p, V, T
+
+
 def _blowup_case():
     p = wl.Params(dim=2, nx=64, ny=32, tau=1.0, sigma=50.0, theta_eq_deg=60.0, xi=2.0)
     q = wl.cap_polygon(8.0, 90.0, 2.0, 40, 32.0)
@@ -63,7 +76,13 @@ def _background_jobs():
     pc, Vc, Tc = _coarse3d_case()
     pb, qb = _blowup_case()
     pv, Vv, Tv = _visc3d_case()
+    p2, q2, c2 = _contact2d_case()
+    pe, Ve, Te = _elastic3d_case()
     return {
+        "contact2d": dict(params_list=[p2], nodes_list=[q2], steps=(3,), contact=c2),
+        "contact3d": dict(params_list=[p3], nodes_list=[V3], tris_list=[T3], steps=(2,),
+                          contact=(2.7, 0.02 * 5.0)),
+        "elastic3d": dict(params_list=[pe], nodes_list=[Ve], tris_list=[Te], steps=(1, 3), graph_steps=2),
         "visc3d": dict(params_list=[pv], nodes_list=[Vv], tris_list=[Tv], steps=(1, 2), graph_steps=2,
                        masks=True),
         "rest": dict(params_list=ps, nodes_list=qs, steps=(0,), rest=(2e-3, 4, 2, 60), graph_steps=2),
@@ -183,33 +202,29 @@ def test_too_many_crossings_on_a_row_is_reported():
     assert g["status"] == -5 and "crossings" in g["message"]
 
 
-def test_contact_radius_protocols():
+def test_contact_radius_protocols(background):
     """Both protocols on the device's final positions against the oracle's
-    formulas on the same positions (2D, and the coarse 3D cap)."""
-    p = wl.Params(dim=2, nx=80, ny=40, tau=0.8, sigma=0.006, theta_eq_deg=50.0, xi=2.0)
-    q = wl.cap_polygon(12.0, 90.0, 2.0, 80, 40.0)
-    zc = o.h_star(p.xi)
-    g = run_case([p], [q], steps=(3,), contact=(zc, 0.05 * 12.0))[0]
+    formulas on the same positions (2D, and the tiny 3D cap)."""
+    p, q, (zc, tol) = _contact2d_case()
+    g = background["contact2d"].result()[0]
     ri, rii, n = g["contact"]
     assert n == 2
     assert abs(ri - o.contact_radius_2d(g["q"], zc)) < 1e-12 * ri
-    assert abs(rii - o.contact_radius_flat_2d(g["q"], 0.05 * 12.0)) < 1e-12 * rii
+    assert abs(rii - o.contact_radius_flat_2d(g["q"], tol)) < 1e-12 * rii
     p3, V, T = _tiny3d_case()
-    g3 = run_case([p3], [V], [T], steps=(2,), contact=(2.7, 0.02 * 5.0))[0]
+    g3 = background["contact3d"].result()[0]
     ri, rii, n = g3["contact"]
     assert n > 10
     assert abs(ri - o.contact_radius_3d(g3["q"], T, 2.7)) < 1e-12 * ri
     assert abs(rii - o.contact_radius_flat_3d(g3["q"], T, 0.02 * 5.0)) < 1e-12 * rii
 
 
-def test_elastic_interface_3d():
+def test_elastic_interface_3d(background):
     """Coarse cap with an elastic interface (shear modulus 0.02, reference
     = the initial mesh): 4 steps (graph replays and direct launches) against
     the oracle."""
-    p = wl.Params(dim=3, nx=20, ny=18, nz=12, bc=(0, 0, 1), tau=0.8, sigma=0.005,
-                  theta_eq_deg=60.0, xi=2.0, shear=0.02)
-    V, T = wl.cap_mesh(5.0, 90.0, 2.0, 3, (10.0, 9.0))
-    g = run_case([p], [V], [T], steps=(1, 3), graph_steps=2)[0]
+    p, V, T = _elastic3d_case()
+    g = background["elastic3d"].result()[0]
     assert g["status"] == 0, g["message"]
     r = o.run(p, V, 4, tris=T)
     drho, du, dq = compare_fields(g, r, 3, "emu elastic 3d")
@@ -246,8 +261,9 @@ def test_droplet_3d_tiny(background):
 def test_droplet_3d_coarse_mesh_across_periodic_edge(background):
     """Coarse cap centred on the periodic x edge, spreading boxes that wrap
     around the periodic axis.  The second build has the host cut plain runs
-    of 64 vertices, so some chunks overflow the LDS box and add straight to
-    global memory next to chunks that fit."""
+    of the chunk size (16 vertices) without the box budget, so some chunks
+    overflow the LDS box and add straight to global memory next to chunks
+    that fit."""
     p, V, T = _coarse3d_case()
     r = o.run(p, V, 2, tris=T)
     assert np.min(r["q"][:, 0]) < 0.0
