@@ -27,11 +27,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-# lattice-kernel variants: block width along x, non-temporal stores,
-# non-temporal loads
-LB_BX = (256, 128, 64) * 4
-LB_NT = (0, 0, 0, 1, 1, 1) * 2
-LB_NTL = (0,) * 6 + (1,) * 6
+# lattice-kernel variants: block width along x (0: flat runs of 256 cells),
+# non-temporal stores, non-temporal loads
+LB_BX = (256, 128, 64) * 4 + (0,) * 4
+LB_NT = (0, 0, 0, 1, 1, 1) * 2 + (0, 1, 0, 1)
+LB_NTL = (0,) * 6 + (1,) * 6 + (0, 0, 1, 1)
 
 
 def lb_kernel_name(dim, storage, variant, vis=0):
@@ -83,7 +83,7 @@ def parse():
     ap.add_argument("--run", type=int, default=1, help="sweep point 0..9 of the 1024x512 set")
     ap.add_argument("--graph-steps", type=int, default=64)
     ap.add_argument("--variant", type=int, default=-1,
-                    help="lattice-kernel variant 0..11; -1 autotunes")
+                    help="lattice-kernel variant 0..15; -1 autotunes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--extra", action="store_true",

@@ -214,6 +214,9 @@ int iblb_run_to_rest(iblb_ctx *ctx, double tol, int check_every, int hold, long 
  *   1: 128x2 cells per block   4: 128x2, non-temporal stores
  *   2:  64x4 cells per block   5:  64x4, non-temporal stores
  *   6-11: as 0-5 with non-temporal population loads
+ *   12-15: 256 consecutive cells per block in storage order (no idle lanes
+ *          when nx is not a multiple of 64): plain, non-temporal stores,
+ *          non-temporal loads, both
  * variant = -1 keeps the current one; *variant_out (may be NULL) receives
  * the variant in use. */
 int iblb_set_lb_variant(iblb_ctx *ctx, int variant, int *variant_out);
@@ -224,7 +227,7 @@ int iblb_set_lb_variant(iblb_ctx *ctx, int variant, int *variant_out);
  * from run to run).  With cache_path
  * non-NULL the winner is looked up in / appended to that text file, keyed
  * by device, lattice, storage and size bucket; a cache hit runs no step.
- * chosen (may be NULL) receives the variant; ms (may be NULL, 12 entries)
+ * chosen (may be NULL) receives the variant; ms (may be NULL, 16 entries)
  * the measured lattice-kernel milliseconds per step (-1 on a cache hit). */
 int iblb_autotune(iblb_ctx *ctx, int steps, const char *cache_path, int *chosen, double *ms);
 

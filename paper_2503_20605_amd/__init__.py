@@ -197,10 +197,10 @@ class Solver:
         return out.value
 
     def autotune(self, steps=50, cache_path=None):
-        """Time the twelve lattice-kernel variants and keep the fastest; returns
+        """Time the sixteen lattice-kernel variants and keep the fastest; returns
         (variant, per-variant ms or -1 on a cache hit)."""
         out = ctypes.c_int()
-        ms = (ctypes.c_double * 12)()
+        ms = (ctypes.c_double * 16)()
         cp = None if cache_path is None else str(cache_path).encode()
         self._chk(self.lib.iblb_autotune(self.ctx, int(steps), cp, ctypes.byref(out), ms))
         return out.value, list(ms)

@@ -28,12 +28,14 @@ namespace {
 
 // Lattice-kernel variants (autotuner candidates): tiles of 256x1, 128x2 or
 // 64x4 cells per block (shape v % 3), ordinary or non-temporal stores
-// ((v / 3) % 2), ordinary or non-temporal loads (v / 6).
-constexpr int kShapes = 3;
-constexpr int kVariants = 12;
-constexpr int kShapeBX[kShapes] = {256, 128, 64};
-constexpr int kShapeBY[kShapes] = {1, 2, 4};
-int shape_of(int variant) { return variant % kShapes; }
+// ((v / 3) % 2), ordinary or non-temporal loads (v / 6) for v < 12; then
+// the flat form (256 consecutive cells per block, shape 3) with the four
+// load/store kinds (v = 12 + stores + 2 loads).
+constexpr int kShapes = 4;
+constexpr int kVariants = 16;
+constexpr int kShapeBX[kShapes] = {256, 128, 64, 0};
+constexpr int kShapeBY[kShapes] = {1, 2, 4, 0};
+int shape_of(int variant) { return variant < 12 ? variant % 3 : 3; }
 constexpr size_t kAlign = 256;
 constexpr int kMaxGraphSteps = 1024;
 constexpr int kTimedLaunches = 256;  // timed lattice launches per replay at most
@@ -83,6 +85,7 @@ long long pop_stride(long long cells) {
 }
 
 int tiles_of(const iblb_params& p, int shape) {
+    if (kShapeBX[shape] == 0) return ceil_div(p.nx * p.ny * (p.dim == 3 ? p.nz : 1), kBlock);
     const int bx = kShapeBX[shape], by = kShapeBY[shape];
     return ceil_div(p.nx, bx) * ceil_div(p.ny, by) * (p.dim == 3 ? p.nz : 1);
 }
@@ -111,7 +114,7 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.tri_off.assign(n, 0);
     L.row_off.assign(n, 0);
     L.rows = 0;
-    int tiles[kShapes] = {0, 0, 0};
+    int tiles[kShapes] = {0, 0, 0, 0};
     for (int d = 0; d < n; ++d) {
         const iblb_params& p = P[d];
         char buf[256];
@@ -187,7 +190,7 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.U = take(sizeof(float) * dim * C);
     L.Fout = take(sizeof(float) * dim * C);
     L.rho = take(sizeof(float) * C);
-    L.flags = take((size_t)L.flag_bytes);
+    L.flags = take(2 * (size_t)L.flag_bytes);  // band flags, one set per step parity
     L.pos0 = take(sizeof(double) * 3 * N);  // positions, one buffer per step parity
     L.pos1 = take(sizeof(double) * 3 * N);
     L.phi = take(sizeof(float) * 3 * N);
@@ -306,6 +309,12 @@ void set_window(DropDev& D, const int* bc, const double* ref) {
     D.img_r = D.win[0] - D.img_base;
 }
 
+// Band flags of step parity p: set by the spreading for a step of that
+// parity, read by its lattice update.
+uint8_t* band_flags(const iblb_ctx* c, int p) {
+    return c->at<uint8_t>(c->L.flags) + (p ? c->L.flag_bytes : 0);
+}
+
 // Crossing tables of step parity p (see cell_inside).
 int* cross_count(const iblb_ctx* c, int p) { return c->at<int>(p ? c->L.xcnt1 : c->L.xcnt0); }
 double* cross_x(const iblb_ctx* c, int p) { return c->at<double>(p ? c->L.xpos1 : c->L.xpos0); }
@@ -379,6 +388,10 @@ int upload_chunks(iblb_ctx* c) {
 // Tiles of droplet d in the given shape, x fastest, then y, then z.
 void push_tiles(const iblb_ctx* c, int d, int shape, std::vector<int4>& v) {
     const iblb_params& p = c->params[d];
+    if (kShapeBX[shape] == 0) {  // flat: runs of kBlock cells in storage order
+        for (int b = 0; b < tiles_of(p, shape); ++b) v.push_back(make_int4(d, b, 0, 0));
+        return;
+    }
     const int bx = kShapeBX[shape], by = kShapeBY[shape];
     const int ntx = ceil_div(p.nx, bx), nty = ceil_div(p.ny, by);
     const int nz = c->dim == 3 ? p.nz : 1;
@@ -422,7 +435,8 @@ void launch_lb_v(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned l
         hipLaunchKernelGGL(kern, grid, block, 0, s, c->at<DropDev>(c->L.drops),
                            c->at<int4>(c->L.tiles_lb), (const T*)f[src], f[src ^ 1],
                            c->at<float>(c->L.F), c->at<float>(c->L.U), c->at<float>(c->L.rho),
-                           c->at<float>(c->L.Fout), c->at<uint8_t>(c->L.flags), full, stamps,
+                           c->at<float>(c->L.Fout), (const uint8_t*)band_flags(c, src),
+                           clear ? band_flags(c, src ^ 1) : nullptr, full, stamps,
                            (const int*)cross_count(c, src), (const double*)cross_x(c, src),
                            clear ? cross_count(c, src ^ 1) : nullptr);
     };
@@ -438,7 +452,11 @@ void launch_lb_v(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned l
         case 8: go(k_lb<DIM, S, 64, 0, 1, VIS>); break;
         case 9: go(k_lb<DIM, S, 256, 1, 1, VIS>); break;
         case 10: go(k_lb<DIM, S, 128, 1, 1, VIS>); break;
-        default: go(k_lb<DIM, S, 64, 1, 1, VIS>); break;
+        case 11: go(k_lb<DIM, S, 64, 1, 1, VIS>); break;
+        case 12: go(k_lb<DIM, S, 0, 0, 0, VIS>); break;
+        case 13: go(k_lb<DIM, S, 0, 1, 0, VIS>); break;
+        case 14: go(k_lb<DIM, S, 0, 0, 1, VIS>); break;
+        default: go(k_lb<DIM, S, 0, 1, 1, VIS>); break;
     }
 }
 
@@ -484,7 +502,7 @@ void launch_spread(const iblb_ctx* c, hipStream_t s, int p, int want_dropped) {
     const bool one = c->n == 1;
     if (c->dim == 2) {
         hipLaunchKernelGGL((one ? k_force_spread<2, true> : k_force_spread<2, false>), grid, block, 0, s, D,
-                           A, c->at<float>(c->L.F), c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status),
+                           A, c->at<float>(c->L.F), band_flags(c, p), c->at<int>(c->L.status),
                            want_dropped);
         return;
     }
@@ -493,7 +511,7 @@ void launch_spread(const iblb_ctx* c, hipStream_t s, int p, int want_dropped) {
     if (c->nchunks == 0) return;
     hipLaunchKernelGGL(k_spread3, dim3(c->nchunks), dim3(kSpreadBlock), 0, s, D, A,
                        (const int4*)c->at<int4>(c->L.chunks), c->at<float>(c->L.F),
-                       c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status), want_dropped);
+                       band_flags(c, p), c->at<int>(c->L.status), want_dropped);
 }
 
 // Node work after the lattice step of parity p: interpolate and advect
@@ -510,7 +528,7 @@ void launch_after(const iblb_ctx* c, hipStream_t s, int p, bool last, int want_d
     const float* U = c->at<float>(c->L.U);
     if (c->dim == 2 && !last) {
         hipLaunchKernelGGL(one ? k_ib_fused2<true> : k_ib_fused2<false>, grid, block, 0, s, D, A, U,
-                           c->at<float>(c->L.F), c->at<uint8_t>(c->L.flags), c->at<int>(c->L.status),
+                           c->at<float>(c->L.F), band_flags(c, p ^ 1), c->at<int>(c->L.status),
                            want_dropped, cross_count(c, p ^ 1), cross_x(c, p ^ 1));
         return;
     }
@@ -636,7 +654,8 @@ int reset_droplet(iblb_ctx* c, int d) {
     HIPCHK(c, hipMemsetAsync(c->ws + c->L.Fout + vo, 0, vb, c->stream));
     const iblb_params& p = c->params[d];
     const size_t fb = (size_t)(c->dim == 3 ? p.nz : 1) * p.ny * ceil_div(p.nx, kStrip);
-    HIPCHK(c, hipMemsetAsync(c->ws + c->L.flags + D.flag_off, 0, fb, c->stream));
+    HIPCHK(c, hipMemsetAsync(band_flags(c, 0) + D.flag_off, 0, fb, c->stream));
+    HIPCHK(c, hipMemsetAsync(band_flags(c, 1) + D.flag_off, 0, fb, c->stream));
     hipLaunchKernelGGL(k_fill_f32, dim3(ceil_div(D.ncell, kBlock)), dim3(kBlock), 0, c->stream,
                        c->at<float>(c->L.rho) + D.c_off, (long long)D.ncell, 1.0f);
     HIPCHK(c, hipGetLastError());
@@ -1350,7 +1369,7 @@ int iblb_run_to_rest(iblb_ctx* c, double tol, int check_every, int hold, long lo
 int iblb_set_lb_variant(iblb_ctx* c, int variant, int* variant_out) {
     if (!c) return IBLB_EINVAL;
     if (variant >= kVariants || variant < -1)
-        return fail(c, IBLB_EINVAL, "lattice-kernel variant must be -1 or 0..11");
+        return fail(c, IBLB_EINVAL, "lattice-kernel variant must be -1 or 0..15");
     if (variant >= 0 && variant != c->variant) {
         c->variant = variant;
         c->tiles_dirty = true;

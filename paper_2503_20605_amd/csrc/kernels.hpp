@@ -204,6 +204,10 @@ __device__ __forceinline__ bool cell_inside(const DropDev& D, const int* __restr
 // that x-streamed populations straddle).
 // VIS = 1 (instantiated only while some droplet of the handle has two
 // viscosities) takes each cell's relaxation time from the classification.
+// BX = 0 is the flat form: a block takes 256 consecutive cells of the
+// droplet in storage order, whatever nx is, so rows that are not a multiple
+// of 64 cells long leave no lanes idle (a wavefront may then span two rows,
+// and the band flag and the row of the classification are read per lane).
 template <int DIM, int S, int BX, int NT, int NTL, int VIS>
 __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops,
                                                const int4* __restrict__ tiles,
@@ -212,7 +216,8 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
                                                float* __restrict__ F_all, float* __restrict__ U_all,
                                                float* __restrict__ rho_all,
                                                float* __restrict__ Fout_all,
-                                               uint8_t* __restrict__ flags_all, int full,
+                                               const uint8_t* __restrict__ flags_all,
+                                               uint8_t* __restrict__ flags_clr, int full,
                                                unsigned long long* __restrict__ stamps,
                                                const int* __restrict__ xcnt,
                                                const double* __restrict__ xpos,
@@ -220,7 +225,8 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
     using L = Lattice<DIM>;
     using C = Codec<S>;
     constexpr int Q = L::Q;
-    constexpr int BY = kBlock / BX;
+    constexpr bool FLAT = BX == 0;
+    constexpr int BY = FLAT ? 1 : kBlock / (FLAT ? 1 : BX);
     // timing only (stamps non-null): block start on the device's
     // constant-rate clock, folded into one of kStampSpread slots (one cache
     // line each) so that the atomics do not pile up on a single address
@@ -229,10 +235,20 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
     const int4 tile = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const DropDev& D = drops[tile.x];
     const int nx = D.nx, ny = D.ny, nz = D.nz;
-    const int x = tile.y * BX + (int)(threadIdx.x % BX);
-    const int y = tile.z * BY + (int)(threadIdx.x / BX);
-    const int z = tile.w;
-    if (x >= nx || y >= ny) return;
+    int x, y, z;
+    if constexpr (FLAT) {
+        const int c = tile.y * kBlock + (int)threadIdx.x;
+        if (c >= D.ncell) return;
+        const int r = c / nx;
+        x = c - r * nx;
+        z = r / ny;
+        y = r - z * ny;
+    } else {
+        x = tile.y * BX + (int)(threadIdx.x % (FLAT ? 1 : BX));
+        y = tile.z * BY + (int)(threadIdx.x / (FLAT ? 1 : BX));
+        z = tile.w;
+        if (x >= nx || y >= ny) return;
+    }
     const int ncell = D.ncell, fst = D.fst;
     const int cell = (z * ny + y) * nx + x;
     const typename C::T* __restrict__ fsrc = fsrc_all + D.f_off;
@@ -267,13 +283,18 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
     float* __restrict__ U = U_all + (long long)DIM * D.c_off;
     bool forced;
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
-    uint8_t* flag = nullptr;
     if (D.force_mode == 1) {
         forced = true;
     } else {
-        flag = flags_all + D.flag_off + (z * ny + y) * D.nstrip + (x >> 6);
-        // every lane of a wavefront lies in the same strip
-        forced = __builtin_amdgcn_readfirstlane((int)*flag) != 0;
+        // band flags of this step (set by the spreading); those of the
+        // other parity, read by the step before, are cleared for the
+        // spreading of the next step by the first lane of each strip
+        const long long fi = D.flag_off + (long long)(z * ny + y) * D.nstrip + (x >> 6);
+        if constexpr (FLAT)
+            forced = flags_all[fi] != 0;
+        else  // every lane of a wavefront lies in the same strip
+            forced = __builtin_amdgcn_readfirstlane((int)flags_all[fi]) != 0;
+        if (flags_clr && (x & 63) == 0) flags_clr[fi] = 0;
     }
     if (forced) {
         Fx = F[cell];
@@ -284,8 +305,8 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
     const float rho = M.rho, ux = M.ux, uy = M.uy, uz = M.uz;
     float om = D.omega, g = D.guo;
     if (VIS && D.visc) {
-        // every lane of a wavefront lies in the same row (BX >= 64)
-        const int row = __builtin_amdgcn_readfirstlane(z * ny + y);
+        // every lane of a wavefront lies in the same row when BX >= 64
+        const int row = FLAT ? z * ny + y : __builtin_amdgcn_readfirstlane(z * ny + y);
         if (cell_inside(D, xcnt, xpos, x, row)) {
             om = D.omega_in;
             g = D.guo_in;
@@ -311,7 +332,6 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         F[cell] = 0.f;
         F[ncell + cell] = 0.f;
         if (DIM == 3) F[2 * ncell + cell] = 0.f;
-        *flag = 0;
     }
     if (full) {
         float* __restrict__ Fo = Fout_all + (long long)DIM * D.c_off;
@@ -327,7 +347,8 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
     }
     if (stamp) {
         // wavefront end, once its stores have completed; lane 0 of a
-        // wavefront is active whenever any lane is (x grows with the lane)
+        // wavefront is active whenever any lane is (the cell index grows
+        // with the lane)
         __builtin_amdgcn_s_waitcnt(0);
         if ((threadIdx.x & 63) == 0) atomicMax(stamp + 1, (unsigned long long)wall_clock64());
     }

@@ -106,7 +106,7 @@ def test_droplet_2d_graph_and_tiles():
     """Three tile shapes and a non-temporal-load variant; graph replays of 2
     steps plus direct launches, the timed schedule, and no graphs."""
     W = wl.droplet_2d_small()
-    cases = ((0, 2), (4, 2), (2, 0), (10, 2))
+    cases = ((0, 2), (4, 2), (2, 0), (10, 2), (13, 2))
     outs = run_cases([dict(params_list=[W.params], nodes_list=[W.nodes], steps=(5, 4), shape=shape,
                            graph_steps=gs, timing=(shape == 4)) for shape, gs in cases])
     r = o.run(W.params, W.nodes, 9)
@@ -118,10 +118,13 @@ def test_droplet_2d_graph_and_tiles():
         assert abs(g["diag"]["mass"] - r["f"].sum()) < 1e-6
 
 
-def test_ragged_box_and_periodic_crossing():
+@pytest.mark.parametrize("shape", [5, 14])
+def test_ragged_box_and_periodic_crossing(shape):
+    """A box whose rows are not a multiple of 64 cells, with a tiled and a
+    flat lattice-kernel variant (in the flat one a wavefront spans rows)."""
     p = wl.Params(dim=2, nx=101, ny=37, tau=0.8, sigma=0.008, theta_eq_deg=110.0, xi=2.0)
     q = wl.cap_polygon(10.0, 95.0, 2.0, 70, 2.0)
-    g = run_case([p], [q], steps=(7,), shape=5, graph_steps=2)[0]
+    g = run_case([p], [q], steps=(7,), shape=shape, graph_steps=2)[0]
     r = o.run(p, q, 7)
     drho, du, dq = compare_fields(g, r, 2, "emu ragged")
     assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7

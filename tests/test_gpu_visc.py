@@ -133,10 +133,10 @@ def test_two_viscosities_droplet_300_steps():
     assert np.max(np.abs(g1["U"] - g["U"])) > 100 * du * np.max(np.abs(r["U"]))
 
 
-@pytest.mark.parametrize("variant", [0, 4, 8, 11])
+@pytest.mark.parametrize("variant", [0, 4, 8, 11, 12, 15])
 def test_two_viscosities_lattice_variants(variant):
     """Every tile shape and load/store kind takes the classification (BX >= 64
-    keeps each wavefront on one row)."""
+    keeps each wavefront on one row; the flat form reads the row per lane)."""
     W = wl.droplet_2d_small()
     p = wl.Params(**{**W.params.to_dict(), "lam": 0.3})
     print(f"[visc] variant {variant}", flush=True)
