@@ -146,12 +146,13 @@ def test_two_viscosities_lattice_variants(variant):
     assert drho <= 1e-5 and du <= 1e-5 and dq <= 1e-6
 
 
-def test_two_viscosities_3d_across_periodic_edge():
+@pytest.mark.parametrize("variant", [0, 13])
+def test_two_viscosities_3d_across_periodic_edge(variant):
     p = wl.Params(dim=3, nx=30, ny=28, nz=16, bc=(wl.BC_PERIODIC, wl.BC_PERIODIC, wl.BC_WALL),
                   tau=0.7, sigma=0.006, theta_eq_deg=80.0, xi=2.0, lam=6.0)
     V, T = wl.cap_mesh(8.0, 90.0, 2.0, 5, (1.5, 27.3))
-    print("[visc] 3d lambda=6 6 steps", flush=True)
-    g = gpu_run(p, V, 6, tris=T, graph_steps=2)
+    print(f"[visc] 3d lambda=6 6 steps, variant {variant}", flush=True)
+    g = gpu_run(p, V, 6, tris=T, graph_steps=2, shape=variant)
     r = o.run(p, V, 6, tris=T)
     drho, du, dq = compare_fields(g, r, 3, "3d-lambda6")
     assert drho <= 1e-5 and du <= 1e-5 and dq <= 1e-6
