@@ -155,7 +155,8 @@ def solve(theta, eps, N=801, n=6, m=3, guess=None):
     else:
         x0 = np.concatenate([np.interp(u, guess["u"], guess["g"]), [guess["delta"], guess["k"]]])
     x, nr = newton(x0, u, theta, eps, n, m)
-    if not np.isfinite(nr) or nr > 1e-9:
+    # the residual's rounding floor grows with 1/du^2 (second differences)
+    if not np.isfinite(nr) or nr > 1e-9 * max(1.0, (N / 801.0) ** 2):
         raise RuntimeError(f"shape solver did not converge: |res| = {nr:.3e}")
     g = x[:N]
     return dict(u=u, g=g, delta=float(x[N]), k=float(x[N + 1]), ell=float(g[-1]))

@@ -29,15 +29,18 @@ def radial_profile(q, centre, nbins):
 
 
 def theory(theta, eps):
-    """App. B solution, reached by continuation in the angle from pi/2 for
-    acute angles."""
-    if theta >= math.pi / 2:
-        return sh.solve(theta, eps)
-    s = sh.solve(math.pi / 2, eps)
+    """App. B solution, reached by continuation from theta = pi/2 at
+    xi/R0 = 0.1 (where the truncated-cap guess converges): first in the angle
+    (steps of pi/16), then in xi/R0 (steps of at most 0.02)."""
+    s = sh.solve(math.pi / 2, 0.1)
     th = math.pi / 2
-    while th > theta + 1e-12:
-        th = max(theta, th - math.pi / 16)
-        s = sh.solve(th, eps, guess=s)
+    while abs(th - theta) > 1e-12:
+        th = th + max(-math.pi / 16, min(math.pi / 16, theta - th))
+        s = sh.solve(th, 0.1, guess=s)
+    e = 0.1
+    while abs(e - eps) > 1e-12:
+        e = e + max(-0.02, min(0.02, eps - e))
+        s = sh.solve(theta, e, guess=s)
     return s
 
 
