@@ -104,6 +104,9 @@ def parse():
                     help="contact radius against time on the spreading set-up (240x240x130, "
                          "R0 = 60, viscosity ratio 10) by both protocols, with the exponent of "
                          "the early power law")
+    ap.add_argument("--tanner", action="store_true",
+                    help="contact radius against time in the late, viscous stage: a hemisphere of "
+                         "R0 = 60 spreading towards theta_eq = 22.5 deg (Tanner's law r_c ~ t^(1/10))")
     ap.add_argument("--hbm-probe", action="store_true",
                     help="only the lattice kernel on an 8192x4096 D2Q9 box and the copy probe "
                          "(short; used for hardware-counter runs)")
@@ -192,6 +195,59 @@ def spreading(a):
     print(json.dumps({"metric": "contact-radius exponent of early spreading (inertial law: 1/2)",
                       "workload": W.name, "fit_window_t_over_t_tilde": [0.05, 0.5],
                       "runs": runs}), flush=True)
+
+
+def tanner(a):
+    """Late-stage spreading (Sec. Dynamics): the droplet starts as a
+    hemisphere of the volume of a sphere of radius R0 = 60 and spreads towards
+    its theta_eq = 22.5 deg cap.  The contact radius is sampled on a
+    logarithmic grid of steps by protocol (i) (z_cut = h* + 1, just above the
+    film the wall term holds) and protocol (ii) (eps = 0.003); the exponent of
+    r_c ~ t^alpha is fitted per decade of steps.  Tanner's law predicts
+    alpha = 1/10 once viscous forces and surface tension balance."""
+    import numpy as np
+    import workloads as wl
+    from paper_2503_20605_amd import Solver, params_from
+    W = wl.droplet_3d_tanner()
+    p = W.params
+    R0 = W.meta["R0"]
+    s = Solver([params_from(p)], [W.nodes], [W.tris])
+    s.autotune(steps=16)
+    zc = p.xi * 2.0 ** (1.0 / 3.0) + 1.0
+    n_total = a.max_steps if a.max_steps != 200000 else 150000
+    marks = sorted({int(round(10 ** e)) for e in np.arange(1.0, math.log10(n_total) + 1e-9, 0.05)})
+    ts, ri, rii = [], [], []
+    t0 = time.perf_counter()
+    done = 0
+    for m in marks:
+        s.step(m - done)
+        done = m
+        r1, r2, _ = s.contact_radius(0, zc, 0.003 * R0)
+        ts.append(done)
+        ri.append(r1)
+        rii.append(r2)
+        if done % 10000 == 0 or m == marks[-1]:
+            print(json.dumps({"steps": done, "r_i": r1, "r_ii": r2}), file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    d = s.diagnostics(0)
+    s.close()
+    t = np.array(ts, dtype=np.float64)
+    fits = {}
+    for name, r in (("i", np.array(ri)), ("ii", np.array(rii))):
+        for lo in (100, 1000, 10000):
+            sel = (t >= lo) & (t <= 10 * lo) & np.isfinite(r) & (r > 0)
+            fits[f"{name}_{lo}_{10 * lo}"] = (round(float(np.polyfit(np.log(t[sel]), np.log(r[sel]), 1)[0]), 4)
+                                              if sel.sum() >= 3 else None)
+    print(json.dumps({"metric": "contact-radius exponent of late spreading (Tanner's law: 1/10)",
+                      "workload": W.name, "cells": p.nx * p.ny * p.nz, "vertices": len(W.nodes),
+                      "steps": n_total, "wall_s": round(wall, 1),
+                      "ms_per_step": round(wall / n_total * 1e3, 4), "z_cut": round(zc, 4),
+                      "eps": 0.003, "r_eq_closed_form": round(W.meta["r_eq"], 3), "alpha": fits,
+                      "final": {"r_i": ri[-1], "r_ii": rii[-1],
+                                "theta_meas_deg": math.degrees(d["theta_meas"]),
+                                "max_normal_speed": d["max_normal_speed"]},
+                      "series": {"steps": ts, "r_i": [None if not math.isfinite(v) else round(v, 4) for v in ri],
+                                 "r_ii": [round(v, 4) for v in rii]}}), flush=True)
 
 
 def tte(a):
@@ -338,6 +394,9 @@ def main():
         return
     if a.spreading:
         spreading(a)
+        return
+    if a.tanner:
+        tanner(a)
         return
     if a.hbm_probe:
         from paper_2503_20605_amd import probe_copy_bandwidth

@@ -305,6 +305,29 @@ def droplet_3d_statics(theta_eq_deg: float, xi_over_R0: float = 0.1, nu: int = 4
                     meta={"R0": R0})
 
 
+def droplet_3d_tanner(theta_eq_deg: float = 22.5, R0: float = 60.0, xi: float = 3.0,
+                      nu: int = 80) -> Workload:
+    """Late-stage (viscous) spreading set-up after Sec. Dynamics: the droplet
+    starts as a hemisphere of the volume of a sphere of radius R0 (so the
+    inertial stage is skipped) on the substrate of a periodic box wide enough
+    for its equilibrium cap at theta_eq (contact radius about 2.4 R0 at
+    22.5 deg), xi = 3.  Frequency-nu icosphere projected onto the cap (nu = 80:
+    128000 triangles, edges of about 1.4 lattice units at R0 = 60); tau = 0.8,
+    sigma = 0.005 (the paper lists neither)."""
+    Rc = R0 * 2.0 ** (1.0 / 3.0)                       # hemisphere of the sphere's volume
+    th = math.radians(theta_eq_deg)
+    # equilibrium cap of the same volume: V = (pi/3) R^3 (2 - 3 cos + cos^3)
+    Req = (4.0 * R0 ** 3 / (2.0 - 3.0 * math.cos(th) + math.cos(th) ** 3)) ** (1.0 / 3.0)
+    r_eq = Req * math.sin(th)
+    n = int(math.ceil((2.0 * r_eq + 40.0) / 16.0)) * 16
+    nz = int(math.ceil((Rc + xi + 20.0) / 16.0)) * 16
+    p = Params(dim=3, nx=n, ny=n, nz=nz, bc=(BC_PERIODIC, BC_PERIODIC, BC_WALL),
+               tau=0.8, sigma=0.005, theta_eq_deg=theta_eq_deg, xi=xi)
+    V, T = cap_mesh(Rc, 90.0, xi, nu, (n / 2.0, n / 2.0))
+    return Workload(f"d3q19_{n}x{n}x{nz}_R{R0:g}_theta{theta_eq_deg:g}_tanner", p, V, tris=T,
+                    meta={"R0": R0, "r_eq": r_eq})
+
+
 # ----------------------------------------------------------------------------
 # Raw arrays for unit and parity tests
 # ----------------------------------------------------------------------------
