@@ -497,7 +497,7 @@ void launch_spread(const iblb_ctx* c, hipStream_t s, int p, int want_dropped) {
     if (c->any_visc) launch_cross(c, s, p, p, 0);
     const NodeArrays A = node_arrays(c, p);
     const int lanes = c->L.ntot * (c->dim == 2 ? Taps<2>::n : Taps<3>::n);
-    const dim3 grid(ceil_div(lanes, kBlock)), block(kBlock);
+    const dim3 grid(ceil_div(lanes, kNodeBlock)), block(kNodeBlock);
     const DropDev* D = c->at<DropDev>(c->L.drops);
     const bool one = c->n == 1;
     if (c->dim == 2) {
@@ -506,7 +506,7 @@ void launch_spread(const iblb_ctx* c, hipStream_t s, int p, int want_dropped) {
                            want_dropped);
         return;
     }
-    hipLaunchKernelGGL(one ? k_force3<true> : k_force3<false>, dim3(ceil_div(c->L.ntot, kBlock)), block, 0, s,
+    hipLaunchKernelGGL(one ? k_force3<true> : k_force3<false>, dim3(ceil_div(c->L.ntot, kBlock)), dim3(kBlock), 0, s,
                        D, A);
     if (c->nchunks == 0) return;
     hipLaunchKernelGGL(k_spread3, dim3(c->nchunks), dim3(kSpreadBlock), 0, s, D, A,
@@ -522,7 +522,7 @@ void launch_after(const iblb_ctx* c, hipStream_t s, int p, bool last, int want_d
     if (c->L.ntot == 0) return;
     const NodeArrays A = node_arrays(c, p);
     const int lanes = c->L.ntot * (c->dim == 2 ? Taps<2>::n : Taps<3>::n);
-    const dim3 grid(ceil_div(lanes, kBlock)), block(kBlock);
+    const dim3 grid(ceil_div(lanes, kNodeBlock)), block(kNodeBlock);
     const DropDev* D = c->at<DropDev>(c->L.drops);
     const bool one = c->n == 1;
     const float* U = c->at<float>(c->L.U);
