@@ -1,11 +1,14 @@
 // Host runtime and C ABI of the gfx950 IB-LB wetting solver (see iblb.h).
 //
 // One handle owns a batch of droplets.  All device arrays are carved from
-// the caller's workspace.  A time step is three launches on the caller's
-// stream: k_force_spread (nodes), k_lb (cells, over a tile list that
-// concatenates every active droplet's tiles), k_interp_advect (nodes).
-// Long runs replay a hipGraph that holds a fixed, even number of steps, so
-// the ping-pong buffers are back in place after every replay.
+// the caller's workspace.  A time step in 2D is two launches on the
+// caller's stream: k_lb (cells, over a tile list that concatenates every
+// active droplet's tiles) and k_ib_fused2 (nodes: interpolation and
+// advection, then the forces and spreading of the next step); in 3D k_lb,
+// k_interp_advect, (k_cross3,) k_force3 and k_spread3.  The first step of a
+// call spreads its own forces and the last one only interpolates.  Long
+// runs replay a hipGraph that holds a fixed, even number of steps, so the
+// ping-pong buffers are back in place after every replay.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 

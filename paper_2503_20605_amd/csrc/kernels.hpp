@@ -13,19 +13,28 @@
 //   k_ib_fused2       2D: interpolation and advection of one step fused with
 //                     the forces and spreading of the next
 //   k_force3,
-//   k_spread3         3D: forces one lane per vertex, then spreading summed
-//                     per chunk of nearby vertices in LDS
+//   k_spread3         3D: forces one lane per vertex (surface tension, an
+//                     elastic interface's shear part, wetting), then
+//                     spreading summed per chunk of nearby vertices in LDS
+//   k_cross2,
+//   k_cross3          crossings of the interface with the lattice rows, for
+//                     the inside/outside classification of two viscosities
+//   k_inside_mask     that classification as a per-cell mask
+//   k_tri_ref         reference triangles of an elastic interface
 //   k_cell_sums,
-//   k_diag            FP64 reductions for the diagnostics
+//   k_diag, k_contact FP64 reductions for the diagnostics and the contact
+//                     radius
 //
 // Populations are stored as deviations f_i - w_i (see lattice.hpp), in two
 // ping-pong buffers laid out [i][z][y][x] per droplet, x fastest.
 //
 // The force density F and the velocity U are dense per-cell arrays, but the
 // lattice kernel touches them only inside the interface band: the spreading
-// kernel raises a one-byte flag for every 64-cell x strip (one wavefront of
-// the lattice kernel) that receives a tap, and only flagged wavefronts read
-// F, write U for the interpolation, clear F and clear the flag.
+// kernel raises a one-byte flag for every 64-cell x strip that receives a
+// tap, and only flagged cells read F, write U for the interpolation and
+// clear F.  The flags come in two sets, one per step parity: a lattice
+// update reads its own parity's set and clears the other one for the
+// spreading of the next step.
 #pragma once
 
 #include <hip/hip_runtime.h>
