@@ -40,16 +40,24 @@ def lb_kernel_name(dim, storage, variant, vis=0):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lb_traffic.md")
 
 
-def lb_source_hash():
-    """Hash of the lattice kernel's source (lattice.hpp and the part of
-    kernels.hpp up to the end of the lattice kernel), to tell whether stored
-    counter readings still describe the kernel as built."""
+def code_only(src):
+    """C++ source without // comments and with whitespace collapsed."""
+    import re
+    return re.sub(rb"\s+", b" ", re.sub(rb"//[^\n]*", b"", src)).strip()
+
+
+def lb_source_hash(lattice_src=None, kernels_src=None):
+    """Hash of the lattice kernel's code (lattice.hpp and the part of
+    kernels.hpp up to the end of the lattice kernel, comments and layout
+    left out), to tell whether stored counter readings still describe the
+    kernel as built."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2503_20605_amd", "csrc")
+    lat = lattice_src if lattice_src is not None else open(os.path.join(csrc, "lattice.hpp"), "rb").read()
+    k = kernels_src if kernels_src is not None else open(os.path.join(csrc, "kernels.hpp"), "rb").read()
     h = hashlib.sha256()
-    h.update(open(os.path.join(csrc, "lattice.hpp"), "rb").read())
-    k = open(os.path.join(csrc, "kernels.hpp"), "rb").read()
-    h.update(k[:k.index(b"// Nodes whose coordinates are not finite")])
+    h.update(code_only(lat))
+    h.update(code_only(k[:k.index(b"// Nodes whose coordinates are not finite")]))
     return h.hexdigest()[:16]
 
 
