@@ -115,6 +115,9 @@ def parse():
     ap.add_argument("--tanner", action="store_true",
                     help="contact radius against time in the late, viscous stage: a hemisphere of "
                          "R0 = 60 spreading towards theta_eq = 22.5 deg (Tanner's law r_c ~ t^(1/10))")
+    ap.add_argument("--sweep", action="store_true",
+                    help="the ten-run 1024x512 sweep (tau 0.6/1.0 x theta_eq 30-150 deg), 50000 steps "
+                         "each: measured angle and contact radius at the end of every run")
     ap.add_argument("--hbm-probe", action="store_true",
                     help="only the lattice kernel on an 8192x4096 D2Q9 box and the copy probe "
                          "(short; used for hardware-counter runs)")
@@ -256,6 +259,40 @@ def tanner(a):
                                 "max_normal_speed": d["max_normal_speed"]},
                       "series": {"steps": ts, "r_i": [None if not math.isfinite(v) else round(v, 4) for v in ri],
                                  "r_ii": [round(v, 4) for v in rii]}}), flush=True)
+
+
+def sweep(a):
+    """The ten runs of the 1024x512 workload (tau in {0.6, 1.0} x theta_eq in
+    {30, 60, 90, 120, 150} deg, initial cap angle theta_eq + U(-5, 5) deg),
+    50000 coupled steps each: wall time, the angle from the half-height (2D
+    counterpart of eq. angleh) and the contact radius (protocol (i) at h*)
+    at the end."""
+    import workloads as wl
+    from paper_2503_20605_amd import Solver, params_from
+    runs = []
+    for run in range(10):
+        W = wl.droplet_2d_large(run=run)
+        p = W.params
+        s = Solver([params_from(p)], [W.nodes])
+        s.autotune(steps=16)
+        import torch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(W.steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        d = s.diagnostics(0)
+        s.close()
+        runs.append({"run": run, "tau": p.tau, "theta_eq_deg": p.theta_eq_deg,
+                     "theta0_deg": round(W.meta["theta0_deg"], 3), "steps": W.steps,
+                     "wall_s": round(wall, 3),
+                     "MLUPS": round(p.nx * p.ny * W.steps / wall / 1e6, 1),
+                     "theta_meas_deg": round(math.degrees(d["theta_meas"]), 3),
+                     "contact_radius": round(d["contact_radius"], 3),
+                     "max_normal_speed": d["max_normal_speed"], "status": d["status"]})
+        print(json.dumps(runs[-1]), file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "1024x512 sweep: angle from the half-height after 50000 steps",
+                      "workload": "d2q9_1024x512_R120_N1024_run0-9", "runs": runs}), flush=True)
 
 
 def tte(a):
@@ -405,6 +442,9 @@ def main():
         return
     if a.tanner:
         tanner(a)
+        return
+    if a.sweep:
+        sweep(a)
         return
     if a.hbm_probe:
         from paper_2503_20605_amd import probe_copy_bandwidth
