@@ -67,10 +67,11 @@ typedef enum {
                              speed became non-finite or above 0.3, or a node
                              position became non-finite (such nodes are
                              then left out of spreading and interpolation) */
-    IBLB_ELIMIT = -5      /* a fixed capacity was exceeded: more than 16
-                             interface crossings on one lattice row in the
-                             inside/outside classification (the extra
-                             crossings are dropped)                        */
+    IBLB_ELIMIT = -5      /* a limit of the inside/outside classification
+                             was exceeded: more than 16 interface crossings
+                             on one lattice row (the extra crossings are
+                             dropped), or a node outside the classification
+                             window along a periodic axis                  */
 } iblb_status;
 
 typedef enum { IBLB_PERIODIC = 0, IBLB_WALL = 1 } iblb_bc;
@@ -253,8 +254,8 @@ int iblb_set_active(iblb_ctx *ctx, int droplet, int active);
  * exact while every node stays inside that window.  lambda = 1 (the
  * default) turns the classification off.  lambda must be positive and
  * finite, tau finite, and the droplet must have an interface (EINVAL
- * otherwise).  More than 16 crossings on one row fail the step with
- * IBLB_ELIMIT.  Synchronises the stream. */
+ * otherwise).  More than 16 crossings on one row, or a node outside the
+ * window, fail the step with IBLB_ELIMIT.  Synchronises the stream. */
 int iblb_set_viscosity_ratio(iblb_ctx *ctx, int droplet, double lambda);
 
 /* Elastic interface for droplet d (3D): the strain energy of eq. force_bb
@@ -273,8 +274,9 @@ int iblb_set_membrane_shear(iblb_ctx *ctx, int droplet, double mu_s);
  * positions (the rule of iblb_set_viscosity_ratio, for any lambda):
  * d_mask (device, uint8, ncell = nx*ny*nz, [z][y][x]) receives 1 for cells
  * enclosed by the interface and 0 for the others.  The droplet must have
- * an interface.  IBLB_ELIMIT if a row has more than 16 crossings,
- * IBLB_EUNSTABLE for a non-finite node.  Synchronises the stream. */
+ * an interface.  IBLB_ELIMIT if a row has more than 16 crossings or a node
+ * lies outside the window, IBLB_EUNSTABLE for a non-finite node.
+ * Synchronises the stream. */
 int iblb_inside_mask(iblb_ctx *ctx, int droplet, uint8_t *d_mask);
 
 /* Contact radius of droplet d at its current node positions by the two

@@ -1220,12 +1220,13 @@ int iblb_step(iblb_ctx* c, int n_steps) {
         if (c->status_h[d] && c->drops[d].active) {
             char buf[256];
             const int code = c->status_h[d];
-            snprintf(buf, sizeof buf, "droplet %d %s (code %d:%s%s%s%s) by step %lld", d,
+            snprintf(buf, sizeof buf, "droplet %d %s (code %d:%s%s%s%s%s) by step %lld", d,
                      (code & 7) ? "unstable" : "over a fixed limit", code,
                      (code & 1) ? " node at or below the substrate" : "",
                      (code & 2) ? " node speed above 0.3 or not finite" : "",
                      (code & 4) ? " node position not finite or far outside the box" : "",
                      (code & 8) ? " more than 16 interface crossings on one lattice row" : "",
+                     (code & 16) ? " a node left the window of the inside/outside classification" : "",
                      (long long)c->step);
             return fail(c, (code & 7) ? IBLB_EUNSTABLE : IBLB_ELIMIT, buf);
         }
@@ -1461,6 +1462,9 @@ int iblb_inside_mask(iblb_ctx* c, int d, uint8_t* d_mask) {
     code &= ~before;
     if (code & 4) return fail(c, IBLB_EUNSTABLE, "inside mask: node position not finite");
     if (code & 8) return fail(c, IBLB_ELIMIT, "inside mask: more than 16 crossings on one lattice row");
+    if (code & 16)
+        return fail(c, IBLB_ELIMIT, "inside mask: a node lies outside the classification window "
+                                    "(the droplet spans more than the box along a periodic axis)");
     return IBLB_OK;
 }
 

@@ -714,6 +714,19 @@ __device__ __forceinline__ void add_crossing(const DropDev& D, int* __restrict__
         atomicOr(status + d, 8);
 }
 
+// Whether a node lies inside the droplet's classification window along its
+// periodic axes (along a wall axis the box itself bounds it).  A node
+// outside would make the rows' crossings miss or double the interface: the
+// crossing kernels then set status bit 16.
+template <int DIM>
+__device__ __forceinline__ bool in_window(const DropDev& D, const double* q) {
+    bool ok = true;
+    if (!D.bcx) ok = ok && q[0] >= D.win[0] && q[0] < D.win[0] + D.nx;
+    if (!D.bcy) ok = ok && q[1] >= D.win[1] && q[1] < D.win[1] + D.ny;
+    if (DIM == 3 && !D.bcz) ok = ok && q[2] >= D.win[2] && q[2] < D.win[2] + D.nz;
+    return ok;
+}
+
 // Row index of the image j of a row coordinate along an axis of n rows.
 __device__ __forceinline__ int wrap_row(int j, int n) {
     j %= n;
@@ -727,6 +740,7 @@ __device__ __forceinline__ int wrap_row(int j, int n) {
 __device__ __forceinline__ void cross_edge_2d(const DropDev& D, int* __restrict__ cnt,
                                               double* __restrict__ xs, const double a[2],
                                               const double b[2], int* __restrict__ status, int d) {
+    if (!in_window<2>(D, a)) atomicOr(status + d, 16);  // node a of this edge
     const double wlo = D.win[1], whi = D.win[1] + D.ny;
     const double lo = fmax(fmin(a[1], b[1]), wlo), hi = fmin(fmax(a[1], b[1]), whi);
     if (!(lo <= hi)) return;
@@ -764,6 +778,8 @@ __device__ __forceinline__ int edge_side(const double P[3], int ip, const double
 __device__ __forceinline__ void cross_tri_3d(const DropDev& D, int* __restrict__ cnt,
                                              double* __restrict__ xs, const double P[3][3],
                                              const int id[3], int* __restrict__ status, int d) {
+    if (!(in_window<3>(D, P[0]) && in_window<3>(D, P[1]) && in_window<3>(D, P[2])))
+        atomicOr(status + d, 16);
     const double ylo = D.win[1], yhi = D.win[1] + D.ny, zlo = D.win[2], zhi = D.win[2] + D.nz;
     const double y0 = fmax(fmin(fmin(P[0][1], P[1][1]), P[2][1]), ylo);
     const double y1 = fmin(fmax(fmax(P[0][1], P[1][1]), P[2][1]), yhi);

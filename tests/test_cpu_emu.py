@@ -239,6 +239,14 @@ def test_elastic_interface_3d(background):
     assert np.max(np.abs(r0["phi"] - r["phi"])) > 1e-3 * np.max(np.abs(r["phi"]))
 
 
+def test_droplet_wider_than_the_window_is_reported():
+    p = wl.Params(dim=2, nx=40, ny=32, tau=0.8, sigma=0.004, wetting=False, lam=2.0)
+    t = 2.0 * np.pi * np.arange(120) / 120
+    q = np.stack([20.0 + 22.0 * np.cos(t), 16.0 + 6.0 * np.sin(t)], axis=1)
+    g = run_case([p], [q], steps=(1,), graph_steps=0)[0]
+    assert g["status"] == -5 and "window" in g["message"]
+
+
 def test_two_viscosities_3d(background):
     p, V, T = _visc3d_case()
     g = background["visc3d"].result()[0]

@@ -207,3 +207,18 @@ def test_too_many_crossings_on_a_row_is_reported():
     s.set_viscosity_ratio(0, 3.0)
     with pytest.raises(Exception, match="IBLB_ELIMIT"):
         s.step(2)
+
+
+def test_droplet_wider_than_the_window_is_reported():
+    """An ellipse wider than the periodic box along x: its nodes cannot all
+    lie in the classification window, which the mask and the step report."""
+    p = wl.Params(dim=2, nx=40, ny=32, tau=0.8, sigma=0.004, wetting=False)
+    t = 2.0 * np.pi * np.arange(120) / 120
+    q = np.stack([20.0 + 22.0 * np.cos(t), 16.0 + 6.0 * np.sin(t)], axis=1)
+    s = gpu_solver([p], [q])
+    with pytest.raises(Exception, match="IBLB_ELIMIT"):
+        s.inside_mask(0)
+    s.set_viscosity_ratio(0, 2.0)
+    with pytest.raises(Exception, match="IBLB_ELIMIT"):
+        s.step(1)
+
