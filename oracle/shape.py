@@ -202,3 +202,138 @@ def radial_profile_about(u, g, z0, phis):
     dist = np.hypot(rho, z)
     order = np.argsort(ang)
     return np.interp(phis, ang[order], dist[order])
+
+
+# --------------------------------------------------------------------------
+# 2D counterpart (a droplet that is a long cylinder, the 2D model of this
+# library): the outline r = R0 g(phi) in the plane, phi from the +z axis on
+# [0, pi] by symmetry, origin midway between the top and the bottom.  The
+# curvature of a polar curve replaces the divergence of eq. YL; the wall
+# term is the same (the wedge argument of App. A is planar); the area of a
+# circle of radius R0 replaces eq. volconstr.
+# --------------------------------------------------------------------------
+
+def curvature_2d(g, gd, gdd):
+    """Curvature (times R0) of the polar curve r = g(phi)."""
+    return (g * g + 2.0 * gd * gd - g * gdd) / (g * g + gd * gd) ** 1.5
+
+
+def derivatives_2d(g, dphi):
+    """Second-order central differences with the mirror symmetry of the
+    outline about the axis at phi = 0 and phi = pi (g' = 0 there)."""
+    ge = np.concatenate([[g[1]], g, [g[-2]]])
+    gd = (ge[2:] - ge[:-2]) / (2.0 * dphi)
+    gdd = (ge[2:] - 2.0 * g + ge[:-2]) / (dphi * dphi)
+    return gd, gdd
+
+
+def residual_2d(x, phi, theta, eps, n=6, m=3, wall=True):
+    N = phi.size
+    g, delta, k = x[:N], x[N], x[N + 1]
+    dphi = phi[1] - phi[0]
+    gd, gdd = derivatives_2d(g, dphi)
+    r = curvature_2d(g, gd, gdd) - k
+    if wall:
+        h = g * np.cos(phi) + g[-1] + delta
+        r = r + wall_term(h, theta, eps, n, m)
+    area = dphi * (np.sum(g ** 2) - 0.5 * (g[0] ** 2 + g[-1] ** 2)) - math.pi
+    return np.concatenate([r, [g[0] - g[-1], area]])
+
+
+def solve_2d(theta, eps, N=801, n=6, m=3, guess=None):
+    """2D equilibrium outline for contact angle theta and eps = xi / R0, from
+    a truncated circular cap of the same area (or a previous solution).
+    Returns dict(phi, g, delta, k, ell) with ell = g(0) the half-height."""
+    phi = np.linspace(0.0, math.pi, N)
+    if guess is None:
+        # circular cap of area pi (R0 = 1): Rc^2 (theta - sin cos) = pi
+        Rc = math.sqrt(math.pi / (theta - math.sin(theta) * math.cos(theta)))
+        ell = Rc * math.sin(theta / 2.0) ** 2
+        zc = ell - Rc
+        u = np.cos(phi)
+        r_s = u * zc + np.sqrt(np.maximum(u * u * zc * zc - zc * zc + Rc * Rc, 0.0))
+        with np.errstate(divide="ignore"):
+            r_p = np.where(u < 0.0, ell / np.maximum(-u, 1e-300), np.inf)
+        x0 = np.concatenate([np.minimum(r_s, r_p), [eps, 1.0 / Rc]])
+    else:
+        x0 = np.concatenate([np.interp(phi, guess["phi"], guess["g"]), [guess["delta"], guess["k"]]])
+
+    def res(x):
+        return residual_2d(x, phi, theta, eps, n, m)
+
+    dphi = phi[1] - phi[0]
+    w = np.full(N, dphi)
+    w[0] *= 0.5
+    w[-1] *= 0.5
+
+    def jac(x, r0):
+        """Forward differences: g_j enters curvature rows j - 1 .. j + 1 only
+        (the mirror ghosts keep rows 0 and N - 1 on g_1 and g_N-2), so columns
+        five apart share an evaluation; g(pi) (through h), delta and k enter
+        every row.  The rows of the end condition and the area are exact."""
+        J = np.zeros((r0.size, x.size))
+        for j in (N - 1, N, N + 1):
+            hj = 1e-7 * max(1.0, abs(x[j]))
+            xp = x.copy()
+            xp[j] += hj
+            J[:N, j] = (res(xp)[:N] - r0[:N]) / hj
+        for c in range(5):
+            cols = np.arange(c, N - 1, 5)
+            hs = 1e-7 * np.maximum(1.0, np.abs(x[cols]))
+            xp = x.copy()
+            xp[cols] += hs
+            dr = res(xp)[:N] - r0[:N]
+            for j, hj in zip(cols, hs):
+                for i in (j - 1, j, j + 1):
+                    if 0 <= i < N:
+                        J[i, j] = dr[i] / hj
+        J[N, 0] = 1.0
+        J[N, N - 1] = -1.0
+        J[N + 1, :N] = 2.0 * w * x[:N]
+        return J
+
+    x = x0
+    r = res(x)
+    nr = np.linalg.norm(r)
+    for _ in range(60):
+        if nr < 1e-10:
+            break
+        J = jac(x, r)
+        dx = np.linalg.solve(J, -r)
+        lam = 1.0
+        while lam > 1e-6:
+            xn = x + lam * dx
+            if xn[N] > 0.0 and np.all(xn[:N] > 0.0):
+                rn = res(xn)
+                if np.all(np.isfinite(rn)) and np.linalg.norm(rn) < nr:
+                    break
+            lam *= 0.5
+        else:
+            break
+        x, r, nr = xn, rn, np.linalg.norm(rn)
+    if not np.isfinite(nr) or nr > 1e-9 * max(1.0, (N / 801.0) ** 2):
+        raise RuntimeError(f"2D shape solver did not converge: |res| = {nr:.3e}")
+    g = x[:N]
+    return dict(phi=phi, g=g, delta=float(x[N]), k=float(x[N + 1]), ell=float(g[0]))
+
+
+def centroid_height_2d(phi, g):
+    """Height of the centroid of the region r <= g(phi) above the origin:
+    triangles of area g^2 dphi / 2 with centroids at (2/3) g cos(phi)."""
+    w = np.full_like(phi, phi[1] - phi[0])
+    w[0] *= 0.5
+    w[-1] *= 0.5
+    return float(np.sum(w * g ** 3 * np.cos(phi)) * (2.0 / 3.0) / np.sum(w * g ** 2))
+
+
+def radial_profile_about_2d(phi, g, z0, phis):
+    """Distance from the axis point at height z0 to the outline along polar
+    angles phis (from +z, in [0, pi])."""
+    pp = np.linspace(0.0, math.pi, 20001)
+    gg = np.interp(pp, phi, g)
+    x = gg * np.sin(pp)
+    z = gg * np.cos(pp) - z0
+    ang = np.arctan2(x, z)
+    dist = np.hypot(x, z)
+    order = np.argsort(ang)
+    return np.interp(phis, ang[order], dist[order])

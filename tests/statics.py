@@ -58,3 +58,27 @@ def l2_error(q, tris, theta, xi, nbins=90):
     err = math.sqrt(np.sum((Gs[sel] - Gt[sel]) ** 2) / np.sum(Gt[sel] ** 2))
     return dict(E_L2=err, R0=R0, theta_bar_theory=sh.angle_from_half_height(s["ell"]),
                 ell_theory=s["ell"] * R0, bins_filled=int(sel.sum()))
+
+
+def l2_error_2d(q, theta, xi, nbins=90):
+    """2D counterpart of eq. L2-error_equilibrium: node distances from the
+    polygon's area centroid, binned by the polar angle from +y folded onto
+    [0, pi], against the 2D App. B-type outline of the same area."""
+    x, y = q[:, 0], q[:, 1]
+    xn, yn = np.roll(x, -1), np.roll(y, -1)
+    cr = x * yn - xn * y
+    A = 0.5 * cr.sum()
+    cen = np.array([((x + xn) * cr).sum() / (6 * A), ((y + yn) * cr).sum() / (6 * A)])
+    R0 = math.sqrt(A / math.pi)
+    s = sh.solve_2d(theta, xi / R0)
+    d = q - cen[None, :]
+    G = np.linalg.norm(d, axis=1)
+    phi = np.arccos(np.clip(d[:, 1] / G, -1.0, 1.0))
+    k = np.minimum((phi / math.pi * nbins).astype(int), nbins - 1)
+    Gs = np.bincount(k, weights=G, minlength=nbins) / np.maximum(np.bincount(k, minlength=nbins), 1)
+    n = np.bincount(k, minlength=nbins)
+    phis = (np.arange(nbins) + 0.5) * math.pi / nbins
+    Gt = R0 * sh.radial_profile_about_2d(s["phi"], s["g"], sh.centroid_height_2d(s["phi"], s["g"]), phis)
+    sel = n > 0
+    err = math.sqrt(np.sum((Gs[sel] - Gt[sel]) ** 2) / np.sum(Gt[sel] ** 2))
+    return dict(E_L2=err, R0=R0, ell_theory=s["ell"] * R0, area=A)

@@ -9,6 +9,7 @@ import os
 import numpy as np
 import pytest
 
+import oracle as o
 from oracle import shape as sh
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -72,3 +73,33 @@ def test_without_the_wall_term_the_drop_is_a_sphere():
     r = residual(np.concatenate([np.ones_like(u), [0.1, 2.0]]), u, math.pi / 3, 0.1, wall=False)
     assert np.max(np.abs(r[:-1])) < 1e-14 and abs(r[-1]) < 1e-12
     assert np.max(np.abs(residual(x0, u, math.pi / 3, 0.1, wall=False))) > 1e-3
+
+
+def test_curvature_of_circles_2d():
+    phi = np.linspace(0.0, math.pi, 401)
+    d = phi[1] - phi[0]
+    g = np.ones_like(phi)
+    gd, gdd = sh.derivatives_2d(g, d)
+    assert np.allclose(sh.curvature_2d(g, gd, gdd), 1.0, atol=1e-14)
+    # a circle of radius c whose centre sits z0 below the origin: 1 / c
+    c, z0 = 1.3, 0.4
+    g = -z0 * np.cos(phi) + np.sqrt(c * c - z0 * z0 * np.sin(phi) ** 2)
+    gd, gdd = sh.derivatives_2d(g, d)
+    assert np.max(np.abs(sh.curvature_2d(g, gd, gdd) - 1.0 / c)) < 1e-5
+
+
+@pytest.mark.parametrize("theta", [math.pi / 4, math.pi / 2, 3 * math.pi / 4])
+def test_2d_solution_constraints_and_grid_convergence(theta):
+    a = sh.solve_2d(theta, 0.1, N=801)
+    b = sh.solve_2d(theta, 0.1, N=1601)
+    for s in (a, b):
+        g, phi = s["g"], s["phi"]
+        dphi = phi[1] - phi[0]
+        assert abs(g[0] - g[-1]) < 1e-10
+        assert abs(dphi * (np.sum(g ** 2) - 0.5 * (g[0] ** 2 + g[-1] ** 2)) - math.pi) < 1e-10
+        assert abs(s["delta"] - 0.1) < 0.01
+    assert abs(a["ell"] - b["ell"]) < 1e-3  # second-order convergence in the grid
+    # the outline's angle from the half-height sits near theta, closer for
+    # obtuse angles
+    t = o.angle_from_height_2d(b["ell"], math.pi)
+    assert abs(t - theta) < 0.2 * theta
