@@ -37,3 +37,26 @@ def test_equilibrium_shape_against_app_b(theta, xi_over_R0):
     assert d["status"] == 0 and d["max_normal_speed"] < 1e-5
     assert r["E_L2"] < bound
     assert abs(d["theta_meas"] - r["theta_bar_theory"]) < math.radians(1.5)
+
+
+@pytest.mark.parametrize("theta,xi_over_R0", [(45.0, 0.2), (90.0, 0.2), (135.0, 0.2), (135.0, 0.1)])
+def test_equilibrium_outline_2d(theta, xi_over_R0):
+    """2D counterpart: a circle of R0 = 20 (200 nodes) on the substrate of a
+    128x80 box, 40000 steps, against the planar outline of the same area
+    that balances curvature and the wall term (oracle/shape.py, solve_2d)."""
+    import oracle as o
+    W = wl.droplet_2d_statics(theta, xi_over_R0)
+    print(f"[statics2d] theta {theta} xi/R0 {xi_over_R0}", flush=True)
+    s = gpu_solver([W.params], [W.nodes])
+    s.step(40000)
+    q, _, _ = s.read_nodes(0)
+    d = s.diagnostics(0)
+    r = statics.l2_error_2d(q, math.radians(theta), W.params.xi)
+    tb = o.angle_from_height_2d(r["ell_theory"], r["area"])
+    print("[statics2d] " + json.dumps({"theta_eq_deg": theta, "xi_over_R0": xi_over_R0,
+                                       "E_L2": round(r["E_L2"], 5),
+                                       "theta_bar_sim_deg": round(math.degrees(d["theta_meas"]), 3),
+                                       "theta_bar_outline_deg": round(math.degrees(tb), 3)}), flush=True)
+    assert d["status"] == 0
+    assert r["E_L2"] < 1.5e-2
+    assert abs(d["theta_meas"] - tb) < math.radians(1.5)
