@@ -60,6 +60,21 @@ def l2_error(q, tris, theta, xi, nbins=90):
                 ell_theory=s["ell"] * R0, bins_filled=int(sel.sum()))
 
 
+def theory_2d(theta, eps):
+    """Planar outline, reached by the same continuation as theory(): from
+    theta = pi/2 at xi/R0 = 0.1 first in the angle, then in xi/R0."""
+    s = sh.solve_2d(math.pi / 2, 0.1)
+    th = math.pi / 2
+    while abs(th - theta) > 1e-12:
+        th = th + max(-math.pi / 16, min(math.pi / 16, theta - th))
+        s = sh.solve_2d(th, 0.1, guess=s)
+    e = 0.1
+    while abs(e - eps) > 1e-12:
+        e = e + max(-0.02, min(0.02, eps - e))
+        s = sh.solve_2d(theta, e, guess=s)
+    return s
+
+
 def l2_error_2d(q, theta, xi, nbins=90):
     """2D counterpart of eq. L2-error_equilibrium: node distances from the
     polygon's area centroid, binned by the polar angle from +y folded onto
@@ -70,7 +85,7 @@ def l2_error_2d(q, theta, xi, nbins=90):
     A = 0.5 * cr.sum()
     cen = np.array([((x + xn) * cr).sum() / (6 * A), ((y + yn) * cr).sum() / (6 * A)])
     R0 = math.sqrt(A / math.pi)
-    s = sh.solve_2d(theta, xi / R0)
+    s = theory_2d(theta, xi / R0)
     d = q - cen[None, :]
     G = np.linalg.norm(d, axis=1)
     phi = np.arccos(np.clip(d[:, 1] / G, -1.0, 1.0))

@@ -9,6 +9,7 @@ about 1e-3 as xi/R0 grows, largest for the acute angle, with its
 import json
 import math
 
+import numpy as np
 import pytest
 
 import workloads as wl
@@ -39,9 +40,10 @@ def test_equilibrium_shape_against_app_b(theta, xi_over_R0):
     assert abs(d["theta_meas"] - r["theta_bar_theory"]) < math.radians(1.5)
 
 
-@pytest.mark.parametrize("theta,xi_over_R0", [(45.0, 0.2), (90.0, 0.2), (135.0, 0.2), (135.0, 0.1)])
+@pytest.mark.parametrize("theta", [45.0, 90.0, 135.0])
+@pytest.mark.parametrize("xi_over_R0", [0.1, 0.2, 0.3])
 def test_equilibrium_outline_2d(theta, xi_over_R0):
-    """2D counterpart: a circle of R0 = 20 (200 nodes) on the substrate of a
+    """2D counterpart: a circle of R0 = 20 (800 nodes) on the substrate of a
     128x80 box, 40000 steps, against the planar outline of the same area
     that balances curvature and the wall term (oracle/shape.py, solve_2d)."""
     import oracle as o
@@ -53,10 +55,12 @@ def test_equilibrium_outline_2d(theta, xi_over_R0):
     d = s.diagnostics(0)
     r = statics.l2_error_2d(q, math.radians(theta), W.params.xi)
     tb = o.angle_from_height_2d(r["ell_theory"], r["area"])
+    gap = float(np.linalg.norm(np.roll(q, -1, 0) - q, axis=1).max())
     print("[statics2d] " + json.dumps({"theta_eq_deg": theta, "xi_over_R0": xi_over_R0,
-                                       "E_L2": round(r["E_L2"], 5),
+                                       "E_L2": round(r["E_L2"], 5), "max_gap": round(gap, 3),
                                        "theta_bar_sim_deg": round(math.degrees(d["theta_meas"]), 3),
                                        "theta_bar_outline_deg": round(math.degrees(tb), 3)}), flush=True)
     assert d["status"] == 0
-    assert r["E_L2"] < 1.5e-2
-    assert abs(d["theta_meas"] - tb) < math.radians(1.5)
+    assert gap < 1.0
+    assert r["E_L2"] < 1.0e-2
+    assert abs(d["theta_meas"] - tb) < math.radians(0.5)
