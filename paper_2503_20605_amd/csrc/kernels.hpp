@@ -1138,21 +1138,38 @@ __global__ __launch_bounds__(kNodeBlock) void k_ib_fused2(const DropDev* __restr
     const int j = gid / T, k = gid % T;
     if (j >= A.ntot) return;
     const int d = node_droplet<ONE>(A, j);
-    const DropDev& D = drops[d];
     const int st = A.stride;
+    // a lone droplet's ring is nodes 0 .. ntot - 1, so its positions are
+    // fetched alongside the droplet's parameters instead of after them
+    int jm = 0, jp = 0;
+    double q[3][3];
+    if constexpr (ONE) {
+        jm = j == 0 ? A.ntot - 1 : j - 1;
+        jp = j == A.ntot - 1 ? 0 : j + 1;
+        const int id[3] = {jm, j, jp};
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            q[m][0] = A.pos[id[m]];
+            q[m][1] = A.pos[st + id[m]];
+        }
+    }
+    const DropDev& D = drops[d];
     if (!D.active || D.force_mode != 0) {
         hold_position<2>(A, j, k);
         return;
     }
-    int jm, jp;
-    ring_2d(D, j, jm, jp);
-    const int id[3] = {jm, j, jp};
-    double q[3][3];
+    if constexpr (!ONE) {
+        ring_2d(D, j, jm, jp);
+        const int id[3] = {jm, j, jp};
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            q[m][0] = A.pos[id[m]];
+            q[m][1] = A.pos[st + id[m]];
+        }
+    }
     bool ok = true;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        q[m][0] = A.pos[id[m]];
-        q[m][1] = A.pos[st + id[m]];
         q[m][2] = 0.0;
         ok = ok && coord_ok(q[m][0]) && coord_ok(q[m][1]);
     }
