@@ -34,9 +34,11 @@ LB_NT = (0, 0, 0, 1, 1, 1) * 2 + (0, 1, 0, 1)
 LB_NTL = (0,) * 6 + (1,) * 6 + (0, 0, 1, 1)
 
 
-def lb_kernel_name(dim, storage, variant, vis=0):
+def lb_kernel_name(dim, storage, variant, vis=0, one=1):
+    """Name of the lattice kernel instance as the kernel trace prints it; one:
+    the form for a handle of a single droplet (used unless vis)."""
     return (f"k_lb<{dim}, {storage}, {LB_BX[variant]}, {LB_NT[variant]}, {LB_NTL[variant]}, "
-            f"{vis}>")
+            f"{vis}, {0 if vis else one}>")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lb_traffic.md")
 
 
@@ -475,9 +477,10 @@ def main():
         steps, warm = min(steps, 2000), min(warm, 200)
 
     # warm-up: pick the lattice-kernel variant (its steps are real steps of
-    # the run), then plain steps
+    # the run; enough of them to replay the step graph twice per timing),
+    # then plain steps
     if a.variant < 0:
-        variant, tune_ms = s.autotune(steps=64)
+        variant, tune_ms = s.autotune(steps=max(64, 2 * a.graph_steps + 2))
     else:
         variant, tune_ms = s.set_lb_variant(a.variant), None
     s.step(warm)
@@ -536,7 +539,7 @@ def main():
                      "achieved_over_exec_span": round(bpc * cells / (span_ms * 1e-3) / 1e9, 1),
                      "working_set_MB": round(bpc * cells / 1e6, 1)},
         "step_us_timed_pass": round(step_ms_timed * 1e3, 3),
-        "autotune_lb_ms": tune_ms,
+        "autotune_step_ms": tune_ms,
         "diag": {"mass": diag["mass"], "theta_meas_deg": math.degrees(diag["theta_meas"]),
                  "volume": diag["volume"]},
     }

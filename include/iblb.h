@@ -222,14 +222,17 @@ int iblb_run_to_rest(iblb_ctx *ctx, double tol, int check_every, int hold, long 
  * the variant in use. */
 int iblb_set_lb_variant(iblb_ctx *ctx, int variant, int *variant_out);
 
-/* Time every lattice-kernel variant over `steps` real time steps each (the
- * steps advance the simulation) and keep the fastest (the lowest-numbered
- * variant within 2% of the fastest, so that near-ties resolve the same way
- * from run to run).  With cache_path
- * non-NULL the winner is looked up in / appended to that text file, keyed
- * by device, lattice, storage and size bucket; a cache hit runs no step.
- * chosen (may be NULL) receives the variant; ms (may be NULL, 16 entries)
- * the measured lattice-kernel milliseconds per step (-1 on a cache hit). */
+/* Time every lattice-kernel variant on the handle's own coupled steps and
+ * keep the fastest (the lowest-numbered variant within 2% of the fastest,
+ * so that near-ties resolve the same way from run to run).  Each variant
+ * runs iblb_step(steps) twice: the first call builds its graphs, the second
+ * is timed between two events on the handle's stream (graphs are replayed
+ * only when steps >= graph steps + 2, as in any iblb_step call).  All these
+ * steps advance the simulation.  With cache_path non-NULL the winner is
+ * looked up in / appended to that text file, keyed by device, lattice,
+ * storage and size bucket; a cache hit runs no step.  chosen (may be NULL)
+ * receives the variant; ms (may be NULL, 16 entries) the measured
+ * milliseconds per coupled step of each variant (-1 on a cache hit). */
 int iblb_autotune(iblb_ctx *ctx, int steps, const char *cache_path, int *chosen, double *ms);
 
 /* Number of steps captured in one replayed graph (even, 2..1024); default

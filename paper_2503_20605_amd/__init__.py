@@ -197,8 +197,9 @@ class Solver:
         return out.value
 
     def autotune(self, steps=50, cache_path=None):
-        """Time the sixteen lattice-kernel variants and keep the fastest; returns
-        (variant, per-variant ms or -1 on a cache hit)."""
+        """Time the sixteen lattice-kernel variants on the handle's own coupled
+        steps and keep the fastest; returns (variant, per-variant ms per
+        coupled step, or -1 on a cache hit)."""
         out = ctypes.c_int()
         ms = (ctypes.c_double * 16)()
         cp = None if cache_path is None else str(cache_path).encode()

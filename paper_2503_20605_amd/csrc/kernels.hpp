@@ -217,7 +217,10 @@ __device__ __forceinline__ bool cell_inside(const DropDev& D, const int* __restr
 // droplet in storage order, whatever nx is, so rows that are not a multiple
 // of 64 cells long leave no lanes idle (a wavefront may then span two rows,
 // and the band flag and the row of the classification are read per lane).
-template <int DIM, int S, int BX, int NT, int NTL, int VIS>
+// ONE = 1 (a handle holding a single droplet) reads that droplet's
+// parameters without waiting for the block's tile entry, so the two loads
+// that open every wavefront are in flight together.
+template <int DIM, int S, int BX, int NT, int NTL, int VIS, int ONE>
 __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops,
                                                const int4* __restrict__ tiles,
                                                const typename Codec<S>::T* __restrict__ fsrc_all,
@@ -242,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
     unsigned long long* stamp = stamps ? stamps + (blockIdx.x % kStampSpread) * kStampStride : nullptr;
     if (stamp && threadIdx.x == 0) atomicMin(stamp, (unsigned long long)wall_clock64());
     const int4 tile = tiles[xcd_remap(blockIdx.x, gridDim.x)];
-    const DropDev& D = drops[tile.x];
+    const DropDev& D = drops[ONE ? 0 : tile.x];
     const int nx = D.nx, ny = D.ny, nz = D.nz;
     int x, y, z;
     if constexpr (FLAT) {
