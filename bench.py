@@ -275,8 +275,13 @@ def sweep(a):
     for run in range(10):
         W = wl.droplet_2d_large(run=run)
         p = W.params
+        # the variant is picked on a scratch copy of the run (tuning steps
+        # advance the simulation), over enough steps to replay the step graph
         s = Solver([params_from(p)], [W.nodes])
-        s.autotune(steps=16)
+        v, _ = s.autotune(steps=130)
+        s.close()
+        s = Solver([params_from(p)], [W.nodes])
+        s.set_lb_variant(v)
         import torch
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -286,7 +291,7 @@ def sweep(a):
         d = s.diagnostics(0)
         s.close()
         runs.append({"run": run, "tau": p.tau, "theta_eq_deg": p.theta_eq_deg,
-                     "theta0_deg": round(W.meta["theta0_deg"], 3), "steps": W.steps,
+                     "theta0_deg": round(W.meta["theta0_deg"], 3), "steps": W.steps, "lb_variant": v,
                      "wall_s": round(wall, 3),
                      "MLUPS": round(p.nx * p.ny * W.steps / wall / 1e6, 1),
                      "theta_meas_deg": round(math.degrees(d["theta_meas"]), 3),
