@@ -1182,14 +1182,29 @@ __global__ __launch_bounds__(kNodeBlock) void k_ib_fused2(const DropDev* __restr
         return;
     }
     const float* __restrict__ U = U_all + 2LL * D.c_off;
+    float w[3];
+    int cell[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        int row, ix;
+        cell[m] = lane_tap<2>(D, q[m], k, w[m], row, ix);
+    }
+    // all six gathers are issued before any is used (a conditional load per
+    // tap would wait for each in turn): a tap beyond a wall, where the fluid
+    // is at rest, reads cell 0 with weight zero
+    float u[3][2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const int c = cell[m] >= 0 ? cell[m] : 0;
+        u[m][0] = U[c];
+        u[m][1] = U[D.ncell + c];
+    }
     float acc[3][2];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        float w;
-        int row, ix;
-        const int cell = lane_tap<2>(D, q[m], k, w, row, ix);
-        acc[m][0] = cell >= 0 ? U[cell] * w : 0.f;
-        acc[m][1] = cell >= 0 ? U[D.ncell + cell] * w : 0.f;
+        const float wm = cell[m] >= 0 ? w[m] : 0.f;
+        acc[m][0] = u[m][0] * wm;
+        acc[m][1] = u[m][1] * wm;
     }
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
