@@ -1,7 +1,9 @@
 """Pins of the oracle's equilibrium-shape solver (App. B, eqs. YL, bc,
 volconstr; App. C): the curvature operator on shapes with known curvature,
 the solution's constraints, grid convergence, and the measured angle that
-App. C prints for theta_eq = pi/4, xi/R0 = 0.1."""
+App. C prints for theta_eq = pi/4, xi/R0 = 0.1; the planar outline's
+solver by circles, its constraints, grid convergence and the exact first
+integral of a plane curve whose curvature depends on the height alone."""
 import json
 import math
 import os
@@ -103,3 +105,47 @@ def test_2d_solution_constraints_and_grid_convergence(theta):
     # obtuse angles
     t = o.angle_from_height_2d(b["ell"], math.pi)
     assert abs(t - theta) < 0.2 * theta
+
+
+def _first_integral_gap(s, theta, eps, n=6, m=3):
+    """Largest violation, over the outline, of the first integral of the
+    planar equilibrium: along a plane curve whose curvature depends on the
+    height alone, kappa dh = sin(psi) dpsi with psi the tangent's angle to
+    the substrate (App. A: div n = dpsi/ds, sin psi = dh/ds), so with
+    kappa = dp R0 / sigma - Pi(h) R0 / sigma (the planar eq. laplace-pi)
+        1 - cos psi(h) = k (h - delta) - int_delta^h Pi R0 / sigma dh',
+    the integral taken in closed form from eq. (disjoin-p) and eq.
+    (A_choice); psi = 0 at the bottom of the outline, pi at its top."""
+    phi, g, d, k = s["phi"], s["g"], s["delta"], s["k"]
+    gd = np.gradient(g, phi[1] - phi[0], edge_order=2)
+    # tangent walking up the right half (phi decreasing): (-dx/dphi, -dz/dphi)
+    one_minus_cos = 1.0 + (gd * np.sin(phi) + g * np.cos(phi)) / np.sqrt(g * g + gd * gd)
+    h = g * np.cos(phi) + g[-1] + d
+    a = (m - 1) * (n - 1) * (1.0 + math.cos(theta)) / ((n - m) * eps)
+    integral = a * (eps ** n * (h ** (1 - n) - d ** (1 - n)) / (1 - n)
+                    - eps ** m * (h ** (1 - m) - d ** (1 - m)) / (1 - m))
+    return float(np.max(np.abs(one_minus_cos - (k * (h - d) - integral))))
+
+
+@pytest.mark.parametrize("theta_deg,eps", [(45, 0.1), (60, 0.15), (90, 0.2), (135, 0.3)])
+def test_2d_solution_satisfies_the_first_integral(theta_deg, eps):
+    import sys
+    sys.path.insert(0, HERE)
+    import statics
+    th = math.radians(theta_deg)
+    s = statics.theory_2d(th, eps)
+    # second-order finite differences on 801 points: 2.3e-3 at the sharpest
+    # profile (45 deg, 0.1), 2e-4 or less elsewhere; a 10% error in the wall
+    # strength leaves 0.1-0.15
+    assert _first_integral_gap(s, th, eps) < 5e-3
+
+
+def test_2d_first_integral_gap_falls_at_second_order():
+    import sys
+    sys.path.insert(0, HERE)
+    import statics
+    th, eps = math.pi / 4, 0.1
+    a = statics.theory_2d(th, eps)
+    b = sh.solve_2d(th, eps, N=1601, guess=a)
+    ga, gb = _first_integral_gap(a, th, eps), _first_integral_gap(b, th, eps)
+    assert 3.5 < ga / gb < 4.5, (ga, gb)
