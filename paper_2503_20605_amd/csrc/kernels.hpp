@@ -486,6 +486,37 @@ __device__ __forceinline__ void shear_force(double mu, const NodeArrays& A, int 
     }
 }
 
+// Contribution of triangle t (vertices P, node j in slot s) to node j: the
+// surface-tension force -sigma/2 n_t x (q_c - q_b) (the gradient of sigma
+// times the triangle's area), its unit normal and its area; plus the shear
+// part of an elastic interface.
+__device__ __forceinline__ void tri_contrib(const DropDev& D, const NodeArrays& A, int t, int s,
+                                            const double P[3][3], double fs[3], double ns[3],
+                                            double& chi) {
+    const double e1[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+    const double e2[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+    double nt[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                    e1[0] * e2[1] - e1[1] * e2[0]};
+    const double len = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+    nt[0] /= len;
+    nt[1] /= len;
+    nt[2] /= len;
+    const int sb = s == 2 ? 0 : s + 1, sc = s == 0 ? 2 : s - 1;
+    const double d[3] = {P[sc][0] - P[sb][0], P[sc][1] - P[sb][1], P[sc][2] - P[sb][2]};
+    fs[0] -= 0.5 * D.sigma * (nt[1] * d[2] - nt[2] * d[1]);
+    fs[1] -= 0.5 * D.sigma * (nt[2] * d[0] - nt[0] * d[2]);
+    fs[2] -= 0.5 * D.sigma * (nt[0] * d[1] - nt[1] * d[0]);
+    ns[0] += nt[0];
+    ns[1] += nt[1];
+    ns[2] += nt[2];
+    chi += 0.5 * len;
+    if (D.shear != 0.0) shear_force(D.shear, A, t, s, e1, e2, fs);
+}
+
+// Incident triangles of a vertex fetched in one batch (icosphere and cap
+// meshes have 5-6 per vertex; a vertex with more takes the plain loop).
+constexpr int kIncBatch = 8;
+
 // Geometry of vertex j of a closed 3D triangle mesh (CCW seen from
 // outside): surface-tension force -sigma d(area)/dq_j summed over the
 // incident triangles, vertex normal (mean of the incident unit normals),
@@ -500,7 +531,53 @@ __device__ __forceinline__ void node_geom_3d(const DropDev& D, const NodeArrays&
     fs[0] = fs[1] = fs[2] = 0.0;
     double ns[3] = {0.0, 0.0, 0.0};
     chi = 0.0;
-    for (int k = A.inc_beg[j]; k < A.inc_end[j]; ++k) {
+    const int beg = A.inc_beg[j], end = A.inc_end[j];
+    if (end > beg && end - beg <= kIncBatch) {
+        // the usual vertex (at most kIncBatch triangles): the incidence
+        // entries, then the triangles' vertex ids, then the positions of the
+        // two other vertices of each are each fetched in one batch, three
+        // round trips in all instead of three per triangle; out-of-range
+        // slots repeat the last entry and are not summed
+        const int cnt = end - beg;
+        int e[kIncBatch];
+#pragma unroll
+        for (int i = 0; i < kIncBatch; ++i) e[i] = A.inc[beg + (i < cnt ? i : cnt - 1)];
+        int vb[kIncBatch], vc[kIncBatch];
+#pragma unroll
+        for (int i = 0; i < kIncBatch; ++i) {
+            const int t = e[i] >> 2, s = e[i] & 3;
+            const int sb = s == 2 ? 0 : s + 1, sc = s == 0 ? 2 : s - 1;
+            vb[i] = A.tri[sb * ts + t];
+            vc[i] = A.tri[sc * ts + t];
+        }
+        double Pb[kIncBatch][3], Pc[kIncBatch][3];
+#pragma unroll
+        for (int i = 0; i < kIncBatch; ++i)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                Pb[i][a] = A.pos[a * st + vb[i]];
+                Pc[i][a] = A.pos[a * st + vc[i]];
+            }
+#pragma unroll
+        for (int i = 0; i < kIncBatch; ++i) {
+            if (i >= cnt) break;
+            const int t = e[i] >> 2, s = e[i] & 3;
+            const int sb = s == 2 ? 0 : s + 1;
+            // vertex slot s of triangle t is node j itself
+            double P[3][3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) P[m][a] = m == s ? q[a] : (m == sb ? Pb[i][a] : Pc[i][a]);
+            tri_contrib(D, A, t, s, P, fs, ns, chi);
+        }
+        const double nn = sqrt(ns[0] * ns[0] + ns[1] * ns[1] + ns[2] * ns[2]);
+        n[0] = ns[0] / nn;
+        n[1] = ns[1] / nn;
+        n[2] = ns[2] / nn;
+        return;
+    }
+    for (int k = beg; k < end; ++k) {
         const int e = A.inc[k];
         const int t = e >> 2, s = e & 3;
         const int v0 = A.tri[t], v1 = A.tri[ts + t], v2 = A.tri[2 * ts + t];
@@ -512,25 +589,7 @@ __device__ __forceinline__ void node_geom_3d(const DropDev& D, const NodeArrays&
             P[m][1] = A.pos[st + vv[m]];
             P[m][2] = A.pos[2 * st + vv[m]];
         }
-        const double e1[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
-        const double e2[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
-        double nt[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
-                        e1[0] * e2[1] - e1[1] * e2[0]};
-        const double len = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
-        nt[0] /= len;
-        nt[1] /= len;
-        nt[2] /= len;
-        const int sb = s == 2 ? 0 : s + 1, sc = s == 0 ? 2 : s - 1;
-        const double d[3] = {P[sc][0] - P[sb][0], P[sc][1] - P[sb][1], P[sc][2] - P[sb][2]};
-        // -sigma/2 n_t x (q_c - q_b)
-        fs[0] -= 0.5 * D.sigma * (nt[1] * d[2] - nt[2] * d[1]);
-        fs[1] -= 0.5 * D.sigma * (nt[2] * d[0] - nt[0] * d[2]);
-        fs[2] -= 0.5 * D.sigma * (nt[0] * d[1] - nt[1] * d[0]);
-        ns[0] += nt[0];
-        ns[1] += nt[1];
-        ns[2] += nt[2];
-        chi += 0.5 * len;
-        if (D.shear != 0.0) shear_force(D.shear, A, t, s, e1, e2, fs);
+        tri_contrib(D, A, t, s, P, fs, ns, chi);
     }
     const double nn = sqrt(ns[0] * ns[0] + ns[1] * ns[1] + ns[2] * ns[2]);
     n[0] = ns[0] / nn;
