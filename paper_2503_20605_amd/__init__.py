@@ -196,10 +196,12 @@ class Solver:
         self._chk(self.lib.iblb_set_lb_variant(self.ctx, int(variant), ctypes.byref(out)))
         return out.value
 
-    def autotune(self, steps=50, cache_path=None):
+    def autotune(self, steps=130, cache_path=None):
         """Time the sixteen lattice-kernel variants on the handle's own coupled
         steps and keep the fastest; returns (variant, per-variant ms per
-        coupled step, or -1 on a cache hit)."""
+        coupled step, or -1 on a cache hit).  The default runs the step graph
+        (64 steps unless set otherwise) twice per timing; every step taken
+        here advances the simulation."""
         out = ctypes.c_int()
         ms = (ctypes.c_double * 16)()
         cp = None if cache_path is None else str(cache_path).encode()
