@@ -1095,17 +1095,21 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restr
         const int j = A.perm[ch.y + t];
         bool ok = true;
         double q[3];
+        float ph[3];
+        // the force is fetched with the position, not after its check
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             q[a] = A.pos[a * st + j];
-            ok = ok && coord_ok(q[a]);
+            ph[a] = A.phi[a * st + j];
         }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ok = ok && coord_ok(q[a]);
         sok[t] = ok;
         if (ok) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 sq[t][a] = q[a];
-                sph[t][a] = A.phi[a * st + j];
+                sph[t][a] = ph[a];
                 const int b = (int)floor(q[a] - 0.5) - 1;
                 atomicMin(&lo[a], b);
                 atomicMax(&hi[a], b);
