@@ -277,6 +277,12 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         if (zp >= nz) zp = D.bcz ? -1 : 0;
     }
 
+    // the band flag of this cell's strip is requested before the
+    // populations: loads return in order, so waiting for the flag then does
+    // not wait for the populations, and a band wavefront's F loads overlap
+    // them instead of following them
+    const long long fi = D.flag_off + (long long)(z * ny + y) * D.nstrip + (x >> 6);
+    const int flag = D.force_mode == 1 ? 1 : (int)flags_all[fi];
     float f[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -301,11 +307,10 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         // band flags of this step (set by the spreading); those of the
         // other parity, read by the step before, are cleared for the
         // spreading of the next step by the first lane of each strip
-        const long long fi = D.flag_off + (long long)(z * ny + y) * D.nstrip + (x >> 6);
         if constexpr (FLAT)
-            forced = flags_all[fi] != 0;
+            forced = flag != 0;
         else  // every lane of a wavefront lies in the same strip
-            forced = __builtin_amdgcn_readfirstlane((int)flags_all[fi]) != 0;
+            forced = __builtin_amdgcn_readfirstlane(flag) != 0;
         if (flags_clr && (x & 63) == 0) flags_clr[fi] = 0;
     }
     if (forced) {
