@@ -542,8 +542,9 @@ void launch_after(const iblb_ctx* c, hipStream_t s, int p, bool last, int want_d
         hipLaunchKernelGGL((one ? k_interp_advect<2, true> : k_interp_advect<2, false>), grid, block, 0, s, D, A,
                            U, c->at<int>(c->L.status));
     else
-        hipLaunchKernelGGL((one ? k_interp_advect<3, true> : k_interp_advect<3, false>), grid, block, 0, s, D, A,
-                           U, c->at<int>(c->L.status));
+        hipLaunchKernelGGL((one ? k_interp_advect<3, true> : k_interp_advect<3, false>),
+                           dim3(ceil_div(c->L.ntot * InterpLanes<3>::n, kNodeBlock)), block, 0, s, D, A, U,
+                           c->at<int>(c->L.status));
     if (!last) launch_spread(c, s, p ^ 1, want_dropped);
 }
 

@@ -629,9 +629,18 @@ __device__ __forceinline__ int node_droplet(const NodeArrays& A, int j) {
 #endif
 constexpr int kNodeBlock = IBLB_NODE_BLOCK;
 
+
 template <int DIM>
 struct Taps {
     static constexpr int n = DIM == 2 ? 16 : 64;
+};
+
+// Lanes per node of the interpolation kernel: one per tap in 2D; in 3D two
+// taps per lane, so the 64 taps of a vertex take half a wavefront and a
+// batch of vertices half as many wavefronts.
+template <int DIM>
+struct InterpLanes {
+    static constexpr int n = DIM == 3 ? Taps<3>::n / 2 : Taps<2>::n;
 };
 
 // ---------------------------------------------------------------------------
@@ -983,9 +992,10 @@ __global__ __launch_bounds__(kNodeBlock) void k_interp_advect(const DropDev* __r
                                                           NodeArrays A,
                                                           const float* __restrict__ U_all,
                                                           int* __restrict__ status) {
-    constexpr int T = Taps<DIM>::n;
+    // G lanes per node, each taking T / G taps (k, k + G, ...)
+    constexpr int T = Taps<DIM>::n, G = InterpLanes<DIM>::n, R = T / G;
     const int gid = blockIdx.x * kNodeBlock + threadIdx.x;
-    const int j = gid / T, k = gid % T;
+    const int j = gid / G, k = gid % G;
     if (j >= A.ntot) return;
     const int d = node_droplet<ONE>(A, j);
     const DropDev& D = drops[d];
@@ -1006,17 +1016,32 @@ __global__ __launch_bounds__(kNodeBlock) void k_interp_advect(const DropDev* __r
         if (k == 0) atomicOr(status + d, 4);
         return;
     }
-    float w;
-    int row, ix;
-    const int cell = lane_tap<DIM>(D, q, k, w, row, ix);
-    float acc[3] = {0.f, 0.f, 0.f};
-    if (cell >= 0) {  // beyond a wall the fluid is at rest: no contribution
-        const float* __restrict__ U = U_all + (long long)DIM * D.c_off;
+    const float* __restrict__ U = U_all + (long long)DIM * D.c_off;
+    float w[R];
+    int cell[R];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) acc[a] = U[a * D.ncell + cell] * w;
+    for (int r = 0; r < R; ++r) {
+        int row, ix;
+        cell[r] = lane_tap<DIM>(D, q, k + r * G, w[r], row, ix);
+    }
+    // every gather is issued before any is used: a tap beyond a wall, where
+    // the fluid is at rest, reads cell 0 with weight zero
+    float u[R][3];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int c = cell[r] >= 0 ? cell[r] : 0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) u[r][a] = U[a * D.ncell + c];
+    }
+    float acc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const float wr = cell[r] >= 0 ? w[r] : 0.f;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) acc[a] += u[r][a] * wr;
     }
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) acc[a] = group_sum<T>(acc[a]);
+    for (int a = 0; a < DIM; ++a) acc[a] = group_sum<G>(acc[a]);
     if (k != 0) return;
     float sp = 0.f;
 #pragma unroll
