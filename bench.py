@@ -1,16 +1,21 @@
 """Benchmark of the coupled IB-LB step on one MI355X.
 
-Workload (default): a 1024x512 D2Q9 box, walls at y = 0 and y = 512,
-periodic x; one droplet of circle radius 120 with 1024 interface nodes,
-sigma = 0.005, xi = 3, tau = 0.6, theta_eq = 60 degrees, fp32 arithmetic and
-fp32 shifted storage.  A step is the whole coupled method: nodal forces,
+Workload (default): the 3D droplet, a 256x256x128 D3Q19 box (periodic x and
+y, walls at z = 0 and z = 128) holding a hemispherical cap of radius 40 meshed
+by a frequency-45 icosphere (20 252 vertices, 40 500 triangles), xi = 4,
+sigma = 0.005, tau = 0.8, theta_eq = 90 degrees, fp32 arithmetic and fp32
+shifted storage.  A step is the whole coupled method: nodal forces,
 spreading, fused stream + collide, interpolation, advection.  Inputs are
-resident in HBM before the timed region; steps replay a captured graph.
+resident in HBM before the timed region.
 
-Prints one JSON line: MLUPS of the whole step (value), the roofline of the
-dominant kernel (the fused lattice kernel, HBM bound, 72 algorithmic bytes
-per cell update in fp32) measured with HIP events around each of its
-launches, and the FP64 CPU oracle timed on a bounded sample.
+Prints one JSON line: MLUPS of the whole step over exactly --steps timed
+steps (value); the roofline of the dominant kernel (the fused lattice
+kernel, HBM bound, 152 algorithmic bytes per cell update in fp32) from the
+pair of HIP events that each of its launches in the timed region marks at
+dispatch; the same steps replayed from a captured graph for comparison;
+secondary lines (the 1024x512 D2Q9 step, the lattice kernel alone on boxes
+far above the last-level cache); and the FP64 CPU oracle timed on a bounded
+sample of the same workload, on one thread and on every thread.
 """
 from __future__ import annotations
 
@@ -87,24 +92,24 @@ def bytes_per_cell(dim, storage):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--run", type=int, default=1, help="sweep point 0..9 of the 1024x512 set")
     ap.add_argument("--graph-steps", type=int, default=64)
     ap.add_argument("--variant", type=int, default=-1,
                     help="lattice-kernel variant 0..15; -1 autotunes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--cpu-steps", type=int, default=60)
-    ap.add_argument("--extra", action="store_true",
-                    help="also time the lattice kernel on working sets far above the LLC")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the secondary lines (1024x512 D2Q9 step, lattice kernel alone on "
+                         "working sets far above the last-level cache)")
     ap.add_argument("--profile-only", action="store_true",
                     help="short run for profilers: no CPU leg, no extra sizes")
     ap.add_argument("--tte", action="store_true",
                     help="time to equilibrium of the 256-droplet batch instead of the step rate")
     ap.add_argument("--droplets", type=int, default=256)
     ap.add_argument("--max-steps", type=int, default=200000)
-    ap.add_argument("--workload", default="d2q9", choices=["d2q9", "d3q19", "d3q19_spreading"])
+    ap.add_argument("--workload", default="d3q19", choices=["d3q19", "d2q9", "d3q19_spreading"])
     ap.add_argument("--lam", type=float, default=None,
                     help="viscosity ratio mu_in / mu_out (default: the workload's own)")
     ap.add_argument("--mlp", action="store_true",
@@ -404,28 +409,83 @@ def mlp_rate(a):
 
 def lb_only_rate(dim, nx, ny, nz, storage, steps):
     """Lattice kernel on a big box with no interface (every cell is a plain
-    collide + stream), autotuned: GB/s of one launch."""
+    collide + stream), autotuned; its per-launch duration from the events its
+    dispatch marks, over `steps` timed steps."""
     from paper_2503_20605_amd import Solver, make_params
     p = make_params(dim=dim, nx=nx, ny=ny, nz=nz, tau=0.8, wetting=False)
     s = Solver([p], None, storage=storage)
     v, _ = s.autotune(steps=16)
     s.set_timing(True)
     s.step(steps + 1)
-    span_ms, _ = s.last_timing()
+    lb_ms, _ = s.last_timing()
     s.set_timing(False)
-    lb_ms = s.time_lattice(min(256, 2 * (steps // 2)))
     cells = nx * ny * nz
     gbs = bytes_per_cell(dim, storage) * cells / (lb_ms * 1e-3) / 1e9
     s.close()
     return {"lattice": f"{'D2Q9' if dim == 2 else 'D3Q19'} {nx}x{ny}" + (f"x{nz}" if dim == 3 else ""),
             "storage": ["f32", "f16", "bf16"][storage], "variant": v,
             "working_set_MB": round(bytes_per_cell(dim, storage) * cells / 1e6, 1),
-            "lb_us": round(lb_ms * 1e3, 2), "lb_exec_span_us": round(span_ms * 1e3, 2),
+            "lb_us": round(lb_ms * 1e3, 2),
             "MLUPS": round(cells / (lb_ms * 1e-3) / 1e6, 1),
             "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(lb_kernel_name(dim, storage, v),
                                         f"d{dim}q{9 if dim == 2 else 19}_{nx}x{ny}"
                                         + (f"x{nz}" if dim == 3 else "") + "_lattice_only")}
+
+
+def log(msg):
+    """Progress line on stderr (the JSON result alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(W, steps_one, steps_all):
+    """The FP64 oracle on the same workload, on the host: `steps_one`
+    coupled steps on one thread and `steps_all` on every thread OpenMP is
+    given (the lattice update shares rows among threads).  The set-up of the
+    oracle's arrays (a zero-step run) is timed separately and left out."""
+    import oracle as o
+    p = W.params
+    cells = p.nx * p.ny * (p.nz if p.dim == 3 else 1)
+
+    def timed(n):
+        t0 = time.perf_counter()
+        r = o.run(p, W.nodes, n, tris=W.tris)
+        dt = time.perf_counter() - t0
+        assert r["status"] == 0
+        return dt
+
+    default_threads = o.threads(0)
+    all_threads = int(os.environ.get("OMP_NUM_THREADS") or 0) or default_threads
+    o.threads(1)
+    setup1 = timed(0)
+    t1 = timed(steps_one) - setup1
+    used = o.threads(all_threads)
+    setupn = timed(0)
+    tn = timed(steps_all) - setupn
+    o.threads(default_threads)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {
+        "value": round(cells * steps_all / tn / 1e6, 3), "unit": "MLUPS", "cores": used,
+        "kind": "oracle",
+        "sample": f"{steps_all} coupled steps of the same {W.name} workload, FP64 oracle on {used} "
+                  f"threads ({tn:.1f} s after {setupn:.1f} s of array set-up)",
+        "single_thread": {"value": round(cells * steps_one / t1 / 1e6, 3), "unit": "MLUPS",
+                          "cores": 1,
+                          "sample": f"{steps_one} coupled steps, 1 thread ({t1:.1f} s)"},
+        "nproc": os.cpu_count(), "cpus_available": affinity, "cpu_model": cpu_model()}
 
 
 def main():
@@ -460,12 +520,7 @@ def main():
         print(json.dumps(res), flush=True)
         return
     storage = STORAGE[a.storage]
-    if a.workload == "d3q19":
-        W = wl.droplet_3d(theta_eq_deg=90.0, small=False)
-    elif a.workload == "d3q19_spreading":
-        W = wl.droplet_3d_spreading(lam=10.0 if a.lam is None else a.lam)
-    else:
-        W = wl.droplet_2d_large(run=a.run)
+    W = workload_of(a.workload, a.run)
     if a.lam is not None and a.lam != W.params.lam:
         W.params.lam = a.lam
         W.name += f"_lam{a.lam:g}"
@@ -473,42 +528,52 @@ def main():
     lam = float(p.lam)
     dim = p.dim
     cells = p.nx * p.ny * (p.nz if dim == 3 else 1)
+    log(f"workload {W.name}, storage {a.storage}, {steps_arg(a)}")
     s = Solver([params_from(p)], [W.nodes], None if W.tris is None else [W.tris], storage=storage)
     if lam != 1.0:
         s.set_viscosity_ratio(0, lam)
     s.set_graph_steps(a.graph_steps)
     steps, warm = a.steps, a.warmup
     if a.profile_only:
-        steps, warm = min(steps, 2000), min(warm, 200)
+        steps, warm = min(steps, 200), min(warm, 20)
 
-    # warm-up: pick the lattice-kernel variant (its steps are real steps of
-    # the run; enough of them to replay the step graph twice per timing),
-    # then plain steps
+    # untimed: pick the lattice-kernel variant (its steps are real steps of
+    # the run, enough of them to replay the step graph twice per timing),
+    # then the warm-up steps
     if a.variant < 0:
-        variant, tune_ms = s.autotune(steps=max(64, 2 * a.graph_steps + 2))
+        variant, tune_ms = s.autotune(steps=2 * a.graph_steps + 2)
+        tune_steps = 16 * 2 * (2 * a.graph_steps + 2)
     else:
-        variant, tune_ms = s.set_lb_variant(a.variant), None
+        variant, tune_ms, tune_steps = s.set_lb_variant(a.variant), None, 0
     s.step(warm)
+    torch.cuda.synchronize()
+    log(f"variant {variant}; timing {steps} steps")
+
+    # timed region: exactly `steps` coupled steps, each lattice launch timed
+    # by the pair of HIP events its own dispatch marks (direct launches, on
+    # the library's stream)
+    s.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.step(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    lb_ms, step_ms_events = s.last_timing()
+    s.set_timing(False)
     ms_per_step = wall / steps * 1e3
     mlups = cells * steps / wall / 1e6
 
-    # dominant kernel, two ways: (1) execution span stamped by the kernel
-    # itself on the device clock during further coupled steps of the same
-    # schedule; (2) per-launch time with dispatch, from events around a
-    # graph of 256 back-to-back lattice launches on the same lattice (run
-    # last: it advances the populations without the node work)
-    s.set_timing(True)
-    nt = min(steps, 4096)
-    s.step(nt + 1)
-    span_ms, step_ms_timed = s.last_timing()
-    s.set_timing(False)
+    # the same steps replayed from captured graphs (no events), for
+    # comparison: a graph of min(steps - 2, graph steps) steps (even)
+    g = max(2, min(a.graph_steps, (steps - 2) // 2 * 2))
+    s.set_graph_steps(g)
+    s.step(g + 2)  # builds the graph of the current parity
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(g + 2)
+    torch.cuda.synchronize()
+    wall_g = time.perf_counter() - t0
     diag = s.diagnostics(0)
-    lb_ms = s.time_lattice(256)
     bpc = bytes_per_cell(dim, storage)
     achieved = bpc * cells / (lb_ms * 1e-3) / 1e9
     lb_name = lb_kernel_name(dim, storage, variant, vis=int(lam != 1.0))
@@ -530,48 +595,97 @@ def main():
         "config": {"workload": W.name,
                    "lattice": (f"D2Q9 {p.nx}x{p.ny}" if dim == 2
                                else f"D3Q19 {p.nx}x{p.ny}x{p.nz}"),
-                   "nodes": len(W.nodes), "viscosity_ratio": lam,
+                   "nodes": len(W.nodes),
+                   "triangles": None if W.tris is None else len(W.tris),
+                   "viscosity_ratio": lam,
                    "tau": p.tau, "theta_eq_deg": p.theta_eq_deg, "sigma": p.sigma, "xi": p.xi,
-                   "storage": a.storage, "graph_steps": a.graph_steps,
-                   "lb_variant": variant},
+                   "storage": a.storage, "lb_variant": variant},
         "roofline": {"kernel": lb_name + " (fused pull-stream + BGK + Guo)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "bytes_per_cell": bpc, "cells_per_launch": cells,
                      "lb_us_per_launch": round(lb_ms * 1e3, 3),
-                     "lb_exec_span_us": round(span_ms * 1e3, 3),
-                     "achieved_over_exec_span": round(bpc * cells / (span_ms * 1e-3) / 1e9, 1),
+                     "timed_launches": steps - 1,
                      "working_set_MB": round(bpc * cells / 1e6, 1)},
-        "step_us_timed_pass": round(step_ms_timed * 1e3, 3),
+        "step_us_events": round(step_ms_events * 1e3, 3),
+        "graph_replay": {"steps": g + 2, "graph_steps": g,
+                         "ms_per_step": round(wall_g / (g + 2) * 1e3, 5),
+                         "MLUPS": round(cells * (g + 2) / wall_g / 1e6, 1)},
+        "untimed_steps_before": tune_steps + warm,
         "autotune_step_ms": tune_ms,
         "diag": {"mass": diag["mass"], "theta_meas_deg": math.degrees(diag["theta_meas"]),
                  "volume": diag["volume"]},
     }
     s.close()
 
+    log(f"{out['value']} MLUPS, lattice kernel {out['roofline']['lb_us_per_launch']} us "
+        f"({out['roofline']['frac']} of peak)")
     if not a.profile_only:
         from paper_2503_20605_amd import probe_copy_bandwidth
         out["copy_probe_GBs"] = round(probe_copy_bandwidth(1 << 30, 20), 1)
-    if a.extra and not a.profile_only:
-        out["lb_hbm"] = [lb_only_rate(2, 8192, 4096, 1, 0, 200),
-                         lb_only_rate(2, 8192, 4096, 1, 1, 200),
-                         lb_only_rate(3, 256, 256, 128, 0, 100),
-                         lb_only_rate(3, 256, 256, 128, 1, 100)]
-
-    if not a.no_cpu and not a.profile_only and dim == 2:
-        import oracle as o
-        import numpy as np
-        t0 = time.perf_counter()
-        r = o.run(p, W.nodes, a.cpu_steps)
-        cpu = time.perf_counter() - t0
-        assert r["status"] == 0
-        out["cpu_baseline"] = {
-            "value": round(cells * a.cpu_steps / cpu / 1e6, 3), "unit": "MLUPS",
-            "cores": 1, "kind": "oracle",
-            "sample": f"{a.cpu_steps} coupled steps of the same 1024x512 workload, FP64, "
-                      f"single thread ({cpu:.1f} s)"}
+        if not a.no_extra:
+            log("secondary lines")
+            out["extra"] = extra_workloads(a)
+    if not a.no_cpu and not a.profile_only:
+        log("CPU oracle baseline")
+        n1, nn = (1, 4) if dim == 3 else (20, 200)
+        out["cpu_baseline"] = cpu_baseline(W, n1, nn)
     print(json.dumps(out), flush=True)
+
+
+def steps_arg(a):
+    return f"--steps {a.steps} --warmup {a.warmup}"
+
+
+def workload_of(name, run=1):
+    import workloads as wl
+    if name == "d3q19":
+        return wl.droplet_3d(theta_eq_deg=90.0, small=False)
+    if name == "d3q19_spreading":
+        return wl.droplet_3d_spreading(lam=10.0)
+    return wl.droplet_2d_large(run=run)
+
+
+def extra_workloads(a):
+    """Secondary lines: the 1024x512 D2Q9 coupled step (its two population
+    copies, 38 MB, fit the 256 MB last-level cache, so its GB/s is an
+    effective figure) and the lattice kernel alone on boxes far above that
+    cache in fp32 and fp16 storage."""
+    import torch
+    from paper_2503_20605_amd import Solver, params_from
+    W = workload_of("d2q9", a.run)
+    p = W.params
+    s = Solver([params_from(p)], [W.nodes])
+    v, _ = s.autotune(steps=130)
+    s.step(200)
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(2000)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lb_ms, _ = s.last_timing()
+    s.set_timing(False)
+    s.set_graph_steps(64)
+    s.step(2000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(2000)
+    torch.cuda.synchronize()
+    wall_g = time.perf_counter() - t0
+    s.close()
+    cells = p.nx * p.ny
+    d2 = {"workload": W.name, "lb_variant": v, "steps": 2000,
+          "MLUPS": round(cells * 2000 / wall / 1e6, 1),
+          "MLUPS_graph_replay": round(cells * 2000 / wall_g / 1e6, 1),
+          "lb_us": round(lb_ms * 1e3, 3),
+          "effective_GBs": round(72 * cells / (lb_ms * 1e-3) / 1e9, 1)}
+    return {"d2q9_1024x512_coupled": d2,
+            "lb_hbm": [lb_only_rate(2, 8192, 4096, 1, 0, 200),
+                       lb_only_rate(2, 8192, 4096, 1, 1, 200),
+                       lb_only_rate(3, 256, 256, 128, 0, 100),
+                       lb_only_rate(3, 256, 256, 128, 1, 100)]}
 
 
 if __name__ == "__main__":

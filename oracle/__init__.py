@@ -58,6 +58,8 @@ def _load():
     lib.orc_forces_3d.argtypes = [c_int, D, c_int, I, c_double, c_double, c_double,
                                   c_int, c_int, c_int, D, D]
     lib.orc_inside.argtypes = [c_int, c_int, c_int, c_int, I, c_int, D, c_int, I, D, I]
+    lib.orc_threads.argtypes = [c_int]
+    lib.orc_threads.restype = c_int
     lib.orc_inside_cells.argtypes = [c_int, c_int, c_int, c_int, I, c_int, D, c_int, I, D,
                                      ctypes.c_long, ctypes.POINTER(ctypes.c_long), I]
     lib.orc_forces_3d_elastic.argtypes = [c_int, D, D, c_int, I, c_double, c_double, c_double,
@@ -92,6 +94,12 @@ def _bc(bc):
 # --------------------------------------------------------------------------
 # lattice and collision pieces
 # --------------------------------------------------------------------------
+
+def threads(n: int = 0) -> int:
+    """Threads of the lattice update (OpenMP over rows); n > 0 sets the
+    count.  Returns the count in force."""
+    return int(_load().orc_threads(int(n)))
+
 
 def lattice(dim: int):
     """Velocity set of Table I (D3Q19) or its 2D analogue D2Q9."""

@@ -45,6 +45,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_PERIODIC 0
 #define ORC_WALL 1
@@ -151,10 +154,13 @@ void orc_lb_step(int dim, int nx, int ny, int nz, const int *bc, double tau,
     const int Q = nq(dim);
     const long ncell = (long)nx * ny * nz;
     const int n[3] = {nx, ny, nz};
-    double f[19], feq[19], S[19];
+    /* cells are independent: the rows may be shared among threads without
+       changing any result */
+#pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
+                double f[19], feq[19], S[19];
                 const long cell = ((long)z * ny + y) * nx + x;
                 const int pos[3] = {x, y, z};
                 for (int i = 0; i < Q; ++i) {
@@ -690,4 +696,17 @@ int orc_run(int dim, int nx, int ny, int nz, const int *bc, double tau, double t
     free(tau_cell);
     free(inside);
     return status;
+}
+
+/* Threads used by the lattice update (OpenMP over rows; 1 without OpenMP).
+ * n <= 0 leaves the count unchanged.  Returns the count in force. */
+int orc_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

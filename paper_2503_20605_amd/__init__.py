@@ -250,8 +250,8 @@ class Solver:
         self._chk(self.lib.iblb_set_timing(self.ctx, int(bool(on))))
 
     def last_timing(self):
-        """(lattice-kernel execution span, whole step), milliseconds,
-        averaged over the last timed step() call."""
+        """(lattice-kernel duration from events marked by its dispatch, whole
+        step), milliseconds, averaged over the last timed step() call."""
         a, b = ctypes.c_double(), ctypes.c_double()
         self._chk(self.lib.iblb_last_timing(self.ctx, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <tuple>
 #include <vector>
 
 // the ABI entry points are the only exported symbols
@@ -41,7 +42,7 @@ constexpr int kShapeBY[kShapes] = {1, 2, 4, 0};
 int shape_of(int variant) { return variant < 12 ? variant % 3 : 3; }
 constexpr size_t kAlign = 256;
 constexpr int kMaxGraphSteps = 1024;
-constexpr int kTimedLaunches = 256;  // timed lattice launches per replay at most
+constexpr int kTimedChunk = 256;  // timed lattice launches between two reads of their events
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
@@ -49,7 +50,7 @@ int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 struct Layout {
     // byte offsets into the workspace
     size_t drops, tiles_lb, tiles_all, f0, f1, F, U, Fout, rho, flags, pos0, pos1, phi, qdot, dropped,
-        node_drop, tri, inc, inc_beg, inc_end, perm, chunks, status, partials, diag, stamps, stamps_out,
+        node_drop, tri, inc, inc_beg, inc_end, perm, chunks, status, partials, diag,
         xcnt0, xcnt1, xpos0, xpos1, tref, total;
     int nchunks;           // capacity of the 3D spreading chunk table
     long long cells;       // sum of cells
@@ -210,8 +211,6 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.status = take(sizeof(int) * n);
     L.partials = take(sizeof(double) * 8 * L.max_tiles);
     L.diag = take(sizeof(DiagDev) * n);
-    L.stamps = take(sizeof(unsigned long long) * (size_t)kStampWords * kTimedLaunches);
-    L.stamps_out = take(sizeof(unsigned long long) * 2 * kTimedLaunches);
     // interface crossings of the lattice rows, one table pair per step parity
     L.xcnt0 = take(sizeof(int) * L.rows);
     L.xcnt1 = take(sizeof(int) * L.rows);
@@ -239,14 +238,11 @@ struct iblb_ctx {
     std::vector<int4> tiles_h;
     int graph_steps = 64;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
-    hipGraphExec_t texec[2] = {nullptr, nullptr};  // same steps, lattice launches stamped
     hipGraphExec_t lexec = nullptr;                // lattice-only launches (time_lattice)
     int lexec_n = 0, lexec_p = 0;                  // its launch count and start parity
     bool timing = false;
     double t_lb = 0.0, t_step = 0.0;
-    std::vector<hipEvent_t> events;
-    std::vector<unsigned long long> stamps_h;
-    double clock_khz = 0.0;  // rate of wall_clock64() on the device
+    std::vector<hipEvent_t> events;  // [0, 2): around a whole call; then pairs per timed lattice launch
     long long step = 0;
     std::vector<int> status_h;
     std::vector<std::vector<int4>> chunks_h;  // 3D spreading chunks per droplet
@@ -349,10 +345,6 @@ void drop_graphs(iblb_ctx* c) {
             (void)hipGraphExecDestroy(c->exec[k]);
             c->exec[k] = nullptr;
         }
-        if (c->texec[k]) {
-            (void)hipGraphExecDestroy(c->texec[k]);
-            c->texec[k] = nullptr;
-        }
     }
     if (c->lexec) {
         (void)hipGraphExecDestroy(c->lexec);
@@ -429,19 +421,28 @@ int rebuild_tiles(iblb_ctx* c) {
 // ---- kernel dispatch -------------------------------------------------------
 
 template <int DIM, int S, int VIS, int ONE>
-void launch_lb_v(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned long long* stamps,
+void launch_lb_v(const iblb_ctx* c, hipStream_t s, int src, int full, const hipEvent_t* ev,
                  bool clear) {
     using T = typename Codec<S>::T;
     T* f[2] = {c->at<T>(c->L.f0), c->at<T>(c->L.f1)};
     const dim3 grid(c->ntiles_lb), block(kBlock);
+    // ev (timing only, never under graph capture): a pair of events that
+    // the dispatch itself marks at the kernel's start and end
     auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, grid, block, 0, s, c->at<DropDev>(c->L.drops),
-                           c->at<int4>(c->L.tiles_lb), (const T*)f[src], f[src ^ 1],
-                           c->at<float>(c->L.F), c->at<float>(c->L.U), c->at<float>(c->L.rho),
-                           c->at<float>(c->L.Fout), (const uint8_t*)band_flags(c, src),
-                           clear ? band_flags(c, src ^ 1) : nullptr, full, stamps,
-                           (const int*)cross_count(c, src), (const double*)cross_x(c, src),
-                           clear ? cross_count(c, src ^ 1) : nullptr);
+        auto args = std::make_tuple(
+            c->at<DropDev>(c->L.drops), c->at<int4>(c->L.tiles_lb), (const T*)f[src], f[src ^ 1],
+            c->at<float>(c->L.F), c->at<float>(c->L.U), c->at<float>(c->L.rho), c->at<float>(c->L.Fout),
+            (const uint8_t*)band_flags(c, src), clear ? band_flags(c, src ^ 1) : nullptr, full,
+            (const int*)cross_count(c, src), (const double*)cross_x(c, src),
+            clear ? cross_count(c, src ^ 1) : nullptr);
+        std::apply(
+            [&](auto... a) {
+                if (ev)
+                    hipExtLaunchKernelGGL(kern, grid, block, 0, s, ev[0], ev[1], 0, a...);
+                else
+                    hipLaunchKernelGGL(kern, grid, block, 0, s, a...);
+            },
+            args);
     };
     switch (c->variant) {
         case 0: go(k_lb<DIM, S, 256, 0, 0, VIS, ONE>); break;
@@ -467,34 +468,34 @@ void launch_lb_v(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned l
 // needs it (graphs are dropped when that changes); a handle of one droplet
 // uses the form whose tiles all belong to droplet 0.
 template <int DIM, int S>
-void launch_lb_t(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned long long* stamps,
+void launch_lb_t(const iblb_ctx* c, hipStream_t s, int src, int full, const hipEvent_t* ev,
                  bool clear) {
     if (c->any_visc)
-        launch_lb_v<DIM, S, 1, 0>(c, s, src, full, stamps, clear);
+        launch_lb_v<DIM, S, 1, 0>(c, s, src, full, ev, clear);
     else if (c->n == 1)
-        launch_lb_v<DIM, S, 0, 1>(c, s, src, full, stamps, clear);
+        launch_lb_v<DIM, S, 0, 1>(c, s, src, full, ev, clear);
     else
-        launch_lb_v<DIM, S, 0, 0>(c, s, src, full, stamps, clear);
+        launch_lb_v<DIM, S, 0, 0>(c, s, src, full, ev, clear);
 }
 
 template <int DIM>
-void launch_lb_d(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned long long* stamps,
+void launch_lb_d(const iblb_ctx* c, hipStream_t s, int src, int full, const hipEvent_t* ev,
                  bool clear) {
     switch (c->storage) {
-        case ST_F32: launch_lb_t<DIM, ST_F32>(c, s, src, full, stamps, clear); break;
-        case ST_F16: launch_lb_t<DIM, ST_F16>(c, s, src, full, stamps, clear); break;
-        default: launch_lb_t<DIM, ST_BF16>(c, s, src, full, stamps, clear); break;
+        case ST_F32: launch_lb_t<DIM, ST_F32>(c, s, src, full, ev, clear); break;
+        case ST_F16: launch_lb_t<DIM, ST_F16>(c, s, src, full, ev, clear); break;
+        default: launch_lb_t<DIM, ST_BF16>(c, s, src, full, ev, clear); break;
     }
 }
 
 // Lattice update of parity src.  With two viscosities the kernel reads the
 // crossing tables of parity src and, with clear, empties those of the other
 // parity for the next step's crossings.
-void launch_lb(const iblb_ctx* c, hipStream_t s, int src, int full, unsigned long long* stamps,
+void launch_lb(const iblb_ctx* c, hipStream_t s, int src, int full, const hipEvent_t* ev,
                bool clear = true) {
     if (c->ntiles_lb == 0) return;
-    if (c->dim == 2) launch_lb_d<2>(c, s, src, full, stamps, clear);
-    else launch_lb_d<3>(c, s, src, full, stamps, clear);
+    if (c->dim == 2) launch_lb_d<2>(c, s, src, full, ev, clear);
+    else launch_lb_d<3>(c, s, src, full, ev, clear);
 }
 
 // Forces at the positions of parity p, spread for the step of parity p.
@@ -549,11 +550,11 @@ void launch_after(const iblb_ctx* c, hipStream_t s, int p, bool last, int want_d
 }
 
 // One time step of parity p, its forces already spread: lattice update,
-// then the node work (see launch_after).  stamps (may be null) is the
-// timing slot set of the lattice launch.
+// then the node work (see launch_after).  ev (may be null) is the event
+// pair that times the lattice launch.
 void launch_step(const iblb_ctx* c, hipStream_t s, int p, bool last, int full, int want_dropped,
-                 unsigned long long* stamps = nullptr) {
-    launch_lb(c, s, p, full, stamps);
+                 const hipEvent_t* ev = nullptr) {
+    launch_lb(c, s, p, full, ev);
     launch_after(c, s, p, last, want_dropped);
 }
 
@@ -567,17 +568,15 @@ int ensure_events(iblb_ctx* c, int need) {
 }
 
 // Graph of graph_steps steps starting from buffer `parity` (none of them
-// the last step of a call); with `timed` the lattice launch of step k uses
-// timing slot set k (timed graphs hold at most kTimedLaunches steps).
-int ensure_graph(iblb_ctx* c, int parity, bool timed = false) {
-    hipGraphExec_t* slot = timed ? &c->texec[parity] : &c->exec[parity];
+// the last step of a call).
+int ensure_graph(iblb_ctx* c, int parity) {
+    hipGraphExec_t* slot = &c->exec[parity];
     if (*slot) return IBLB_OK;
-    unsigned long long* st = c->at<unsigned long long>(c->L.stamps);
     hipGraph_t g = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     int src = parity;
     for (int k = 0; k < c->graph_steps; ++k) {
-        launch_step(c, c->cap_stream, src, false, 0, 0, timed ? st + (size_t)k * kStampWords : nullptr);
+        launch_step(c, c->cap_stream, src, false, 0, 0);
         src ^= 1;
     }
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
@@ -591,31 +590,16 @@ int ensure_graph(iblb_ctx* c, int parity, bool timed = false) {
     return IBLB_OK;
 }
 
-// Reset the timing slot sets [first, first + n) before a timed sequence
-// (a fill kernel on the stream, never inside a graph).
-int reset_stamps(iblb_ctx* c, int first, int n) {
-    unsigned long long* st = c->at<unsigned long long>(c->L.stamps) + (size_t)first * kStampWords;
-    hipLaunchKernelGGL(k_stamps_reset, dim3(ceil_div((long long)n * kStampSpread, kBlock)), dim3(kBlock),
-                       0, c->stream, st, n);
-    HIPCHK(c, hipGetLastError());
-    return IBLB_OK;
-}
-
-// Sum over slot sets [first, first + n) of (latest end - earliest start),
-// in milliseconds.  Synchronises the stream.
-int read_stamps(iblb_ctx* c, int first, int n, double& ms) {
-    unsigned long long* st = c->at<unsigned long long>(c->L.stamps) + (size_t)first * kStampWords;
-    unsigned long long* out = c->at<unsigned long long>(c->L.stamps_out);
-    hipLaunchKernelGGL(k_stamps_fold, dim3(n), dim3(kStampSpread), 0, c->stream, (const unsigned long long*)st,
-                       out);
-    HIPCHK(c, hipGetLastError());
-    c->stamps_h.resize(2 * n);
-    HIPCHK(c, hipMemcpyAsync(c->stamps_h.data(), out, sizeof(unsigned long long) * 2 * n,
-                             hipMemcpyDeviceToHost, c->stream));
+// Sum of the elapsed times (ms) of the first n event pairs that timed
+// lattice launches (events 2 + 2k, 3 + 2k).  Synchronises the stream.
+int read_lb_events(iblb_ctx* c, int n, double& ms) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     ms = 0.0;
-    for (int k = 0; k < n; ++k)
-        ms += (double)(c->stamps_h[2 * k + 1] - c->stamps_h[2 * k]) / c->clock_khz;
+    for (int k = 0; k < n; ++k) {
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, c->events[2 + 2 * k], c->events[3 + 2 * k]));
+        ms += (double)t;
+    }
     return IBLB_OK;
 }
 
@@ -815,14 +799,6 @@ int iblb_create(int n, const iblb_params* P, const int* nn, const int* nt, int s
                            : p.xi;
         const double centre[3] = {0.5 * p.nx, 0.5 * p.ny, 0.5 * D.nz};
         set_window(D, p.bc, centre);
-    }
-    {
-        int dev = 0, khz = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
-            c->clock_khz = khz;
-        else
-            c->clock_khz = 100000.0;  // 100 MHz, the usual rate
     }
     hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -1133,47 +1109,39 @@ int iblb_step(iblb_ctx* c, int n_steps) {
         HIPCHK(c, hipMemsetAsync(cross_count(c, c->cur), 0, sizeof(int) * c->L.rows, c->stream));
     }
     if (c->timing) {
-        // Same schedule as below (graph replays + direct launches), with the
-        // lattice kernel stamping its own first block start and last store
-        // on the device clock; the stream is synchronised after each replay
-        // to read the stamps.  The final field-storing step is not timed.
-        int rc = ensure_events(c, 2);
+        // Every step launched directly (a dispatch that marks events cannot
+        // be captured in a graph), each lattice launch between a pair of
+        // events marked by its own dispatch; the events are read every
+        // kTimedChunk launches.  The final field-storing step is not part
+        // of the kernel average.
+        int rc = ensure_events(c, 2 + 2 * kTimedChunk);
         if (rc) return rc;
         hipEvent_t* ev = c->events.data();
-        unsigned long long* st = c->at<unsigned long long>(c->L.stamps);
-        const int eager_slot = 0;
-        const bool graphs = c->graph_steps > 0 && c->graph_steps <= kTimedLaunches;
         double lb = 0.0, ms = 0.0;
         long long nlb = 0;
+        int pending = 0;
         HIPCHK(c, hipEventRecord(ev[0], c->stream));
         launch_spread(c, c->stream, c->cur, n_steps == 1);
-        int rem = n_steps;
-        while (rem > 1) {
-            if (graphs && rem >= c->graph_steps + 2) {
-                if ((rc = ensure_graph(c, c->cur, true)) || (rc = reset_stamps(c, 0, c->graph_steps)))
-                    return rc;
-                HIPCHK(c, hipGraphLaunch(c->texec[c->cur], c->stream));
-                if ((rc = read_stamps(c, 0, c->graph_steps, ms))) return rc;
-                nlb += c->graph_steps;
-                rem -= c->graph_steps;
-                c->step += c->graph_steps;
-            } else {
-                if ((rc = reset_stamps(c, eager_slot, 1))) return rc;
-                launch_step(c, c->stream, c->cur, false, 0, rem == 2, st + (size_t)eager_slot * kStampWords);
-                if ((rc = read_stamps(c, eager_slot, 1, ms))) return rc;
-                ++nlb;
-                c->cur ^= 1;
-                rem--;
-                c->step++;
+        for (int rem = n_steps; rem > 1; --rem) {
+            if (pending == kTimedChunk) {
+                if ((rc = read_lb_events(c, pending, ms))) return rc;
+                lb += ms;
+                nlb += pending;
+                pending = 0;
             }
-            lb += ms;
+            launch_step(c, c->stream, c->cur, false, 0, rem == 2, ev + 2 + 2 * pending);
+            ++pending;
+            c->cur ^= 1;
+            c->step++;
         }
         launch_step(c, c->stream, c->cur, true, 1, 0);
         c->cur ^= 1;
         c->step++;
         HIPCHK(c, hipEventRecord(ev[1], c->stream));
         HIPCHK(c, hipGetLastError());
-        HIPCHK(c, hipEventSynchronize(ev[1]));
+        if ((rc = read_lb_events(c, pending, ms))) return rc;
+        lb += ms;
+        nlb += pending;
         float total = 0.f;
         HIPCHK(c, hipEventElapsedTime(&total, ev[0], ev[1]));
         c->t_lb = nlb ? lb / nlb : 0.0;

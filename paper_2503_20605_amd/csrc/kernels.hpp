@@ -88,43 +88,6 @@ struct DiagDev {
     double cross_n;
 };
 
-// Timing slots of one lattice launch: kStampSpread (start, end) pairs,
-// kStampStride words apart (one 128-byte line each).
-constexpr int kStampSpread = 256;
-constexpr int kStampStride = 16;
-constexpr int kStampWords = kStampSpread * kStampStride;
-
-// Reset the timing slots of `launches` launches: starts to the maximum,
-// ends to zero.
-__global__ void k_stamps_reset(unsigned long long* __restrict__ st, int launches) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= launches * kStampSpread) return;
-    st[(long long)i * kStampStride] = ~0ULL;
-    st[(long long)i * kStampStride + 1] = 0ULL;
-}
-
-// Fold each launch's slots into (earliest start, latest end): one block of
-// kStampSpread threads per launch.
-__global__ void k_stamps_fold(const unsigned long long* __restrict__ st,
-                              unsigned long long* __restrict__ out) {
-    __shared__ unsigned long long lo[kStampSpread], hi[kStampSpread];
-    const int l = blockIdx.x, t = threadIdx.x;
-    lo[t] = st[((long long)l * kStampSpread + t) * kStampStride];
-    hi[t] = st[((long long)l * kStampSpread + t) * kStampStride + 1];
-    __syncthreads();
-    for (int o = kStampSpread / 2; o > 0; o >>= 1) {
-        if (t < o) {
-            lo[t] = lo[t] < lo[t + o] ? lo[t] : lo[t + o];
-            hi[t] = hi[t] > hi[t + o] ? hi[t] : hi[t + o];
-        }
-        __syncthreads();
-    }
-    if (t == 0) {
-        out[2 * l] = lo[0];
-        out[2 * l + 1] = hi[0];
-    }
-}
-
 // Blocks are dealt round-robin to the eight XCDs.  Remap the block index so
 // that each XCD works through one contiguous run of tiles: x-neighbouring
 // strips and y-neighbouring rows then meet in the same L2.
@@ -230,7 +193,6 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
                                                float* __restrict__ Fout_all,
                                                const uint8_t* __restrict__ flags_all,
                                                uint8_t* __restrict__ flags_clr, int full,
-                                               unsigned long long* __restrict__ stamps,
                                                const int* __restrict__ xcnt,
                                                const double* __restrict__ xpos,
                                                int* __restrict__ xclr) {
@@ -239,11 +201,6 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
     constexpr int Q = L::Q;
     constexpr bool FLAT = BX == 0;
     constexpr int BY = FLAT ? 1 : kBlock / (FLAT ? 1 : BX);
-    // timing only (stamps non-null): block start on the device's
-    // constant-rate clock, folded into one of kStampSpread slots (one cache
-    // line each) so that the atomics do not pile up on a single address
-    unsigned long long* stamp = stamps ? stamps + (blockIdx.x % kStampSpread) * kStampStride : nullptr;
-    if (stamp && threadIdx.x == 0) atomicMin(stamp, (unsigned long long)wall_clock64());
     const int4 tile = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     const DropDev& D = drops[ONE ? 0 : tile.x];
     const int nx = D.nx, ny = D.ny, nz = D.nz;
@@ -361,13 +318,6 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
             U[2 * ncell + cell] = uz;
             Fo[2 * ncell + cell] = Fz;
         }
-    }
-    if (stamp) {
-        // wavefront end, once its stores have completed; lane 0 of a
-        // wavefront is active whenever any lane is (the cell index grows
-        // with the lane)
-        __builtin_amdgcn_s_waitcnt(0);
-        if ((threadIdx.x & 63) == 0) atomicMax(stamp + 1, (unsigned long long)wall_clock64());
     }
 }
 

@@ -174,23 +174,24 @@ def test_full_size_large_droplet_in_graph_configuration():
 
 
 def test_steps_split_over_calls_and_timing_mode():
-    """The step count split over calls of 1, 2, 3, 66 and 128 steps (graph
+    """The step count split over calls of 1, 2, 3, 66 and 300 steps (graph
     replays of 16 steps, direct launches, the forces of each call's first
     step computed at its start), with the timed schedule on for the last
-    two calls, reaches the oracle's state after the same 200 steps; the
-    lattice kernel's timed span is positive and shorter than a step."""
+    two calls (the last one reads its events in two chunks), reaches the
+    oracle's state after the same 372 steps; the lattice kernel's timed
+    duration is positive and shorter than a step."""
     W = wl.droplet_2d_small()
     s = gpu_solver([W.params], [W.nodes])
     s.set_graph_steps(16)
-    print("[ib] split calls 1+2+3+66+128", flush=True)
-    for k, n in enumerate((1, 2, 3, 66, 128)):
+    print("[ib] split calls 1+2+3+66+300", flush=True)
+    for k, n in enumerate((1, 2, 3, 66, 300)):
         s.set_timing(k >= 3)
         s.step(n)
     span, step = s.last_timing()
     assert 0.0 < span < step
     s.set_timing(False)
     g = collect(s, 0, 2)
-    r = o.run(W.params, W.nodes, 200)
+    r = o.run(W.params, W.nodes, 372)
     drho, du, dq = compare_fields(g, r, 2, "split-calls")
     assert drho <= 1e-5 and du <= 1e-5 and dq <= 1e-5
     assert np.max(np.abs(g["phi"] - r["phi"])) <= 1e-6 * max(1.0, np.max(np.abs(r["phi"])))
@@ -263,19 +264,29 @@ def test_full_batch_of_256_sampled_droplets():
 
 @pytest.mark.parametrize("storage,name", [(1, "f16"), (2, "bf16")])
 def test_shifted_low_precision_storage_error(storage, name):
-    """Report the error of fp16 / bf16 storage of f - w against the oracle.
-    Bounds: the stored deviations are O(1e-3) at most, so one rounding costs
-    ~u * 1e-3 (u = 2^-11 fp16, 2^-8 bf16); after 1000 steps the density error
-    stays a small multiple of that, and node positions move by far less than
-    a lattice spacing."""
+    """Report the error of fp16 / bf16 storage of f - w against the oracle,
+    in density, velocity, node positions, enclosed area and measured angle.
+    The stored deviations are O(1e-3) at most, so one rounding costs
+    ~u * 1e-3 (u = 2^-11 fp16, 2^-8 bf16); after 1000 steps the density
+    error stays a small multiple of that.  The velocity and position bounds
+    are about 4x the values measured on the MI355X (fp16: rel |dU| 6.5e-4,
+    max |dq| 4.4e-5; bf16: 4.8e-3, 1.0e-3), far below what storing f itself
+    instead of f - w would give."""
     W = wl.droplet_2d_small()
     g = gpu_run(W.params, W.nodes, 1000, storage=storage)
     r = o.run(W.params, W.nodes, 1000)
     drho, du, dq = compare_fields(g, r, 2, name)
+    ag, ar = o.volume_2d(g["q"]), o.volume_2d(r["q"])
+    hg = 0.5 * (g["q"][:, 1].max() - g["q"][:, 1].min())
+    hr = 0.5 * (r["q"][:, 1].max() - r["q"][:, 1].min())
+    dth = abs(math.degrees(o.angle_from_height_2d(hg, ag) - o.angle_from_height_2d(hr, ar)))
+    print(f"[prec2d {name}] area rel {abs(ag - ar) / ar:.3e} angle {dth:.3e} deg", flush=True)
     u = 2.0 ** -11 if storage == 1 else 2.0 ** -8
     assert drho <= 50 * u * 1e-3
-    assert dq <= 0.05
-    assert du <= 0.5
+    assert du <= (3e-3 if storage == 1 else 2e-2)
+    assert dq <= (2e-4 if storage == 1 else 4e-3)
+    assert abs(ag - ar) / ar <= (1e-5 if storage == 1 else 2e-4)
+    assert dth <= (0.01 if storage == 1 else 0.1)
 
 
 def test_unstable_run_reports_status():
