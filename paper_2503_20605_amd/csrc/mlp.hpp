@@ -6,7 +6,7 @@
 //                   64x64 tile of C per workgroup, operands staged through
 //                   LDS 32 k at a time (loads along whichever index is
 //                   contiguous), one 32x32 tile per wavefront through
-//                   v_mfma_f32_32x32x8_bf16; optional split of K over
+//                   gfx950's v_mfma_f32_32x32x16_bf16; optional split of K over
 //                   workgroups (fp32 atomic accumulation); epilogue: + bias,
 //                   optional GELU (keeps the fp32 pre-activation and writes
 //                   the bf16 activation)
@@ -26,7 +26,7 @@
 
 namespace iblb {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kMlpBlock = 256;  // 4 wavefronts, a 64x64 tile of C
@@ -46,19 +46,20 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // workgroups of z take the k range [z kc, (z + 1) kc) and add their partial
 // products to Cf atomically (Cf zeroed beforehand; no bias, act = 0).
 //
-// Operand and result layout of one 32x32x8 product (lane l of 64):
-//   A: row l % 32, k = 4 (l / 32) + 0..3;  B: column l % 32, same k;
+// Operand and result layout of one 32x32x16 product (lane l of 64):
+//   A: row l % 32, k = 8 (l / 32) + 0..7;  B: column l % 32, same k;
 //   result register r: row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
 constexpr int kGemmK = 32;         // k per LDS stage
-constexpr int kGemmLd = kGemmK + 4;  // padded LDS row (bf16 elements)
+constexpr int kGemmLd = kGemmK + 8;  // padded LDS row (bf16 elements; 80 bytes, so
+                                     // each lane's 8 operands are one aligned 16-byte read)
 
 __global__ __launch_bounds__(kMlpBlock) void k_gemm_bf16(
     const uint16_t* __restrict__ A, long long sai, long long sak, const uint16_t* __restrict__ B,
     long long sbk, long long sbj, float* __restrict__ Cf, uint16_t* __restrict__ Hb, long long ldc,
     const float* __restrict__ bias, int M, int N, int K, int act, int kc) {
     // tiles stored k-contiguous: As[i][k], Bs[j][k]
-    __shared__ uint16_t As[64 * kGemmLd];
-    __shared__ uint16_t Bs[64 * kGemmLd];
+    __shared__ __attribute__((aligned(16))) uint16_t As[64 * kGemmLd];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * kGemmLd];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int ib = blockIdx.y * 64, jb = blockIdx.x * 64;
     const int kbeg = blockIdx.z * kc, kend = K < kbeg + kc ? K : kbeg + kc;
@@ -96,15 +97,11 @@ __global__ __launch_bounds__(kMlpBlock) void k_gemm_bf16(
         }
         __syncthreads();
 #pragma unroll
-        for (int s8 = 0; s8 < kGemmK; s8 += 8) {
-            const int kq = s8 + (lane >> 5) * 4;
-            bf16x4 a, b;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] = (short)As[(wi + (lane & 31)) * kGemmLd + kq + u];
-                b[u] = (short)Bs[(wj + (lane & 31)) * kGemmLd + kq + u];
-            }
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        for (int s16 = 0; s16 < kGemmK; s16 += 16) {
+            const int kq = s16 + (lane >> 5) * 8;
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(As + (wi + (lane & 31)) * kGemmLd + kq);
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(Bs + (wj + (lane & 31)) * kGemmLd + kq);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
         }
         __syncthreads();
     }

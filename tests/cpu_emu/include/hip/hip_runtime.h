@@ -205,6 +205,31 @@ inline V16 __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(V4 a, V4 b, V16 c, int, int,
     return c;
 }
 
+// v_mfma_f32_32x32x16_bf16 (gfx950): lane l supplies eight bf16 of A (row
+// l % 32, k = 8 (l / 32) + u) and of B (column l % 32, same k); the result
+// layout is that of the 32x32x8 form.  Emulated as two 32x32x8 products,
+// one over u = 0..3 and one over u = 4..7 of every lane, which together
+// take every k once.
+template <typename V8, typename V16>
+inline V16 __builtin_amdgcn_mfma_f32_32x32x16_bf16(V8 a, V8 b, V16 c, int, int, int) {
+    float acc[16];
+    for (int r = 0; r < 16; ++r) acc[r] = c[r];
+    for (int h = 0; h < 2; ++h) {
+        uint64_t pa = 0, pb = 0;
+        for (int u = 0; u < 4; ++u) {
+            const auto ea = a[4 * h + u], eb = b[4 * h + u];
+            uint16_t ua, ub;
+            memcpy(&ua, &ea, 2);
+            memcpy(&ub, &eb, 2);
+            pa |= (uint64_t)ua << (16 * u);
+            pb |= (uint64_t)ub << (16 * u);
+        }
+        ::hipemu::wave_mfma(pa, pb, acc);
+    }
+    for (int r = 0; r < 16; ++r) c[r] = acc[r];
+    return c;
+}
+
 inline int atomicMin(int* p, int v) {
     int old = *p;
     if (v < old) *p = v;
