@@ -126,8 +126,8 @@ def parse():
                     help="the ten-run 1024x512 sweep (tau 0.6/1.0 x theta_eq 30-150 deg), 50000 steps "
                          "each: measured angle and contact radius at the end of every run")
     ap.add_argument("--hbm-probe", action="store_true",
-                    help="only the lattice kernel on an 8192x4096 D2Q9 box and the copy probe "
-                         "(short; used for hardware-counter runs)")
+                    help="only the lattice kernel alone on the boxes far above the last-level "
+                         "cache and the copy probe (short; used for hardware-counter runs)")
     return ap.parse_args()
 
 
@@ -515,8 +515,7 @@ def main():
         return
     if a.hbm_probe:
         from paper_2503_20605_amd import probe_copy_bandwidth
-        res = {"lb": lb_only_rate(2, 8192, 4096, 1, 0, 20),
-               "copy_1GiB_GBs": round(probe_copy_bandwidth(1 << 30, 5), 1)}
+        res = {"lb_hbm": lb_hbm_boxes(20), "copy_1GiB_GBs": round(probe_copy_bandwidth(1 << 30, 5), 1)}
         print(json.dumps(res), flush=True)
         return
     storage = STORAGE[a.storage]
@@ -681,11 +680,17 @@ def extra_workloads(a):
           "MLUPS_graph_replay": round(cells * 2000 / wall_g / 1e6, 1),
           "lb_us": round(lb_ms * 1e3, 3),
           "effective_GBs": round(72 * cells / (lb_ms * 1e-3) / 1e9, 1)}
-    return {"d2q9_1024x512_coupled": d2,
-            "lb_hbm": [lb_only_rate(2, 8192, 4096, 1, 0, 200),
-                       lb_only_rate(2, 8192, 4096, 1, 1, 200),
-                       lb_only_rate(3, 256, 256, 128, 0, 100),
-                       lb_only_rate(3, 256, 256, 128, 1, 100)]}
+    return {"d2q9_1024x512_coupled": d2, "lb_hbm": lb_hbm_boxes(100)}
+
+
+def lb_hbm_boxes(steps):
+    """The lattice kernel alone on boxes whose two population copies far
+    exceed the 256 MB last-level cache: D2Q9 8192x4096 and D3Q19
+    256x256x128, fp32 and fp16 storage."""
+    return [lb_only_rate(2, 8192, 4096, 1, 0, 2 * steps),
+            lb_only_rate(2, 8192, 4096, 1, 1, 2 * steps),
+            lb_only_rate(3, 256, 256, 128, 0, steps),
+            lb_only_rate(3, 256, 256, 128, 1, steps)]
 
 
 if __name__ == "__main__":

@@ -49,7 +49,7 @@ int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 struct Layout {
     // byte offsets into the workspace
-    size_t drops, tiles_lb, tiles_all, f0, f1, F, U, Fout, rho, flags, pos0, pos1, phi, qdot, dropped,
+    size_t drops, tiles_lb, tiles_all, f0, f1, F, Fq, U, Fout, rho, flags, pos0, pos1, phi, qdot, dropped,
         node_drop, tri, inc, inc_beg, inc_end, perm, chunks, status, partials, diag,
         xcnt0, xcnt1, xpos0, xpos1, tref, total;
     int nchunks;           // capacity of the 3D spreading chunk table
@@ -190,7 +190,8 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
     L.tiles_all = take(sizeof(int4) * L.max_tiles);
     L.f0 = take((size_t)L.pop_elems * sb);
     L.f1 = take((size_t)L.pop_elems * sb);
-    L.F = take(sizeof(float) * dim * C);
+    L.F = take(sizeof(float) * dim * C);   // prescribed force fields
+    L.Fq = take(sizeof(unsigned long long) * dim * C);  // spread force, fixed point
     L.U = take(sizeof(float) * dim * C);
     L.Fout = take(sizeof(float) * dim * C);
     L.rho = take(sizeof(float) * C);
@@ -431,7 +432,8 @@ void launch_lb_v(const iblb_ctx* c, hipStream_t s, int src, int full, const hipE
     auto go = [&](auto kern) {
         auto args = std::make_tuple(
             c->at<DropDev>(c->L.drops), c->at<int4>(c->L.tiles_lb), (const T*)f[src], f[src ^ 1],
-            c->at<float>(c->L.F), c->at<float>(c->L.U), c->at<float>(c->L.rho), c->at<float>(c->L.Fout),
+            (const float*)c->at<float>(c->L.F), c->at<unsigned long long>(c->L.Fq), c->at<float>(c->L.U),
+            c->at<float>(c->L.rho), c->at<float>(c->L.Fout),
             (const uint8_t*)band_flags(c, src), clear ? band_flags(c, src ^ 1) : nullptr, full,
             (const int*)cross_count(c, src), (const double*)cross_x(c, src),
             clear ? cross_count(c, src ^ 1) : nullptr);
@@ -509,7 +511,7 @@ void launch_spread(const iblb_ctx* c, hipStream_t s, int p, int want_dropped) {
     const bool one = c->n == 1;
     if (c->dim == 2) {
         hipLaunchKernelGGL((one ? k_force_spread<2, true> : k_force_spread<2, false>), grid, block, 0, s, D,
-                           A, c->at<float>(c->L.F), band_flags(c, p), c->at<int>(c->L.status),
+                           A, c->at<unsigned long long>(c->L.Fq), band_flags(c, p), c->at<int>(c->L.status),
                            want_dropped);
         return;
     }
@@ -517,7 +519,7 @@ void launch_spread(const iblb_ctx* c, hipStream_t s, int p, int want_dropped) {
                        D, A);
     if (c->nchunks == 0) return;
     hipLaunchKernelGGL(k_spread3, dim3(c->nchunks), dim3(kSpreadBlock), 0, s, D, A,
-                       (const int4*)c->at<int4>(c->L.chunks), c->at<float>(c->L.F),
+                       (const int4*)c->at<int4>(c->L.chunks), c->at<unsigned long long>(c->L.Fq),
                        band_flags(c, p), c->at<int>(c->L.status), want_dropped);
 }
 
@@ -535,7 +537,7 @@ void launch_after(const iblb_ctx* c, hipStream_t s, int p, bool last, int want_d
     const float* U = c->at<float>(c->L.U);
     if (c->dim == 2 && !last) {
         hipLaunchKernelGGL(one ? k_ib_fused2<true> : k_ib_fused2<false>, grid, block, 0, s, D, A, U,
-                           c->at<float>(c->L.F), band_flags(c, p ^ 1), c->at<int>(c->L.status),
+                           c->at<unsigned long long>(c->L.Fq), band_flags(c, p ^ 1), c->at<int>(c->L.status),
                            want_dropped, cross_count(c, p ^ 1), cross_x(c, p ^ 1));
         return;
     }
@@ -641,6 +643,7 @@ int reset_droplet(iblb_ctx* c, int d) {
     HIPCHK(c, hipMemsetAsync(c->ws + c->L.f1 + D.f_off * sb, 0, (size_t)c->Q * D.fst * sb, c->stream));
     const size_t vb = sizeof(float) * c->dim * D.ncell, vo = sizeof(float) * c->dim * D.c_off;
     HIPCHK(c, hipMemsetAsync(c->ws + c->L.F + vo, 0, vb, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->ws + c->L.Fq + 2 * vo, 0, 2 * vb, c->stream));
     HIPCHK(c, hipMemsetAsync(c->ws + c->L.U + vo, 0, vb, c->stream));
     HIPCHK(c, hipMemsetAsync(c->ws + c->L.Fout + vo, 0, vb, c->stream));
     const iblb_params& p = c->params[d];
@@ -1083,6 +1086,7 @@ int iblb_set_force_field(iblb_ctx* c, int d, const float* d_F) {
         D.force_mode = 1;
     } else {
         HIPCHK(c, hipMemsetAsync(c->ws + c->L.F + vo, 0, vb, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->ws + c->L.Fq + 2 * vo, 0, 2 * vb, c->stream));
         D.force_mode = 0;
     }
     return upload_drops(c);

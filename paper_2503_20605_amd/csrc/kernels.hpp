@@ -32,7 +32,10 @@
 // lattice kernel touches them only inside the interface band: the spreading
 // kernel raises a one-byte flag for every 64-cell x strip that receives a
 // tap, and only flagged cells read F, write U for the interpolation and
-// clear F.  The flags come in two sets, one per step parity: a lattice
+// clear F.  The spread F is accumulated in fixed point (64-bit integers of
+// 2^-40 force units, see fq_of), so its value does not depend on the order
+// in which the nodes' contributions arrive; a prescribed force field is kept
+// in fp32 in an array of its own.  The flags come in two sets, one per step parity: a lattice
 // update reads its own parity's set and clears the other one for the
 // spreading of the next step.
 #pragma once
@@ -94,6 +97,25 @@ struct DiagDev {
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
     const int q = nb >> 3, r = nb & 7, x = b & 7, l = b >> 3;
     return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
+// Fixed-point accumulation of the spread force density (eq. force_spread):
+// every contribution phi_j Delta is rounded to an integer number of 2^-40
+// force units and added with a 64-bit integer atomic.  Integer addition is
+// associative, so the sum, and the fp32 value the lattice kernel forms from
+// it (one rounding of the exact sum), are the same whatever order the
+// contributions arrive in.  A contribution must stay below 2^10 in
+// magnitude (then up to 2^12 of them cannot overflow a cell); a larger or
+// non-finite one means the run has blown up: it is dropped and the
+// droplet flagged unstable (status bit 2).
+constexpr double kFqScale = 1099511627776.0;  // 2^40
+constexpr float kFqMax = 1024.f;
+__device__ __forceinline__ bool fq_ok(float v) { return fabsf(v) < kFqMax; }  // NaN: false
+__device__ __forceinline__ unsigned long long fq_of(float v) {
+    return (unsigned long long)(long long)rint((double)v * kFqScale);
+}
+__device__ __forceinline__ float fq_value(unsigned long long v) {
+    return (float)((double)(long long)v * (1.0 / kFqScale));
 }
 
 // One cell's collision in deviation form (eqs. LBE, f^eq, S_i,
@@ -188,7 +210,9 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
                                                const int4* __restrict__ tiles,
                                                const typename Codec<S>::T* __restrict__ fsrc_all,
                                                typename Codec<S>::T* __restrict__ fdst_all,
-                                               float* __restrict__ F_all, float* __restrict__ U_all,
+                                               const float* __restrict__ F_all,
+                                               unsigned long long* __restrict__ Fq_all,
+                                               float* __restrict__ U_all,
                                                float* __restrict__ rho_all,
                                                float* __restrict__ Fout_all,
                                                const uint8_t* __restrict__ flags_all,
@@ -240,6 +264,13 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
     // them instead of following them
     const long long fi = D.flag_off + (long long)(z * ny + y) * D.nstrip + (x >> 6);
     const int flag = D.force_mode == 1 ? 1 : (int)flags_all[fi];
+    // Populations move through buffer instructions (32-bit lane offsets,
+    // base in scalar registers): one descriptor per opposite pair (i,
+    // opp(i)), based at the lower index, so that a lane offset never
+    // exceeds 2 fst elements and a bounce-back read of opp(i) stays inside
+    // the same descriptor.  Q fst < 2^31 elements keeps every offset and
+    // size below 2^31 bytes.
+    constexpr int SB = storage_bytes<S>();
     float f[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -250,11 +281,14 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         // a source beyond a wall means the population was reflected there:
         // take the opposite population of this cell (half-way bounce-back)
         const bool wall = (sx | sy | sz) < 0;
-        const int idx = wall ? opp(i) * fst + cell : i * fst + (sz * ny + sy) * nx + sx;
-        f[i] = NTL ? C::load_nt(fsrc, idx) : C::load(fsrc, idx);
+        const int lo = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+        const auto rs = buffer_of(fsrc + (long long)lo * fst, (i == 0 ? 1 : 2) * fst * SB);
+        const int rel = wall ? (opp(i) - lo) * fst + cell : (i - lo) * fst + (sz * ny + sy) * nx + sx;
+        f[i] = C::template load_buf<NTL ? kBufNT : 0>(rs, (unsigned)rel * SB);
     }
 
-    float* __restrict__ F = F_all + (long long)DIM * D.c_off;
+    const float* __restrict__ F = F_all + (long long)DIM * D.c_off;
+    unsigned long long* __restrict__ Fq = Fq_all + (long long)DIM * D.c_off;
     float* __restrict__ U = U_all + (long long)DIM * D.c_off;
     bool forced;
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
@@ -271,9 +305,15 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         if (flags_clr && (x & 63) == 0) flags_clr[fi] = 0;
     }
     if (forced) {
-        Fx = F[cell];
-        Fy = F[ncell + cell];
-        if (DIM == 3) Fz = F[2 * ncell + cell];
+        if (D.force_mode == 1) {
+            Fx = F[cell];
+            Fy = F[ncell + cell];
+            if (DIM == 3) Fz = F[2 * ncell + cell];
+        } else {
+            Fx = fq_value(Fq[cell]);
+            Fy = fq_value(Fq[ncell + cell]);
+            if (DIM == 3) Fz = fq_value(Fq[2 * ncell + cell]);
+        }
     }
     const Moments<DIM> M(f, Fx, Fy, Fz);
     const float rho = M.rho, ux = M.ux, uy = M.uy, uz = M.uz;
@@ -292,10 +332,9 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const float fn = M.relax(i, f[i], om, g, forced);
-        if (NT)
-            C::store_nt(fdst, i * fst + cell, fn);
-        else
-            C::store(fdst, i * fst + cell, fn);
+        const int lo = i == 0 ? 0 : ((i & 1) ? i : i - 1);
+        const auto rd = buffer_of(fdst + (long long)lo * fst, (i == 0 ? 1 : 2) * fst * SB);
+        C::template store_buf<NT ? kBufNT : 0>(rd, (unsigned)((i - lo) * fst + cell) * SB, fn);
     }
 
     if (forced && D.force_mode == 0) {
@@ -303,9 +342,9 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         U[cell] = ux;
         U[ncell + cell] = uy;
         if (DIM == 3) U[2 * ncell + cell] = uz;
-        F[cell] = 0.f;
-        F[ncell + cell] = 0.f;
-        if (DIM == 3) F[2 * ncell + cell] = 0.f;
+        Fq[cell] = 0;
+        Fq[ncell + cell] = 0;
+        if (DIM == 3) Fq[2 * ncell + cell] = 0;
     }
     if (full) {
         float* __restrict__ Fo = Fout_all + (long long)DIM * D.c_off;
@@ -645,8 +684,9 @@ __device__ __forceinline__ int lane_tap(const DropDev& D, const double q[3], int
 template <int DIM>
 __device__ __forceinline__ void spread_lane(const DropDev& D, const NodeArrays& A, int j, int k,
                                             const double q[3], const float ph[3],
-                                            float* __restrict__ F_all,
-                                            uint8_t* __restrict__ flags_all, int want_dropped) {
+                                            unsigned long long* __restrict__ Fq_all,
+                                            uint8_t* __restrict__ flags_all, int want_dropped,
+                                            int* __restrict__ status_d) {
     constexpr int T = Taps<DIM>::n;
     float w;
     int row, ix;
@@ -656,9 +696,17 @@ __device__ __forceinline__ void spread_lane(const DropDev& D, const NodeArrays& 
 #pragma unroll
         for (int a = 0; a < DIM; ++a) lost[a] = ph[a] * w;
     } else {
-        float* __restrict__ F = F_all + (long long)DIM * D.c_off;
+        unsigned long long* __restrict__ Fq = Fq_all + (long long)DIM * D.c_off;
+        bool fine = true;
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) unsafeAtomicAdd(F + a * D.ncell + cell, ph[a] * w);
+        for (int a = 0; a < DIM; ++a) {
+            const float v = ph[a] * w;
+            if (fq_ok(v))
+                atomicAdd(Fq + a * D.ncell + cell, fq_of(v));
+            else
+                fine = false;
+        }
+        if (!fine) atomicOr(status_d, 2);
         flags_all[D.flag_off + row * D.nstrip + (ix >> 6)] = 1;
     }
     if (want_dropped) {
@@ -675,7 +723,8 @@ __device__ __forceinline__ void spread_lane(const DropDev& D, const NodeArrays& 
 // ---------------------------------------------------------------------------
 template <int DIM, bool ONE>
 __global__ __launch_bounds__(kNodeBlock) void k_force_spread(const DropDev* __restrict__ drops,
-                                                         NodeArrays A, float* __restrict__ F_all,
+                                                         NodeArrays A,
+                                                         unsigned long long* __restrict__ Fq_all,
                                                          uint8_t* __restrict__ flags_all,
                                                          int* __restrict__ status,
                                                          int want_dropped) {
@@ -713,7 +762,7 @@ __global__ __launch_bounds__(kNodeBlock) void k_force_spread(const DropDev* __re
         if (k == 0) atomicOr(status + d, 4);
         return;
     }
-    spread_lane<DIM>(D, A, j, k, q, ph, F_all, flags_all, want_dropped);
+    spread_lane<DIM>(D, A, j, k, q, ph, Fq_all, flags_all, want_dropped, status + d);
 }
 
 // Nodes that do not move this step (droplet inactive, prescribed force
@@ -1053,10 +1102,10 @@ constexpr int kSpreadBlock = IBLB_SPREAD_BLOCK;  // wavefronts each taking every
 
 __global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restrict__ drops, NodeArrays A,
                                                     const int4* __restrict__ chunks,
-                                                    float* __restrict__ F_all,
+                                                    unsigned long long* __restrict__ Fq_all,
                                                     uint8_t* __restrict__ flags_all,
                                                     int* __restrict__ status, int want_dropped) {
-    __shared__ float box[3 * kBoxCells];
+    __shared__ unsigned long long box[3 * kBoxCells];
     __shared__ uint8_t touched[kBoxCells];
     __shared__ double sq[kChunk][3];
     __shared__ float sph[kChunk][3];
@@ -1104,13 +1153,14 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restr
     const bool fits = any && (long long)ex * ey * ez <= kBoxCells;
     const int ncb = fits ? ex * ey * ez : 0;
     for (int c = t; c < ncb; c += kSpreadBlock) {
-        box[c] = 0.f;
-        box[kBoxCells + c] = 0.f;
-        box[2 * kBoxCells + c] = 0.f;
+        box[c] = 0;
+        box[kBoxCells + c] = 0;
+        box[2 * kBoxCells + c] = 0;
         touched[c] = 0;
     }
     __syncthreads();
-    float* __restrict__ F = F_all + 3LL * D.c_off;
+    unsigned long long* __restrict__ Fq = Fq_all + 3LL * D.c_off;
+    bool fine = true;
     const int k = t & 63;  // tap of this lane; one vertex per wavefront at a time
     const int kx = k & 3, ky = (k >> 2) & 3, kz = k >> 4;
     for (int v = t >> 6; v < count; v += kSpreadBlock / 64) {
@@ -1127,12 +1177,24 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restr
         } else if (fits) {
             const int c = ((bz + kz - lo[2]) * ey + (by + ky - lo[1])) * ex + (bx + kx - lo[0]);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) atomicAdd(&box[a * kBoxCells + c], sph[v][a] * w);
+            for (int a = 0; a < 3; ++a) {
+                const float val = sph[v][a] * w;
+                if (fq_ok(val))
+                    atomicAdd(&box[a * kBoxCells + c], fq_of(val));
+                else
+                    fine = false;
+            }
             touched[c] = 1;
         } else {
             const int row = gz * D.ny + gy, cell = row * D.nx + gx;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) unsafeAtomicAdd(F + a * D.ncell + cell, sph[v][a] * w);
+            for (int a = 0; a < 3; ++a) {
+                const float val = sph[v][a] * w;
+                if (fq_ok(val))
+                    atomicAdd(Fq + a * D.ncell + cell, fq_of(val));
+                else
+                    fine = false;
+            }
             flags_all[D.flag_off + row * D.nstrip + (gx >> 6)] = 1;
         }
         if (want_dropped) {
@@ -1145,6 +1207,7 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restr
             }
         }
     }
+    if (!fine) atomicOr(status + ch.x, 2);
     if (!fits) return;
     __syncthreads();
     for (int c = t; c < ncb; c += kSpreadBlock) {
@@ -1156,8 +1219,8 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restr
         const int row = gz * D.ny + gy, cell = row * D.nx + gx;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const float v = box[a * kBoxCells + c];
-            if (v != 0.f) unsafeAtomicAdd(F + a * D.ncell + cell, v);
+            const unsigned long long v = box[a * kBoxCells + c];
+            if (v != 0) atomicAdd(Fq + a * D.ncell + cell, v);
         }
         flags_all[D.flag_off + row * D.nstrip + (gx >> 6)] = 1;
     }
@@ -1174,7 +1237,7 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restr
 template <bool ONE>
 __global__ __launch_bounds__(kNodeBlock) void k_ib_fused2(const DropDev* __restrict__ drops, NodeArrays A,
                                                       const float* __restrict__ U_all,
-                                                      float* __restrict__ F_all,
+                                                      unsigned long long* __restrict__ Fq_all,
                                                       uint8_t* __restrict__ flags_all,
                                                       int* __restrict__ status, int want_dropped,
                                                       int* __restrict__ xcnt,
@@ -1292,7 +1355,7 @@ __global__ __launch_bounds__(kNodeBlock) void k_ib_fused2(const DropDev* __restr
         A.phi[j] = ph[0];
         A.phi[st + j] = ph[1];
     }
-    spread_lane<2>(D, A, j, k, qn[1], ph, F_all, flags_all, want_dropped);
+    spread_lane<2>(D, A, j, k, qn[1], ph, Fq_all, flags_all, want_dropped, status + d);
 }
 
 // ---------------------------------------------------------------------------

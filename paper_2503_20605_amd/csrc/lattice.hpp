@@ -46,6 +46,16 @@ __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i 
 // stores round to nearest even.
 enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
 
+// Buffer descriptors for the lattice kernel's population traffic: a
+// buffer_load/buffer_store takes a 32-bit byte offset per lane and keeps the
+// 64-bit base in scalar registers, so no lane forms a 64-bit address.
+// kBufNT: the cache-policy bit of a non-temporal access (nt).
+constexpr int kBufNT = 2;
+constexpr int kBufWord3 = 0x00020000;  // descriptor word 3: raw (untyped) 32-bit data
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, kBufWord3);
+}
+
 template <int S>
 struct Codec;
 
@@ -57,6 +67,14 @@ struct Codec<ST_F32> {
     static __device__ __forceinline__ void store(T* p, int i, float v) { p[i] = v; }
     static __device__ __forceinline__ void store_nt(T* p, int i, float v) {
         __builtin_nontemporal_store(v, p + i);
+    }
+    template <int AUX>
+    static __device__ __forceinline__ float load_buf(__amdgpu_buffer_rsrc_t r, unsigned off) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, AUX));
+    }
+    template <int AUX>
+    static __device__ __forceinline__ void store_buf(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, AUX);
     }
     static __host__ __device__ __forceinline__ T from_double(double v) { return (float)v; }
     static __host__ __device__ __forceinline__ double to_double(T v) { return (double)v; }
@@ -72,6 +90,15 @@ struct Codec<ST_F16> {
     static __device__ __forceinline__ void store(T* p, int i, float v) { p[i] = (_Float16)v; }
     static __device__ __forceinline__ void store_nt(T* p, int i, float v) {
         __builtin_nontemporal_store((_Float16)v, p + i);
+    }
+    template <int AUX>
+    static __device__ __forceinline__ float load_buf(__amdgpu_buffer_rsrc_t r, unsigned off) {
+        return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, AUX));
+    }
+    template <int AUX>
+    static __device__ __forceinline__ void store_buf(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, (int)off, 0,
+                                              AUX);
     }
     // exchange values are narrowed through fp32 (nearest even at each step)
     static __device__ __forceinline__ T from_double(double v) { return (_Float16)(float)v; }
@@ -99,6 +126,14 @@ struct Codec<ST_BF16> {
     static __device__ __forceinline__ void store(T* p, int i, float v) { p[i] = f32_to_bf16_rne(v); }
     static __device__ __forceinline__ void store_nt(T* p, int i, float v) {
         __builtin_nontemporal_store(f32_to_bf16_rne(v), p + i);
+    }
+    template <int AUX>
+    static __device__ __forceinline__ float load_buf(__amdgpu_buffer_rsrc_t r, unsigned off) {
+        return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, AUX));
+    }
+    template <int AUX>
+    static __device__ __forceinline__ void store_buf(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(f32_to_bf16_rne(v), r, (int)off, 0, AUX);
     }
     // exchange values are narrowed through fp32 (nearest even at each step)
     static __device__ __forceinline__ T from_double(double v) { return f32_to_bf16_rne((float)v); }

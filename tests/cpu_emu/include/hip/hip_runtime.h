@@ -230,6 +230,44 @@ inline V16 __builtin_amdgcn_mfma_f32_32x32x16_bf16(V8 a, V8 b, V16 c, int, int, 
     return c;
 }
 
+// Buffer descriptors and raw buffer loads/stores.  The hardware returns
+// zero for (and drops) an access beyond the descriptor's size; here such an
+// access aborts, so that an indexing mistake cannot hide behind it.
+struct HipemuBufferRsrc {
+    char* base;
+    long long bytes;
+};
+typedef HipemuBufferRsrc __amdgpu_buffer_rsrc_t;
+inline __amdgpu_buffer_rsrc_t __builtin_amdgcn_make_buffer_rsrc(void* p, short, int bytes, int) {
+    return HipemuBufferRsrc{static_cast<char*>(p), (long long)bytes};
+}
+inline char* hipemu_buffer_at(__amdgpu_buffer_rsrc_t r, int off, int soff, int size) {
+    const long long o = (long long)(unsigned)off + (long long)(unsigned)soff;
+    if (o + size > r.bytes) {
+        fprintf(stderr, "hipemu: buffer access at byte %lld (+%d) beyond the descriptor's %lld bytes\n", o,
+                size, r.bytes);
+        abort();
+    }
+    return r.base + o;
+}
+inline unsigned __builtin_amdgcn_raw_buffer_load_b32(__amdgpu_buffer_rsrc_t r, int off, int soff, int) {
+    unsigned v;
+    memcpy(&v, hipemu_buffer_at(r, off, soff, 4), 4);
+    return v;
+}
+inline unsigned short __builtin_amdgcn_raw_buffer_load_b16(__amdgpu_buffer_rsrc_t r, int off, int soff, int) {
+    unsigned short v;
+    memcpy(&v, hipemu_buffer_at(r, off, soff, 2), 2);
+    return v;
+}
+inline void __builtin_amdgcn_raw_buffer_store_b32(unsigned v, __amdgpu_buffer_rsrc_t r, int off, int soff, int) {
+    memcpy(hipemu_buffer_at(r, off, soff, 4), &v, 4);
+}
+inline void __builtin_amdgcn_raw_buffer_store_b16(unsigned short v, __amdgpu_buffer_rsrc_t r, int off, int soff,
+                                                  int) {
+    memcpy(hipemu_buffer_at(r, off, soff, 2), &v, 2);
+}
+
 inline int atomicMin(int* p, int v) {
     int old = *p;
     if (v < old) *p = v;
@@ -247,6 +285,11 @@ inline int atomicAdd(int* p, int v) {
 }
 inline float atomicAdd(float* p, float v) {
     float old = *p;
+    *p = old + v;
+    return old;
+}
+inline unsigned long long atomicAdd(unsigned long long* p, unsigned long long v) {
+    unsigned long long old = *p;
     *p = old + v;
     return old;
 }
