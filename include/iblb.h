@@ -370,6 +370,22 @@ int iblb_mlp_gradients(iblb_mlp *mlp, const float *d_x, const float *d_t, int ba
  * iblb_mlp_gradients call. */
 int iblb_mlp_adam_step(iblb_mlp *mlp, float lr, float beta1, float beta2, float eps);
 
+/* Forward pass that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops): the
+ * same result as iblb_mlp_forward (same kernels, bit for bit), but the
+ * bf16 input and the hidden layers' activations live in a static device
+ * array of 8 MiB in the library instead of the handle's workspace, and the
+ * last layer writes d_y directly.  d_x [batch][widths[0]] -> d_y
+ * [batch][widths[n_layers]], device fp32; batch >= 1 and not limited by
+ * max_batch, but the batch's scratch (2 batch widths[0] bytes plus
+ * 8 batch h bytes, h the widest hidden layer, each part rounded up to 256)
+ * must fit the 8 MiB, else EINVAL with the sizes in the message.  Queued
+ * on the handle's stream; no allocation, no host synchronisation.  Every
+ * call on one device shares that device's array: calls that overlap on a
+ * device (several streams or threads) race and must be serialised by the
+ * caller. */
+int iblb_mlp_forward_noalloc(iblb_mlp *mlp, const float *d_x, int batch, float *d_y);
+
 #ifdef __cplusplus
 }
 #endif

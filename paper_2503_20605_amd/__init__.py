@@ -358,6 +358,15 @@ class MLP:
         self.stream.synchronize()
         return y
 
+    def forward_noalloc(self, x, y):
+        """iblb_mlp_forward_noalloc: x (batch, widths[0]) into the caller's
+        y (batch, widths[-1]), both device fp32; the library allocates
+        nothing (its activations live in a static device array)."""
+        _lib.check_mlp(self.lib.iblb_mlp_forward_noalloc(self.h, ctypes.c_void_p(x.data_ptr()),
+                                                         x.shape[0], ctypes.c_void_p(y.data_ptr())),
+                       self.h)
+        return y
+
     def gradients(self, x, t, want_grads=True):
         x, t = self._dev(x), self._dev(t)
         g = np.zeros(self.P, dtype=np.float32) if want_grads else None

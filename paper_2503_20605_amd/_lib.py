@@ -36,7 +36,7 @@ EXPORTED = (
     "iblb_contact_radius", "iblb_set_membrane_shear",
     "iblb_mlp_workspace_bytes", "iblb_mlp_create", "iblb_mlp_destroy", "iblb_mlp_last_error",
     "iblb_mlp_param_count", "iblb_mlp_set_params", "iblb_mlp_get_params", "iblb_mlp_forward",
-    "iblb_mlp_gradients", "iblb_mlp_adam_step",
+    "iblb_mlp_gradients", "iblb_mlp_adam_step", "iblb_mlp_forward_noalloc",
 )
 
 
@@ -127,6 +127,7 @@ def load() -> ctypes.CDLL:
     lib.iblb_mlp_set_params.argtypes = [c_void_p, c_void_p]
     lib.iblb_mlp_get_params.argtypes = [c_void_p, c_void_p]
     lib.iblb_mlp_forward.argtypes = [c_void_p, c_void_p, c_int, c_void_p]
+    lib.iblb_mlp_forward_noalloc.argtypes = [c_void_p, c_void_p, c_int, c_void_p]
     lib.iblb_mlp_gradients.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_void_p, P(c_double)]
     lib.iblb_mlp_adam_step.argtypes = [c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                        ctypes.c_float]

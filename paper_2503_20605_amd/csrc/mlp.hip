@@ -2,13 +2,15 @@
 // connected network widths[0] -> ... -> widths[L] with GELU after every
 // layer but the last, bf16 operands on the matrix cores, fp32 master
 // weights, MSE loss, Adam.  All device memory comes from the caller's
-// workspace.
+// workspace, except the static scratch array of the forward pass that
+// allocates nothing (iblb_mlp_forward_noalloc).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,6 +20,13 @@
 #include "mlp.hpp"
 
 using namespace iblb;
+
+// Scratch of iblb_mlp_forward_noalloc: the input rounded to bf16 and the
+// hidden layers' activations, for callers that cannot allocate device
+// memory.  Each device holds its own copy for the life of the process;
+// every such call on a device shares it.
+constexpr size_t kNoallocScratchBytes = 8u << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
 
 namespace {
 
@@ -81,6 +90,7 @@ bool mlp_plan(int L, const int* widths, int B, MlpLayout& Y, std::string& err) {
 struct iblb_mlp {
     MlpLayout Y;
     char* ws = nullptr;
+    char* scratch = nullptr;  // device address of this device's static scratch
     hipStream_t stream = nullptr;
     long long t = 0;       // Adam steps taken
     int last_batch = 0;    // batch of the last gradient evaluation
@@ -142,6 +152,40 @@ int mlp_forward(iblb_mlp* c, const float* d_x, int batch) {
     return IBLB_OK;
 }
 
+// Device address of the static scratch array on the current device, looked
+// up once per device (host code must never pass the array's own name to a
+// kernel: on the host that name is a stand-in, not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_dev[kMaxDevices] = {};
+
+hipError_t scratch_address(char** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+// Bytes of static scratch a forward pass of `batch` rows needs: the bf16
+// input, one fp32 pre-activation buffer and two bf16 activation buffers of
+// the widest hidden layer (the last layer writes the caller's output).
+size_t noalloc_bytes(const MlpLayout& Y, long long batch) {
+    int mh = 0;
+    for (int l = 1; l < Y.L; ++l) mh = std::max(mh, Y.w[l]);
+    size_t need = mlp_align(2ull * batch * Y.w[0]);
+    if (mh > 0) need += mlp_align(4ull * batch * mh) + 2 * mlp_align(2ull * batch * mh);
+    return need;
+}
+
 int check_batch(iblb_mlp* c, int batch) {
     if (!c) return IBLB_EINVAL;
     if (batch < 1 || batch > c->Y.B) return mlp_fail(c, IBLB_EINVAL, "batch must be 1..max_batch");
@@ -168,11 +212,18 @@ int iblb_mlp_create(int n_layers, const int* widths, int max_batch, void* d_ws, 
     if (!d_ws || reinterpret_cast<uintptr_t>(d_ws) % kMlpAlign)
         return mlp_fail(nullptr, IBLB_EINVAL, "workspace must be non-NULL and 256-byte aligned");
     if (ws_bytes < Y.total) return mlp_fail(nullptr, IBLB_ENOMEM, "workspace too small");
+    char* scr = nullptr;
+    hipError_t e = scratch_address(&scr);
+    if (e != hipSuccess) {
+        g_mlp_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return IBLB_EDEVICE;
+    }
     iblb_mlp* c = new iblb_mlp();
     c->Y = Y;
     c->ws = static_cast<char*>(d_ws);
+    c->scratch = scr;
     c->stream = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMemsetAsync(c->ws, 0, Y.total, c->stream);
+    e = hipMemsetAsync(c->ws, 0, Y.total, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         g_mlp_err = std::string("hipMemsetAsync: ") + hipGetErrorString(e);
@@ -225,6 +276,48 @@ int iblb_mlp_forward(iblb_mlp* c, const float* d_x, int batch, float* d_y) {
     const MlpLayout& Y = c->Y;
     MLPCHK(c, hipMemcpyAsync(d_y, c->at<float>(Y.Z[Y.L - 1]), 4ull * batch * Y.w[Y.L],
                              hipMemcpyDeviceToDevice, c->stream));
+    return IBLB_OK;
+}
+
+int iblb_mlp_forward_noalloc(iblb_mlp* c, const float* d_x, int batch, float* d_y) {
+    if (!c) return IBLB_EINVAL;
+    if (batch < 1) return mlp_fail(c, IBLB_EINVAL, "batch must be >= 1");
+    if (!d_x || !d_y) return mlp_fail(c, IBLB_EINVAL, "NULL input or output");
+    const MlpLayout& Y = c->Y;
+    const size_t need = noalloc_bytes(Y, batch);
+    if (need > kNoallocScratchBytes) {
+        char buf[200];
+        snprintf(buf, sizeof buf,
+                 "forward_noalloc: a batch of %d rows needs %zu bytes of static scratch, more than "
+                 "its %zu",
+                 batch, need, kNoallocScratchBytes);
+        return mlp_fail(c, IBLB_EINVAL, buf);
+    }
+    // carve the scratch: bf16 input, fp32 pre-activations, two bf16
+    // activation buffers used in turn (no clearing needed: every kernel
+    // writes each element it later reads)
+    int mh = 0;
+    for (int l = 1; l < Y.L; ++l) mh = std::max(mh, Y.w[l]);
+    char* p = c->scratch;
+    uint16_t* xb = reinterpret_cast<uint16_t*>(p);
+    p += mlp_align(2ull * batch * Y.w[0]);
+    float* z = reinterpret_cast<float*>(p);
+    p += mlp_align(4ull * batch * mh);
+    uint16_t* h[2] = {reinterpret_cast<uint16_t*>(p),
+                      reinterpret_cast<uint16_t*>(p + mlp_align(2ull * batch * mh))};
+    const long long nx = (long long)batch * Y.w[0];
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)mlp_cdiv(nx, kMlpBlock)), dim3(kMlpBlock), 0, c->stream,
+                       d_x, xb, nx);
+    const uint16_t* in_b = xb;
+    for (int l = 0; l < Y.L; ++l) {
+        const int in = Y.w[l], out = Y.w[l + 1];
+        const bool last = l == Y.L - 1;
+        uint16_t* hb = last ? nullptr : h[l & 1];
+        gemm(c, in_b, in, 1, c->at<uint16_t>(Y.wb) + Y.woff[l], out, 1, last ? d_y : z, hb, out,
+             c->at<float>(Y.master) + Y.boff[l], batch, out, in, last ? 0 : 1);
+        in_b = hb;
+    }
+    MLPCHK(c, hipGetLastError());
     return IBLB_OK;
 }
 

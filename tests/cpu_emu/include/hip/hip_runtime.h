@@ -33,6 +33,7 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static
+#define __align__(x) __attribute__((aligned(x)))
 
 struct dim3 {
     unsigned x, y, z;
@@ -50,8 +51,17 @@ typedef enum {
     hipSuccess = 0,
     hipErrorInvalidValue = 1,
     hipErrorInvalidConfiguration = 9,
+    hipErrorInvalidDevice = 101,
     hipErrorStreamCaptureUnsupported = 900,
 } hipError_t;
+
+// device symbols are plain host arrays here, so a symbol's device address
+// is its own address
+#define HIP_SYMBOL(x) (&(x))
+inline hipError_t hipGetSymbolAddress(void** p, const void* sym) {
+    *p = const_cast<void*>(sym);
+    return hipSuccess;
+}
 
 inline const char* hipGetErrorString(hipError_t e) {
     switch (e) {
