@@ -175,8 +175,12 @@ int iblb_read_populations(iblb_ctx *ctx, int droplet, double *d_fdev);
 int iblb_set_force_field(iblb_ctx *ctx, int droplet, const float *d_F);
 
 /* Advance every droplet by n_steps time steps.  Each step: nodal forces at
- * q(t) -> spread to F(t) -> fused pull-stream + collide with F(t) -> velocity
- * U(t) interpolated at q(t) -> q(t+1) = q(t) + qdot(t).  Asynchronous except
+ * q(t) (surface tension, Sec. "Modelling surface tension forces"; wetting,
+ * eq. disjoin-p with A of eq. A_choice) -> spread to F(t) (eq.
+ * force_spread, Peskin kernel Psi) -> fused pull-stream + collide with F(t)
+ * (eq. LBE with Guo's source; moments of eqs. hydro_var1/hydro_var2) ->
+ * velocity U(t) interpolated at q(t) (eq. vel_interpolation) -> forward
+ * Euler q(t+1) = q(t) + qdot(t).  Asynchronous except
  * for a final status check (synchronises the stream, reads one int per
  * droplet).  Long runs replay a captured graph of a fixed number of steps.
  * The last step of every call also stores rho, U and F of every cell for
@@ -200,15 +204,21 @@ int iblb_diagnostics(iblb_ctx *ctx, int droplet, iblb_diag *out);
 
 /* Run every active droplet that has an interface until it comes to rest:
  * every check_every steps the largest normal node speed |qdot . n| of each
- * such droplet is compared with tol; a droplet below tol for `hold`
- * consecutive checks is frozen (iblb_set_active(ctx, d, 0)) and
+ * such droplet is compared with tol and, with angle_tol > 0, its angle from
+ * the half-height (eq. angleh; 2D: the circular-cap counterpart) with the
+ * angles of the hold checks before.  A droplet below tol for `hold`
+ * consecutive checks, whose angle moved by less than angle_tol (radians)
+ * over those checks, is frozen (iblb_set_active(ctx, d, 0)) and
  * steps_out[d] receives the number of steps it took.  A droplet that turns
  * unstable is frozen with steps_out[d] = -2; one still moving after
  * max_steps keeps -1; droplets without interface or frozen on entry get 0.
  * steps_out: host array of n_droplets entries.  Returns when every tracked
- * droplet is frozen or after max_steps steps. */
-int iblb_run_to_rest(iblb_ctx *ctx, double tol, int check_every, int hold, long long max_steps,
-                     long long *steps_out);
+ * droplet is frozen or after max_steps steps.  (The paper defines no rest
+ * criterion; the speed alone, angle_tol = 0, can sit above a small tol for
+ * a long time through parasitic currents, while the angle window asks for
+ * the shape itself to have stopped changing.) */
+int iblb_run_to_rest(iblb_ctx *ctx, double tol, double angle_tol, int check_every, int hold,
+                     long long max_steps, long long *steps_out);
 
 /* Variant of the lattice kernel (all compute the same result):
  *   0: 256x1 cells per block   3: 256x1, non-temporal stores

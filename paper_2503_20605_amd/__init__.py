@@ -208,12 +208,15 @@ class Solver:
         self._chk(self.lib.iblb_autotune(self.ctx, int(steps), cp, ctypes.byref(out), ms))
         return out.value, list(ms)
 
-    def run_to_rest(self, tol=1e-6, check_every=100, hold=10, max_steps=200000):
-        """Step until every droplet's interface is at rest (see iblb.h);
-        returns the per-droplet step counts (-1 still moving, -2 unstable)."""
+    def run_to_rest(self, tol=1e-6, check_every=100, hold=10, max_steps=200000, angle_tol_deg=0.0):
+        """Step until every droplet's interface is at rest (see iblb.h):
+        normal node speed below tol for `hold` checks and, with
+        angle_tol_deg > 0, the measured angle steady within it over those
+        checks.  Returns the per-droplet step counts (-1 still moving,
+        -2 unstable)."""
         out = (ctypes.c_longlong * self.n)()
-        self._chk(self.lib.iblb_run_to_rest(self.ctx, float(tol), int(check_every), int(hold),
-                                            int(max_steps), out))
+        self._chk(self.lib.iblb_run_to_rest(self.ctx, float(tol), math.radians(float(angle_tol_deg)),
+                                            int(check_every), int(hold), int(max_steps), out))
         return list(out)
 
     def set_graph_steps(self, k):

@@ -105,7 +105,7 @@ def load() -> ctypes.CDLL:
     lib.iblb_set_lb_variant.argtypes = [c_void_p, c_int, ip]
     lib.iblb_autotune.argtypes = [c_void_p, c_int, ctypes.c_char_p, ip, P(c_double)]
     lib.iblb_probe_copy.argtypes = [c_void_p, c_void_p, c_size_t, c_int, c_void_p, P(c_double)]
-    lib.iblb_run_to_rest.argtypes = [c_void_p, c_double, c_int, c_int, ctypes.c_longlong,
+    lib.iblb_run_to_rest.argtypes = [c_void_p, c_double, c_double, c_int, c_int, ctypes.c_longlong,
                                      P(ctypes.c_longlong)]
     lib.iblb_set_graph_steps.argtypes = [c_void_p, c_int]
     lib.iblb_set_active.argtypes = [c_void_p, c_int, c_int]

@@ -84,6 +84,10 @@ constexpr long long kPopRound = IBLB_POP_ROUND;
 #define IBLB_CHUNK_BUDGET 640
 #endif
 
+// Band flags per lattice row: one byte per 16-cell strip, padded to a
+// multiple of four so that a row's flags start on a 32-bit boundary.
+int strips_of(int nx) { return (ceil_div(nx, kStrip) + 3) / 4 * 4; }
+
 long long pop_stride(long long cells) {
     return (cells + kPopRound - 1) / kPopRound * kPopRound + kPopPad;
 }
@@ -169,7 +173,7 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
         L.pop_elems += (long long)Q * L.fst[d];
         if (L.pop_elems >= (1LL << 40)) { err = "population arrays too large"; return false; }
         L.flag_off[d] = L.flag_bytes;
-        L.flag_bytes += (long long)nz * p.ny * ceil_div(p.nx, kStrip);
+        L.flag_bytes += (long long)nz * p.ny * strips_of(p.nx);
         L.node_off[d] = L.ntot;
         L.ntot += nn[d];
         if (dim == 3) L.nchunks += nn[d];  // capacity: at worst one vertex per chunk
@@ -647,7 +651,7 @@ int reset_droplet(iblb_ctx* c, int d) {
     HIPCHK(c, hipMemsetAsync(c->ws + c->L.U + vo, 0, vb, c->stream));
     HIPCHK(c, hipMemsetAsync(c->ws + c->L.Fout + vo, 0, vb, c->stream));
     const iblb_params& p = c->params[d];
-    const size_t fb = (size_t)(c->dim == 3 ? p.nz : 1) * p.ny * ceil_div(p.nx, kStrip);
+    const size_t fb = (size_t)(c->dim == 3 ? p.nz : 1) * p.ny * strips_of(p.nx);
     HIPCHK(c, hipMemsetAsync(band_flags(c, 0) + D.flag_off, 0, fb, c->stream));
     HIPCHK(c, hipMemsetAsync(band_flags(c, 1) + D.flag_off, 0, fb, c->stream));
     hipLaunchKernelGGL(k_fill_f32, dim3(ceil_div(D.ncell, kBlock)), dim3(kBlock), 0, c->stream,
@@ -767,7 +771,7 @@ int iblb_create(int n, const iblb_params* P, const int* nn, const int* nt, int s
         D.nx = p.nx;
         D.ny = p.ny;
         D.nz = c->dim == 3 ? p.nz : 1;
-        D.nstrip = ceil_div(p.nx, kStrip);
+        D.nstrip = strips_of(p.nx);
         D.bcx = p.bc[0];
         D.bcy = p.bc[1];
         D.bcz = c->dim == 3 ? p.bc[2] : 0;
@@ -1294,10 +1298,10 @@ int iblb_diagnostics(iblb_ctx* c, int d, iblb_diag* out) {
     return IBLB_OK;
 }
 
-int iblb_run_to_rest(iblb_ctx* c, double tol, int check_every, int hold, long long max_steps,
-                     long long* steps_out) {
+int iblb_run_to_rest(iblb_ctx* c, double tol, double angle_tol, int check_every, int hold,
+                     long long max_steps, long long* steps_out) {
     if (!c) return IBLB_EINVAL;
-    if (!steps_out || !(tol > 0.0) || check_every < 1 || hold < 1 || max_steps < 1)
+    if (!steps_out || !(tol > 0.0) || !(angle_tol >= 0.0) || check_every < 1 || hold < 1 || max_steps < 1)
         return fail(c, IBLB_EINVAL, "run_to_rest: bad arguments");
     if (c->tiles_dirty) {
         int rc = rebuild_tiles(c);
@@ -1305,6 +1309,10 @@ int iblb_run_to_rest(iblb_ctx* c, double tol, int check_every, int hold, long lo
     }
     std::vector<int> below(c->n, 0);
     std::vector<DiagDev> r(c->n);
+    // measured angles of the last hold + 1 checks of every droplet (ring)
+    // and how many of them have been taken
+    std::vector<double> angles((size_t)c->n * (hold + 1), 0.0);
+    std::vector<int> nang(c->n, 0);
     int live = 0;
     for (int d = 0; d < c->n; ++d) {
         const bool tracked = c->drops[d].active && c->n_nodes[d] > 0;
@@ -1336,7 +1344,26 @@ int iblb_run_to_rest(iblb_ctx* c, double tol, int check_every, int hold, long lo
         for (int d = 0; d < c->n; ++d) {
             if (steps_out[d] != -1) continue;
             below[d] = r[d].max_un < tol ? below[d] + 1 : 0;
-            if (below[d] >= hold) {
+            bool steady = true;
+            if (angle_tol > 0.0) {
+                // the angle from the half-height must also have stayed within
+                // angle_tol over the window: this check and the hold before
+                double* a = angles.data() + (size_t)d * (hold + 1);
+                for (int k = hold; k > 0; --k) a[k] = a[k - 1];
+                a[0] = angle_from_height(c->dim, r[d].volume, r[d].max_h - r[d].min_h);
+                nang[d] = std::min(nang[d] + 1, hold + 1);
+                if (nang[d] <= hold) {
+                    steady = false;
+                } else {
+                    double lo = a[0], hi = a[0];
+                    for (int k = 1; k <= hold; ++k) {
+                        lo = std::min(lo, a[k]);
+                        hi = std::max(hi, a[k]);
+                    }
+                    steady = hi - lo < angle_tol;  // false for a NaN angle
+                }
+            }
+            if (below[d] >= hold && steady) {
                 steps_out[d] = c->step - start;
                 iblb_set_active(c, d, 0);
                 --live;

@@ -30,9 +30,9 @@
 //
 // The force density F and the velocity U are dense per-cell arrays, but the
 // lattice kernel touches them only inside the interface band: the spreading
-// kernel raises a one-byte flag for every 64-cell x strip that receives a
-// tap, and only flagged cells read F, write U for the interpolation and
-// clear F.  The spread F is accumulated in fixed point (64-bit integers of
+// kernel raises a one-byte flag for every 16-cell x strip that receives a
+// tap, and only the cells of flagged strips read F, write U for the
+// interpolation and clear F (where it is not zero already).  The spread F is accumulated in fixed point (64-bit integers of
 // 2^-40 force units, see fq_of), so its value does not depend on the order
 // in which the nodes' contributions arrive; a prescribed force field is kept
 // in fp32 in an array of its own.  The flags come in two sets, one per step parity: a lattice
@@ -49,7 +49,8 @@
 namespace iblb {
 
 constexpr int kBlock = 256;   // threads per block of every kernel
-constexpr int kStrip = 64;    // cells per band flag (one wavefront)
+constexpr int kStrip = 16;    // cells per band flag (a quarter of a wavefront)
+constexpr int kStripShift = 4;
 
 struct DropDev {
     int nx, ny, nz, nstrip;
@@ -262,8 +263,18 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
     // populations: loads return in order, so waiting for the flag then does
     // not wait for the populations, and a band wavefront's F loads overlap
     // them instead of following them
-    const long long fi = D.flag_off + (long long)(z * ny + y) * D.nstrip + (x >> 6);
-    const int flag = D.force_mode == 1 ? 1 : (int)flags_all[fi];
+    // A row's flags are padded to a multiple of four bytes, so a tiled
+    // wavefront (64 cells of one row, starting at a multiple of 64) finds
+    // its four strips' flags in one aligned 32-bit word.
+    const long long fi = D.flag_off + (long long)(z * ny + y) * D.nstrip + (x >> kStripShift);
+    int flag;
+    if constexpr (FLAT) {
+        flag = D.force_mode == 1 ? 1 : (int)flags_all[fi];
+    } else {
+        const uint32_t w = D.force_mode == 1 ? 0xffffffffu
+                                             : *reinterpret_cast<const uint32_t*>(flags_all + (fi & ~3LL));
+        flag = (int)((w >> (8 * (int)(fi & 3))) & 0xffu);
+    }
     // Populations move through buffer instructions (32-bit lane offsets,
     // base in scalar registers): one descriptor per opposite pair (i,
     // opp(i)), based at the lower index, so that a lane offset never
@@ -290,29 +301,37 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
     const float* __restrict__ F = F_all + (long long)DIM * D.c_off;
     unsigned long long* __restrict__ Fq = Fq_all + (long long)DIM * D.c_off;
     float* __restrict__ U = U_all + (long long)DIM * D.c_off;
-    bool forced;
+    // band: this lane's strip is flagged (band); a wavefront holding any
+    // band lane adds the Guo source on every lane (exactly zero where F is)
+    bool band, forced;
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+    unsigned long long q0 = 0, q1 = 0, q2 = 0;
     if (D.force_mode == 1) {
-        forced = true;
+        band = forced = true;
     } else {
         // band flags of this step (set by the spreading); those of the
         // other parity, read by the step before, are cleared for the
         // spreading of the next step by the first lane of each strip
-        if constexpr (FLAT)
-            forced = flag != 0;
-        else  // every lane of a wavefront lies in the same strip
-            forced = __builtin_amdgcn_readfirstlane(flag) != 0;
-        if (flags_clr && (x & 63) == 0) flags_clr[fi] = 0;
+        band = flag != 0;
+        forced = __builtin_amdgcn_ballot_w64(band) != 0;
+        if constexpr (FLAT) {
+            if (flags_clr && (x & (kStrip - 1)) == 0) flags_clr[fi] = 0;
+        } else {
+            if (flags_clr && (x & 63) == 0) *reinterpret_cast<uint32_t*>(flags_clr + fi) = 0u;
+        }
     }
-    if (forced) {
+    if (band) {
         if (D.force_mode == 1) {
             Fx = F[cell];
             Fy = F[ncell + cell];
             if (DIM == 3) Fz = F[2 * ncell + cell];
         } else {
-            Fx = fq_value(Fq[cell]);
-            Fy = fq_value(Fq[ncell + cell]);
-            if (DIM == 3) Fz = fq_value(Fq[2 * ncell + cell]);
+            q0 = Fq[cell];
+            q1 = Fq[ncell + cell];
+            if (DIM == 3) q2 = Fq[2 * ncell + cell];
+            Fx = fq_value(q0);
+            Fy = fq_value(q1);
+            Fz = fq_value(q2);
         }
     }
     const Moments<DIM> M(f, Fx, Fy, Fz);
@@ -337,14 +356,14 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         C::template store_buf<NT ? kBufNT : 0>(rd, (unsigned)((i - lo) * fst + cell) * SB, fn);
     }
 
-    if (forced && D.force_mode == 0) {
+    if (band && D.force_mode == 0) {
         // interface band: keep U for the interpolation, hand back a clean F
         U[cell] = ux;
         U[ncell + cell] = uy;
         if (DIM == 3) U[2 * ncell + cell] = uz;
-        Fq[cell] = 0;
-        Fq[ncell + cell] = 0;
-        if (DIM == 3) Fq[2 * ncell + cell] = 0;
+        if (q0) Fq[cell] = 0;
+        if (q1) Fq[ncell + cell] = 0;
+        if (DIM == 3 && q2) Fq[2 * ncell + cell] = 0;
     }
     if (full) {
         float* __restrict__ Fo = Fout_all + (long long)DIM * D.c_off;
@@ -707,7 +726,7 @@ __device__ __forceinline__ void spread_lane(const DropDev& D, const NodeArrays& 
                 fine = false;
         }
         if (!fine) atomicOr(status_d, 2);
-        flags_all[D.flag_off + row * D.nstrip + (ix >> 6)] = 1;
+        flags_all[D.flag_off + row * D.nstrip + (ix >> kStripShift)] = 1;
     }
     if (want_dropped) {
 #pragma unroll
@@ -1195,7 +1214,7 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restr
                 else
                     fine = false;
             }
-            flags_all[D.flag_off + row * D.nstrip + (gx >> 6)] = 1;
+            flags_all[D.flag_off + row * D.nstrip + (gx >> kStripShift)] = 1;
         }
         if (want_dropped) {
 #pragma unroll
@@ -1222,7 +1241,7 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restr
             const unsigned long long v = box[a * kBoxCells + c];
             if (v != 0) atomicAdd(Fq + a * D.ncell + cell, v);
         }
-        flags_all[D.flag_off + row * D.nstrip + (gx >> 6)] = 1;
+        flags_all[D.flag_off + row * D.nstrip + (gx >> kStripShift)] = 1;
     }
 }
 

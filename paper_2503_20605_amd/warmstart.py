@@ -148,7 +148,15 @@ def equilibrium_state(s, d, p):
     return np.concatenate([(r - rcap) / rc, U_SCALE * Uc.ravel()]), area
 
 
-def generate(draws, storage=1, max_steps=100000, tol=1e-6, batch=256, log=print):
+def rest_args(tol, rest):
+    """Arguments of Solver.run_to_rest: the normal-speed criterion alone
+    (checks every 100 steps, held for 10) unless `rest` gives others."""
+    a = dict(tol=tol, check_every=100, hold=10, angle_tol_deg=0.0)
+    a.update(rest or {})
+    return a
+
+
+def generate(draws, storage=1, max_steps=100000, tol=1e-6, batch=256, log=print, rest=None):
     """Run every draw from its 90-degree start to rest (or max_steps) and
     return (inputs (n, 4), targets (n, N_OUT), steps (n,))."""
     import torch
@@ -161,7 +169,7 @@ def generate(draws, storage=1, max_steps=100000, tol=1e-6, batch=256, log=print)
         for d, w in enumerate(part):
             s.set_interface(d, w.nodes)
         t0 = time.perf_counter()
-        steps = s.run_to_rest(tol=tol, check_every=100, hold=10, max_steps=max_steps)
+        steps = s.run_to_rest(max_steps=max_steps, **rest_args(tol, rest))
         torch.cuda.synchronize()
         log(f"[generate] droplets {b0}..{b0 + len(part) - 1}: {time.perf_counter() - t0:.1f} s, "
             f"at rest {sum(1 for x in steps if x > 0)}/{len(part)}")
@@ -272,7 +280,7 @@ def inside_mask(q, ny, nx):
     return inside
 
 
-def run_from(draws, starts, storage, max_steps, tol=1e-6, log=print):
+def run_from(draws, starts, storage, max_steps, tol=1e-6, log=print, rest=None):
     """Run the batch to rest from given starts (None: the 90-degree caps at
     rest).  Returns wall seconds, steps, measured angles, final outlines."""
     import torch
@@ -291,7 +299,7 @@ def run_from(draws, starts, storage, max_steps, tol=1e-6, log=print):
             s.init_fields(d, rho[None].astype(np.float32), U[:, None].astype(np.float32))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    steps = s.run_to_rest(tol=tol, check_every=100, hold=10, max_steps=max_steps)
+    steps = s.run_to_rest(max_steps=max_steps, **rest_args(tol, rest))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     dg = s.diagnostics(-1)
@@ -305,6 +313,80 @@ def shape_error(q_start, q_final, ref):
     a = radial_profile(q_start, ref)
     b = radial_profile(q_final, ref)
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+def evaluate_arms(draws, m, scale, max_steps, log=print, rest=None):
+    """Run the draws to rest four ways: plain fp32 from the 90-degree cap,
+    fp16 from the 90-degree cap, fp16 from the analytic equal-area cap, fp16
+    from the network's start; plus the learned arm with every start that
+    turned unstable rerun from the analytic cap (its wall time charged to
+    the learned arm)."""
+    res = {}
+    arms = [("plain_f32_90deg", 0, None), ("f16_90deg", 1, None),
+            ("f16_cap_prior", 1, cap_starts(draws)), ("f16_learned", 1, predict_starts(m, scale, draws))]
+    for name, storage, starts in arms:
+        wall, steps, ang, finals = run_from(draws, starts, storage, max_steps, log=log, rest=rest)
+        res[name] = dict(wall=wall, steps=steps, theta=ang, finals=finals, starts=starts)
+        log(f"[evaluate] {name}: {wall:.1f} s, at rest {sum(1 for x in steps if x > 0)}/"
+            f"{len(steps)}")
+    lr = res["f16_learned"]
+    bad = [i for i, x in enumerate(lr["steps"]) if x == -2]
+    fb = dict(lr, steps=list(lr["steps"]), theta=list(lr["theta"]), finals=list(lr["finals"]),
+              fallback=len(bad))
+    if bad:
+        sub = [draws[i] for i in bad]
+        wall2, steps2, ang2, fin2 = run_from(sub, cap_starts(sub), 1, max_steps, log=log, rest=rest)
+        fb["wall"] = lr["wall"] + wall2
+        for k, i in enumerate(bad):
+            fb["steps"][i], fb["theta"][i], fb["finals"][i] = steps2[k], ang2[k], fin2[k]
+        log(f"[evaluate] f16_learned_with_fallback: {len(bad)} droplets rerun from the cap, "
+            f"+{wall2:.1f} s")
+    res["f16_learned_with_fallback"] = fb
+    return res
+
+
+def summarize(draws, res, max_steps):
+    """Per arm: wall time, droplets at rest, paired step and work ratios
+    against the plain arm over the droplets at rest in both, angles against
+    the plain arm, the start's shape error against the plain final shape."""
+    plain = res["plain_f32_90deg"]
+    summary = {"droplets": len(draws), "max_steps": max_steps}
+    for name, r in res.items():
+        conv = [i for i, x in enumerate(r["steps"]) if x > 0]
+        both = [i for i in conv if plain["steps"][i] > 0]
+        dth = np.abs(np.array(r["theta"])[both] - np.array(plain["theta"])[both]) if both \
+            else np.zeros(0)
+        e = {"wall_s": round(r["wall"], 2), "at_rest": len(conv),
+             "fallback_reruns": r.get("fallback", 0),
+             "unstable": sum(1 for x in r["steps"] if x == -2),
+             "median_steps": float(np.median([r["steps"][i] for i in conv])) if conv else None,
+             "theta_vs_plain_within_1deg": int((dth < 1.0).sum()),
+             "theta_vs_plain_compared": len(both),
+             "theta_vs_plain_max_deg": round(float(dth.max()), 3) if len(dth) else None}
+        if both:
+            ratio = [r["steps"][i] / plain["steps"][i] for i in both]
+            cells = [draws[i].params.nx * draws[i].params.ny for i in both]
+            e["paired_at_rest"] = len(both)
+            e["paired_median_step_ratio"] = round(float(np.median(ratio)), 4)
+            e["paired_work_ratio"] = round(
+                sum(c * r["steps"][i] for c, i in zip(cells, both))
+                / sum(c * plain["steps"][i] for c, i in zip(cells, both)), 4)
+        starts = r["starts"] if r["starts"] is not None else [(w.nodes, None, None) for w in draws]
+        errs = []
+        for i, w in enumerate(draws):
+            p = w.params
+            ref, _, _ = reference(math.radians(p.theta_eq_deg), polygon_area(w.nodes), p.xi, p.nx)
+            try:
+                errs.append(shape_error(starts[i][0], plain["finals"][i], ref))
+            except ValueError:
+                pass
+        e["start_shape_error_median"] = float(np.median(errs)) if errs else None
+        summary[name] = e
+    summary["speedup_learned_f16_vs_plain_f32"] = round(
+        res["plain_f32_90deg"]["wall"] / res["f16_learned"]["wall"], 3)
+    summary["speedup_learned_f16_with_fallback_vs_plain_f32"] = round(
+        res["plain_f32_90deg"]["wall"] / res["f16_learned_with_fallback"]["wall"], 3)
+    return summary
 
 
 def main(argv):
@@ -341,78 +423,8 @@ def main(argv):
         net = np.load(os.path.join(out_dir, "net.npz"))
         m.set_params(net["params"])
         scale = (net["mu"], net["sd"])
-        res = {}
-        arms = [("plain_f32_90deg", 0, None), ("f16_90deg", 1, None),
-                ("f16_cap_prior", 1, cap_starts(draws)), ("f16_learned", 1, predict_starts(m, scale, draws))]
-        for name, storage, starts in arms:
-            wall, steps, ang, finals = run_from(draws, starts, storage, max_steps, log=log)
-            res[name] = dict(wall=wall, steps=steps, theta=ang, finals=finals, starts=starts)
-            log(f"[evaluate] {name}: {wall:.1f} s, at rest {sum(1 for x in steps if x > 0)}/"
-                f"{len(steps)}")
-        # production use of the learned start: droplets whose learned start
-        # turned unstable are run again from the analytic cap, and that
-        # second batch's wall time is charged to the learned arm
-        lr = res["f16_learned"]
-        bad = [i for i, x in enumerate(lr["steps"]) if x == -2]
-        fb = dict(lr, steps=list(lr["steps"]), theta=list(lr["theta"]), finals=list(lr["finals"]),
-                  fallback=len(bad))
-        if bad:
-            sub = [draws[i] for i in bad]
-            wall2, steps2, ang2, fin2 = run_from(sub, cap_starts(sub), 1, max_steps, log=log)
-            fb["wall"] = lr["wall"] + wall2
-            for k, i in enumerate(bad):
-                fb["steps"][i], fb["theta"][i], fb["finals"][i] = steps2[k], ang2[k], fin2[k]
-            log(f"[evaluate] f16_learned_with_fallback: {len(bad)} droplets rerun from the cap, "
-                f"+{wall2:.1f} s")
-        res["f16_learned_with_fallback"] = fb
-        plain = res["plain_f32_90deg"]
-        summary = {"droplets": n_test, "max_steps": max_steps}
-        for name, r in res.items():
-            conv = [i for i, x in enumerate(r["steps"]) if x > 0]
-            both = [i for i in conv if plain["steps"][i] > 0]
-            dth = np.abs(np.array(r["theta"])[both] - np.array(plain["theta"])[both]) if both \
-                else np.zeros(0)
-            e = {"wall_s": round(r["wall"], 2), "at_rest": len(conv),
-                 "fallback_reruns": r.get("fallback", 0),
-                 "unstable": sum(1 for x in r["steps"] if x == -2),
-                 "median_steps": float(np.median([r["steps"][i] for i in conv])) if conv else None,
-                 "theta_vs_plain_within_1deg": int((dth < 1.0).sum()),
-                 "theta_vs_plain_compared": len(both),
-                 "theta_vs_plain_max_deg": round(float(dth.max()), 3) if len(dth) else None}
-            both_rest = [i for i in conv if plain["steps"][i] > 0]
-            if both_rest:
-                ratio = [r["steps"][i] / plain["steps"][i] for i in both_rest]
-                cells = [draws[i].params.nx * draws[i].params.ny for i in both_rest]
-                e["paired_at_rest"] = len(both_rest)
-                e["paired_median_step_ratio"] = round(float(np.median(ratio)), 4)
-                e["paired_work_ratio"] = round(
-                    sum(c * r["steps"][i] for c, i in zip(cells, both_rest))
-                    / sum(c * plain["steps"][i] for c, i in zip(cells, both_rest)), 4)
-            if r["starts"] is not None:
-                errs = []
-                for i, w in enumerate(draws):
-                    p = w.params
-                    ref, _, _ = reference(math.radians(p.theta_eq_deg), polygon_area(w.nodes),
-                                          p.xi, p.nx)
-                    try:
-                        errs.append(shape_error(r["starts"][i][0], plain["finals"][i], ref))
-                    except ValueError:
-                        pass
-                e["start_shape_error_median"] = float(np.median(errs)) if errs else None
-            summary[name] = e
-        errs = []
-        for i, w in enumerate(draws):
-            p = w.params
-            ref, _, _ = reference(math.radians(p.theta_eq_deg), polygon_area(w.nodes), p.xi, p.nx)
-            try:
-                errs.append(shape_error(w.nodes, plain["finals"][i], ref))
-            except ValueError:
-                pass
-        summary["plain_f32_90deg"]["start_shape_error_median"] = float(np.median(errs)) if errs else None
-        summary["speedup_learned_f16_vs_plain_f32"] = round(
-            res["plain_f32_90deg"]["wall"] / res["f16_learned"]["wall"], 3)
-        summary["speedup_learned_f16_with_fallback_vs_plain_f32"] = round(
-            res["plain_f32_90deg"]["wall"] / res["f16_learned_with_fallback"]["wall"], 3)
+        res = evaluate_arms(draws, m, scale, max_steps, log=log)
+        summary = summarize(draws, res, max_steps)
         json.dump(summary, open(os.path.join(out_dir, "evaluate.json"), "w"), indent=1)
         log(json.dumps(summary))
     else:

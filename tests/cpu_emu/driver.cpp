@@ -210,7 +210,7 @@ int main(int argc, char** argv) {
         long long mx = 0;
         sscanf(cfg["rest"].c_str(), "%lf,%d,%d,%lld", &tol, &check, &hold, &mx);
         std::vector<long long> so(n);
-        step_rc = iblb_run_to_rest(ctx, tol, check, hold, mx, so.data());
+        step_rc = iblb_run_to_rest(ctx, tol, 0.0, check, hold, mx, so.data());
         save("rest_steps.bin", so.data(), n);
     }
     if (geti("mask", 0) && step_rc == 0 && (rc = save_masks("inside1_"))) return rc;

@@ -84,7 +84,7 @@ struct Stream { int id; };
 struct Graph { std::vector<std::function<void()>> ops; };
 struct Event { int id; };
 
-enum State { READY, AT_WAVE_FIRST, AT_WAVE_XOR, AT_WAVE_MFMA, AT_BLOCK, DONE };
+enum State { READY, AT_WAVE_FIRST, AT_WAVE_XOR, AT_WAVE_MFMA, AT_WAVE_BALLOT, AT_BLOCK, DONE };
 
 struct Fiber {
     ucontext_t ctx;
@@ -173,6 +173,11 @@ inline void __syncthreads() { ::hipemu::block_barrier(); }
 
 inline int __builtin_amdgcn_readfirstlane(int v) {
     return ::hipemu::unpack<int>(::hipemu::wave_op(::hipemu::AT_WAVE_FIRST, ::hipemu::pack(v), 0));
+}
+
+// mask of the wavefront's active lanes whose predicate is true (bit = lane)
+inline unsigned long long __builtin_amdgcn_ballot_w64(bool v) {
+    return ::hipemu::wave_op(::hipemu::AT_WAVE_BALLOT, v ? 1u : 0u, 0);
 }
 
 template <typename T>
@@ -538,9 +543,10 @@ inline void run_block(const std::function<void()>& fn) {
                 ++live;
                 if (first < 0) { first = t; kind = s; }
                 same &= s == kind;
-                kindc += (s == AT_WAVE_FIRST || s == AT_WAVE_XOR || s == AT_WAVE_MFMA);
+                kindc += (s == AT_WAVE_FIRST || s == AT_WAVE_XOR || s == AT_WAVE_MFMA || s == AT_WAVE_BALLOT);
             }
-            if (!live || !same || (kind != AT_WAVE_FIRST && kind != AT_WAVE_XOR && kind != AT_WAVE_MFMA))
+            if (!live || !same ||
+                (kind != AT_WAVE_FIRST && kind != AT_WAVE_XOR && kind != AT_WAVE_MFMA && kind != AT_WAVE_BALLOT))
                 continue;
             if (kind == AT_WAVE_MFMA) {
                 if (live != 64) {
@@ -570,10 +576,16 @@ inline void run_block(const std::function<void()>& fn) {
                 resolved = true;
                 continue;
             }
+            uint64_t ballot = 0;
+            if (kind == AT_WAVE_BALLOT)
+                for (int t = lo; t < hi; ++t)
+                    if (r.fibers[t].st != DONE && r.fibers[t].in) ballot |= 1ull << (t - lo);
             for (int t = lo; t < hi; ++t) {
                 Fiber& f = r.fibers[t];
                 if (f.st == DONE) continue;
-                if (kind == AT_WAVE_FIRST) {
+                if (kind == AT_WAVE_BALLOT) {
+                    f.out = ballot;
+                } else if (kind == AT_WAVE_FIRST) {
                     f.out = r.fibers[first].in;
                 } else {
                     const int p = lo + ((t - lo) ^ f.mask);

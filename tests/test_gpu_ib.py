@@ -314,18 +314,25 @@ def test_interface_validation():
         gpu_solver([p], [q])
 
 
-def test_run_to_rest_state_matches_oracle():
+@pytest.mark.parametrize("angle_tol_deg", [0.0, 0.2])
+def test_run_to_rest_state_matches_oracle(angle_tol_deg):
     """Batch run to rest: each droplet is frozen at the check where its
-    normal node speed stayed below the tolerance; its frozen state equals
-    the oracle after the reported number of steps."""
+    normal node speed stayed below the tolerance (and, with an angle
+    tolerance, its angle from the half-height stayed within it over those
+    checks); its frozen state equals the oracle after the reported number
+    of steps."""
     ps = [wl.Params(dim=2, nx=96, ny=40, tau=1.0, sigma=0.01, theta_eq_deg=70.0, xi=2.0),
           wl.Params(dim=2, nx=64, ny=48, tau=0.7, sigma=0.006, theta_eq_deg=120.0, xi=2.0)]
     qs = [wl.cap_polygon(10.0, 90.0, 2.0, 79, 48.0), wl.cap_polygon(8.0, 90.0, 2.0, 63, 30.0)]
     s = gpu_solver(ps, qs)
     s.set_graph_steps(10)
-    steps = s.run_to_rest(tol=2e-4, check_every=50, hold=3, max_steps=4000)
+    steps = s.run_to_rest(tol=2e-4, check_every=50, hold=3, max_steps=4000, angle_tol_deg=angle_tol_deg)
     print("[rest] steps", steps, flush=True)
     assert all(n > 0 for n in steps)
+    assert all(n % 50 == 0 for n in steps)
+    if angle_tol_deg > 0.0:
+        # the angle window needs hold + 1 = 4 checks of angles
+        assert all(n >= 200 for n in steps)
     for d in range(2):
         g = collect(s, d, 2)
         r = o.run(ps[d], qs[d], steps[d])
