@@ -109,6 +109,8 @@ def parse():
                     help="time to equilibrium of held-out batch droplets, plain fp32 against fp16 "
                          "storage with the learned warm start, instead of the step rate")
     ap.add_argument("--droplets", type=int, default=256)
+    ap.add_argument("--dump", default=None,
+                    help="--tte: write every droplet's steps and angles per arm to this JSON file")
     ap.add_argument("--train-draws", type=int, default=512,
                     help="seeded draws whose equilibria train the warm-start network (--tte)")
     ap.add_argument("--max-steps", type=int, default=200000)
@@ -316,6 +318,17 @@ def tte(a):
     m.close()
     summary = ws.summarize(draws, res, a.max_steps)
     cells = sum(w.params.nx * w.params.ny for w in draws)
+    if a.dump:
+        # per-droplet record of every arm, for checks against the planar
+        # equilibrium outline (tests/report_tte_planar.py)
+        rec = {"rest_criterion": REST, "max_steps": a.max_steps,
+               "draws": [{"nx": w.params.nx, "ny": w.params.ny, "tau": w.params.tau, "sigma": w.params.sigma,
+                          "theta_eq_deg": w.params.theta_eq_deg, "xi": w.params.xi,
+                          "area": float(ws.polygon_area(w.nodes))} for w in draws],
+               "arms": {k: {"steps": [int(x) for x in r["steps"]], "theta_deg": [float(x) for x in r["theta"]],
+                            "wall_s": r["wall"]} for k, r in res.items()}}
+        with open(a.dump, "w") as fh:
+            json.dump(rec, fh)
     print(json.dumps({"metric": "time to equilibrium of held-out batch droplets: plain fp32 from the "
                                 "90-degree cap against fp16 storage with the learned warm start",
                       "rest_criterion": REST, "droplets": len(draws), "cells": cells,

@@ -39,7 +39,8 @@ struct MlpLayout {
     std::vector<int> w;
     std::vector<long long> woff, boff;  // offsets in the packed parameter vector
     long long P = 0;
-    size_t master, grad, m, v, wb, xb, partial, dHf, dZf, dZb, total;
+    size_t master, grad, m, v, wb, xb, partial, total;
+    size_t dZf[2], dZb[2];  // output-side gradients of two consecutive layers, used in turn
     std::vector<size_t> Z, H;  // Z[l]: layer l output (fp32); H[l]: layer l input (bf16)
 };
 
@@ -77,9 +78,10 @@ bool mlp_plan(int L, const int* widths, int B, MlpLayout& Y, std::string& err) {
         Y.H[l] = take(2ull * B * Y.w[l]);
     }
     Y.xb = Y.H[0];
-    Y.dHf = take(4ull * B * Y.maxw);
-    Y.dZf = take(4ull * B * Y.maxw);
-    Y.dZb = take(2ull * B * Y.maxw);
+    for (int h = 0; h < 2; ++h) {
+        Y.dZf[h] = take(4ull * B * Y.maxw);
+        Y.dZb[h] = take(2ull * B * Y.maxw);
+    }
     Y.partial = take(8ull * mlp_cdiv((long long)B * Y.w[L], kMlpBlock));
     Y.total = o;
     return true;
@@ -115,24 +117,62 @@ int mlp_fail(iblb_mlp* c, int code, const std::string& msg) {
             return mlp_fail(ctx, IBLB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// With split_k, K is divided over enough workgroups to give the device at
-// least ~256 of them (at most 16 pieces, each a multiple of the LDS stage);
-// the pieces add into Cf (M x N, leading dimension N), which the caller has
-// zeroed.  Only plain products (no bias, no activation) split.
-void gemm(const iblb_mlp* c, const uint16_t* A, long long sai, long long sak, const uint16_t* B,
-          long long sbk, long long sbj, float* Cf, uint16_t* Hb, long long ldc, const float* bias,
-          int M, int N, int K, int act, bool split_k = false) {
+// One operand of a product: its elements, leading dimension and layout
+// (t = 0: k contiguous, t = 1: the row / column index contiguous).
+struct Operand {
+    const uint16_t* p;
+    long long ld;
+    int t;
+};
+
+// 16-byte pieces need a contiguous extent and leading dimension that are
+// multiples of 8 elements and a 16-byte aligned base.
+int pieces_ok(const Operand& X, int ext) {
+    return X.ld % 8 == 0 && ext % 8 == 0 && (reinterpret_cast<uintptr_t>(X.p) & 15) == 0;
+}
+
+template <int KP>
+void launch_gemm(const iblb_mlp* c, dim3 grid, const Operand& A, const Operand& B, float* Cf, uint16_t* Hb,
+                 long long ldc, const float* bias, const float* Zpre, int M, int N, int K, int act, int kc,
+                 int avec, int bvec) {
+    const dim3 block(kMlpBlock);
+    const int sel = 2 * A.t + B.t;
+    if (sel == 0)
+        hipLaunchKernelGGL((k_gemm_bf16<0, 0, KP>), grid, block, 0, c->stream, A.p, A.ld, B.p, B.ld, Cf, Hb,
+                           ldc, bias, Zpre, M, N, K, act, kc, avec, bvec);
+    else if (sel == 1)
+        hipLaunchKernelGGL((k_gemm_bf16<0, 1, KP>), grid, block, 0, c->stream, A.p, A.ld, B.p, B.ld, Cf, Hb,
+                           ldc, bias, Zpre, M, N, K, act, kc, avec, bvec);
+    else if (sel == 2)
+        hipLaunchKernelGGL((k_gemm_bf16<1, 0, KP>), grid, block, 0, c->stream, A.p, A.ld, B.p, B.ld, Cf, Hb,
+                           ldc, bias, Zpre, M, N, K, act, kc, avec, bvec);
+    else
+        hipLaunchKernelGGL((k_gemm_bf16<1, 1, KP>), grid, block, 0, c->stream, A.p, A.ld, B.p, B.ld, Cf, Hb,
+                           ldc, bias, Zpre, M, N, K, act, kc, avec, bvec);
+}
+
+// C (M x N, leading dimension ldc) = A B.  With split_k, K is divided over
+// enough workgroups to give the device at least ~256 of them (at most 16
+// pieces, each a multiple of the LDS panel); the pieces add into Cf, which
+// the caller has zeroed.  Only plain products (no bias, act 0) split.
+// Panels of 256 k (one fetch for the usual K = 256) unless K is short.
+void gemm(const iblb_mlp* c, const Operand& A, const Operand& B, float* Cf, uint16_t* Hb, long long ldc,
+          const float* bias, const float* Zpre, int M, int N, int K, int act, bool split_k = false) {
+    const int KP = K > 128 ? 256 : 128;
     const long long tiles = mlp_cdiv(N, 64) * mlp_cdiv(M, 64);
     int splits = 1;
-    if (split_k && !bias && !act) {
+    if (split_k && !bias && act == 0) {
         const long long want = mlp_cdiv(256, tiles);
-        splits = (int)std::max(1LL, std::min({want, 16LL, mlp_cdiv(K, 2 * kGemmK)}));
+        splits = (int)std::max(1LL, std::min({want, 16LL, mlp_cdiv(K, KP)}));
     }
-    const int kc = (int)(mlp_cdiv(mlp_cdiv(K, splits), kGemmK) * kGemmK);
+    const int kc = (int)(mlp_cdiv(mlp_cdiv(K, splits), KP) * KP);
     splits = (int)mlp_cdiv(K, kc);
-    const dim3 grid((unsigned)mlp_cdiv(N, 64), (unsigned)mlp_cdiv(M, 64), (unsigned)splits), block(kMlpBlock);
-    hipLaunchKernelGGL(k_gemm_bf16, grid, block, 0, c->stream, A, sai, sak, B, sbk, sbj, Cf, Hb, ldc,
-                       bias, M, N, K, act, kc);
+    const int avec = pieces_ok(A, A.t == 0 ? K : M), bvec = pieces_ok(B, B.t == 0 ? K : N);
+    const dim3 grid((unsigned)mlp_cdiv(N, 64), (unsigned)mlp_cdiv(M, 64), (unsigned)splits);
+    if (KP == 256)
+        launch_gemm<256>(c, grid, A, B, Cf, Hb, ldc, bias, Zpre, M, N, K, act, kc, avec, bvec);
+    else
+        launch_gemm<128>(c, grid, A, B, Cf, Hb, ldc, bias, Zpre, M, N, K, act, kc, avec, bvec);
 }
 
 // forward pass of `batch` rows from device fp32 input x
@@ -144,9 +184,10 @@ int mlp_forward(iblb_mlp* c, const float* d_x, int batch) {
     for (int l = 0; l < Y.L; ++l) {
         const int in = Y.w[l], out = Y.w[l + 1];
         const bool act = l < Y.L - 1;
-        gemm(c, c->at<uint16_t>(Y.H[l]), in, 1, c->at<uint16_t>(Y.wb) + Y.woff[l], out, 1,
+        // Z = H W + b: H (batch x in) k-contiguous, W (in x out) row-major
+        gemm(c, {c->at<uint16_t>(Y.H[l]), in, 0}, {c->at<uint16_t>(Y.wb) + Y.woff[l], out, 1},
              c->at<float>(Y.Z[l]), act ? c->at<uint16_t>(Y.H[l + 1]) : nullptr, out,
-             c->at<float>(Y.master) + Y.boff[l], batch, out, in, act ? 1 : 0);
+             c->at<float>(Y.master) + Y.boff[l], nullptr, batch, out, in, act ? 1 : 0);
     }
     MLPCHK(c, hipGetLastError());
     return IBLB_OK;
@@ -313,8 +354,8 @@ int iblb_mlp_forward_noalloc(iblb_mlp* c, const float* d_x, int batch, float* d_
         const int in = Y.w[l], out = Y.w[l + 1];
         const bool last = l == Y.L - 1;
         uint16_t* hb = last ? nullptr : h[l & 1];
-        gemm(c, in_b, in, 1, c->at<uint16_t>(Y.wb) + Y.woff[l], out, 1, last ? d_y : z, hb, out,
-             c->at<float>(Y.master) + Y.boff[l], batch, out, in, last ? 0 : 1);
+        gemm(c, {in_b, in, 0}, {c->at<uint16_t>(Y.wb) + Y.woff[l], out, 1}, last ? d_y : z, hb, out,
+             c->at<float>(Y.master) + Y.boff[l], nullptr, batch, out, in, last ? 0 : 1);
         in_b = hb;
     }
     MLPCHK(c, hipGetLastError());
@@ -331,32 +372,27 @@ int iblb_mlp_gradients(iblb_mlp* c, const float* d_x, const float* d_t, int batc
     const int L = Y.L;
     const long long ny = (long long)batch * Y.w[L];
     const int nblk = (int)mlp_cdiv(ny, kMlpBlock);
-    float* dZf = c->at<float>(Y.dZf);
-    uint16_t* dZb = c->at<uint16_t>(Y.dZb);
-    float* dHf = c->at<float>(Y.dHf);
     float* grad = c->at<float>(Y.grad);
+    // the gradients of every layer are accumulated atomically: zeroed first
+    hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)mlp_cdiv(Y.P, kMlpBlock)), dim3(kMlpBlock), 0, c->stream, grad,
+                       Y.P);
+    // dZ of layer l lives in buffer pair (L - 1 - l) % 2
     hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(kMlpBlock), 0, c->stream, (const float*)c->at<float>(Y.Z[L - 1]),
-                       d_t, dZf, dZb, c->at<double>(Y.partial), ny);
+                       d_t, c->at<float>(Y.dZf[0]), c->at<uint16_t>(Y.dZb[0]), c->at<double>(Y.partial), ny);
     for (int l = L - 1; l >= 0; --l) {
         const int in = Y.w[l], out = Y.w[l + 1];
-        // bias: column sums of dZ; weights: H^T dZ; input: dZ W^T.  The
-        // layer's weight and bias gradients (contiguous) are zeroed first:
-        // both are accumulated atomically.
-        const long long nwb = (long long)in * out + out;
-        hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)mlp_cdiv(nwb, kMlpBlock)), dim3(kMlpBlock), 0, c->stream,
-                           grad + Y.woff[l], nwb);
+        const int h = (L - 1 - l) & 1;
+        const float* dZf = c->at<float>(Y.dZf[h]);
+        const uint16_t* dZb = c->at<uint16_t>(Y.dZb[h]);
+        // bias: column sums of dZ; weights: H^T dZ (K = batch, split over
+        // workgroups); input side: dZ W^T, times GELU'(Z) of the layer below
         hipLaunchKernelGGL(k_colsum, dim3((unsigned)mlp_cdiv(out, 64), (unsigned)mlp_cdiv(batch, kColsumRows)),
-                           dim3(kColsumBlock), 0, c->stream, (const float*)dZf, grad + Y.boff[l], batch, out);
-        gemm(c, c->at<uint16_t>(Y.H[l]), 1, in, dZb, out, 1, grad + Y.woff[l], nullptr, out, nullptr, in,
-             out, batch, 0, true);
-        if (l > 0) {
-            gemm(c, dZb, out, 1, c->at<uint16_t>(Y.wb) + Y.woff[l], 1, out, dHf, nullptr, in, nullptr,
-                 batch, in, out, 0);
-            const long long nh = (long long)batch * in;
-            hipLaunchKernelGGL(k_gelu_back, dim3((unsigned)mlp_cdiv(nh, kMlpBlock)), dim3(kMlpBlock), 0,
-                               c->stream, (const float*)dHf, (const float*)c->at<float>(Y.Z[l - 1]), dZf,
-                               dZb, nh);
-        }
+                           dim3(kColsumBlock), 0, c->stream, dZf, grad + Y.boff[l], batch, out);
+        gemm(c, {c->at<uint16_t>(Y.H[l]), in, 1}, {dZb, out, 1}, grad + Y.woff[l], nullptr, out, nullptr, nullptr,
+             in, out, batch, 0, true);
+        if (l > 0)
+            gemm(c, {dZb, out, 0}, {c->at<uint16_t>(Y.wb) + Y.woff[l], out, 0}, c->at<float>(Y.dZf[h ^ 1]),
+                 c->at<uint16_t>(Y.dZb[h ^ 1]), in, nullptr, c->at<float>(Y.Z[l - 1]), batch, in, out, 2);
     }
     MLPCHK(c, hipGetLastError());
     c->last_batch = batch;

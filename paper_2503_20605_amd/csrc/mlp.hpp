@@ -2,15 +2,16 @@
 // trained and evaluated with bf16 operands on the matrix cores (fp32
 // accumulation), fp32 master weights, Adam.
 //
-//   k_gemm_bf16     C = A B with A, B bf16 in any strides, fp32 result: a
-//                   64x64 tile of C per workgroup, operands staged through
-//                   LDS 32 k at a time (loads along whichever index is
-//                   contiguous), one 32x32 tile per wavefront through
-//                   gfx950's v_mfma_f32_32x32x16_bf16; optional split of K over
-//                   workgroups (fp32 atomic accumulation); epilogue: + bias,
-//                   optional GELU (keeps the fp32 pre-activation and writes
-//                   the bf16 activation)
-//   k_gelu_back     dZ = dH * GELU'(Z), bf16 copy for the next products
+//   k_gemm_bf16     C = A B with A, B bf16 (either operand k-contiguous or
+//                   not), fp32 result: a 64x64 tile of C per workgroup, K in
+//                   panels staged through LDS with 16-byte loads along the
+//                   operand's contiguous index, the next panel fetched while
+//                   the current one is multiplied, one 32x32 tile per
+//                   wavefront through gfx950's v_mfma_f32_32x32x16_bf16;
+//                   optional split of K over workgroups (fp32 atomic
+//                   accumulation); epilogue: + bias, optional GELU (keeps
+//                   the fp32 pre-activation and writes the bf16
+//                   activation), or the GELU backward dZ = C * GELU'(Z)
 //   k_colsum        bias gradient (column sums of dZ): 64 columns x 256
 //                   rows per workgroup, reduced in LDS, then added
 //                   atomically
@@ -39,27 +40,84 @@ __device__ __forceinline__ float gelu_grad(float z) {
     return cdf + z * pdf;
 }
 
-// C(i, j) = sum_k A(i, k) B(k, j) (+ bias[j]); A(i, k) = A[i * sai + k * sak],
-// B(k, j) = B[k * sbk + j * sbj].  act = 0: C fp32 to Cf[i * ldc + j];
-// act = 1: Cf gets the pre-activation and Hb[i * ldc + j] the bf16 GELU.
-// Operands outside M x N x K read as zero.  With gridDim.z = S > 1 the
-// workgroups of z take the k range [z kc, (z + 1) kc) and add their partial
+// C(i, j) = sum_k A(i, k) B(k, j) (+ bias[j]) with A, B bf16 and fp32
+// accumulation.  Operand layouts (template arguments):
+//   AT = 0: A(i, k) = A[i * lda + k]  (k contiguous);  AT = 1: A[k * lda + i]
+//   BT = 0: B(k, j) = B[j * ldb + k]  (k contiguous);  BT = 1: B[k * ldb + j]
+// A workgroup takes a 64x64 tile of C and walks K in panels of KP: every
+// thread fetches its share of the next panel of both operands (KP / 32
+// 16-byte pieces of eight elements along the operand's contiguous index)
+// while the wavefronts multiply the current one out of LDS, where tiles are
+// kept k-contiguous (rows of KP + 8 elements, so every lane's eight MFMA
+// operands are one aligned 16-byte read).  avec / bvec = 0 fetches the
+// pieces element by element (an operand whose contiguous extent or leading
+// dimension is not a multiple of 8, or is not 16-byte aligned).  Elements
+// outside M x N x [kbeg, kend) read as zero.
+// Epilogue (act): 0: Cf = C + bias; 1: Cf = Z = C + bias, Hb = bf16(GELU(Z));
+// 2: Cf = C * GELU'(Zpre), Hb = its bf16 copy (the backward of a GELU layer,
+// Zpre its pre-activation, same layout as Cf).  With gridDim.z = S > 1 the
+// workgroups of z take k in [z kc, (z + 1) kc) and add their partial
 // products to Cf atomically (Cf zeroed beforehand; no bias, act = 0).
 //
 // Operand and result layout of one 32x32x16 product (lane l of 64):
 //   A: row l % 32, k = 8 (l / 32) + 0..7;  B: column l % 32, same k;
 //   result register r: row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
-constexpr int kGemmK = 32;         // k per LDS stage
-constexpr int kGemmLd = kGemmK + 8;  // padded LDS row (bf16 elements; 80 bytes, so
-                                     // each lane's 8 operands are one aligned 16-byte read)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Piece v (0 .. 64 KP / 8 - 1) of a 64 x KP panel of operand X whose rows r
+// (i of A, j of B) start at rb and whose k start at k0.  T = 0: piece v
+// holds row v / (KP / 8), k 8 (v % (KP / 8)) + 0..7; T = 1: k v / 8, rows
+// 8 (v % 8) + 0..7.
+template <int T, int KP>
+__device__ __forceinline__ u32x4 panel_fetch(const uint16_t* __restrict__ X, long long ld, int R, int kend,
+                                            int rb, int k0, int v, int vec) {
+    int r, k;
+    if (T == 0) {
+        r = rb + v / (KP / 8);
+        k = k0 + 8 * (v % (KP / 8));
+    } else {
+        k = k0 + v / 8;
+        r = rb + 8 * (v % 8);
+    }
+    u32x4 out = {0u, 0u, 0u, 0u};
+    if (vec) {
+        // the contiguous extent is a multiple of 8: a piece lies wholly
+        // inside or wholly outside
+        if (r < R && k < kend)
+            out = *reinterpret_cast<const u32x4*>(X + (T == 0 ? (long long)r * ld + k : (long long)k * ld + r));
+    } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int ru = T == 0 ? r : r + u, ku = T == 0 ? k + u : k;
+            const uint32_t e =
+                (ru < R && ku < kend) ? X[T == 0 ? (long long)ru * ld + ku : (long long)ku * ld + ru] : 0u;
+            out[u >> 1] |= e << (16 * (u & 1));
+        }
+    }
+    return out;
+}
+
+// Piece v into the k-contiguous LDS tile S (rows of KP + 8 elements).
+template <int T, int KP>
+__device__ __forceinline__ void panel_stash(uint16_t* __restrict__ S, int v, u32x4 x) {
+    constexpr int LD = KP + 8;
+    if (T == 0) {
+        *reinterpret_cast<u32x4*>(S + (v / (KP / 8)) * LD + 8 * (v % (KP / 8))) = x;
+    } else {
+        const int k = v / 8, r = 8 * (v % 8);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) S[(r + u) * LD + k] = (uint16_t)(x[u >> 1] >> (16 * (u & 1)));
+    }
+}
+
+template <int AT, int BT, int KP>
 __global__ __launch_bounds__(kMlpBlock) void k_gemm_bf16(
-    const uint16_t* __restrict__ A, long long sai, long long sak, const uint16_t* __restrict__ B,
-    long long sbk, long long sbj, float* __restrict__ Cf, uint16_t* __restrict__ Hb, long long ldc,
-    const float* __restrict__ bias, int M, int N, int K, int act, int kc) {
-    // tiles stored k-contiguous: As[i][k], Bs[j][k]
-    __shared__ __attribute__((aligned(16))) uint16_t As[64 * kGemmLd];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * kGemmLd];
+    const uint16_t* __restrict__ A, long long lda, const uint16_t* __restrict__ B, long long ldb,
+    float* __restrict__ Cf, uint16_t* __restrict__ Hb, long long ldc, const float* __restrict__ bias,
+    const float* __restrict__ Zpre, int M, int N, int K, int act, int kc, int avec, int bvec) {
+    constexpr int LD = KP + 8, NV = KP / 32;
+    __shared__ __attribute__((aligned(16))) uint16_t As[64 * LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * LD];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int ib = blockIdx.y * 64, jb = blockIdx.x * 64;
     const int kbeg = blockIdx.z * kc, kend = K < kbeg + kc ? K : kbeg + kc;
@@ -67,43 +125,38 @@ __global__ __launch_bounds__(kMlpBlock) void k_gemm_bf16(
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    // each thread stages 8 elements of each operand per stage, along the
-    // operand's contiguous index so that neighbouring threads read
-    // neighbouring addresses
-    const bool a_kc = sak == 1, b_kc = sbk == 1;
-    for (int k0 = kbeg; k0 < kend; k0 += kGemmK) {
+    u32x4 ra[NV], rb[NV];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            int ii, kk;
-            if (a_kc) {  // k contiguous: thread -> row t / 4, 8 consecutive k
-                ii = t >> 2;
-                kk = (t & 3) * 8 + u;
-            } else {     // i contiguous: thread -> k t / 8, 8 consecutive rows
-                kk = t >> 3;
-                ii = (t & 7) * 8 + u;
-            }
-            const int gi = ib + ii, gk = k0 + kk;
-            As[ii * kGemmLd + kk] = (gi < M && gk < kend) ? A[gi * sai + gk * sak] : (uint16_t)0;
-            int jj;
-            if (b_kc) {
-                jj = t >> 2;
-                kk = (t & 3) * 8 + u;
-            } else {
-                kk = t >> 3;
-                jj = (t & 7) * 8 + u;
-            }
-            const int gj = jb + jj, gk2 = k0 + kk;
-            Bs[jj * kGemmLd + kk] = (gj < N && gk2 < kend) ? B[gk2 * sbk + gj * sbj] : (uint16_t)0;
+    for (int u = 0; u < NV; ++u) {
+        ra[u] = panel_fetch<AT, KP>(A, lda, M, kend, ib, kbeg, t + kMlpBlock * u, avec);
+        rb[u] = panel_fetch<BT, KP>(B, ldb, N, kend, jb, kbeg, t + kMlpBlock * u, bvec);
+    }
+    for (int k0 = kbeg; k0 < kend; k0 += KP) {
+        if (k0 != kbeg) __syncthreads();  // the previous panel's reads are done
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+            panel_stash<AT, KP>(As, t + kMlpBlock * u, ra[u]);
+            panel_stash<BT, KP>(Bs, t + kMlpBlock * u, rb[u]);
         }
         __syncthreads();
+        if (k0 + KP < kend) {
 #pragma unroll
-        for (int s16 = 0; s16 < kGemmK; s16 += 16) {
-            const int kq = s16 + (lane >> 5) * 8;
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(As + (wi + (lane & 31)) * kGemmLd + kq);
-            const bf16x8 b = *reinterpret_cast<const bf16x8*>(Bs + (wj + (lane & 31)) * kGemmLd + kq);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+            for (int u = 0; u < NV; ++u) {
+                ra[u] = panel_fetch<AT, KP>(A, lda, M, kend, ib, k0 + KP, t + kMlpBlock * u, avec);
+                rb[u] = panel_fetch<BT, KP>(B, ldb, N, kend, jb, k0 + KP, t + kMlpBlock * u, bvec);
+            }
         }
-        __syncthreads();
+        // k steps of 16 past kend hold zeros only: skipped
+        const int nsteps = (kend - k0 < KP ? kend - k0 + 15 : KP) / 16;
+#pragma unroll
+        for (int s = 0; s < KP / 16; ++s) {
+            if (s < nsteps) {
+                const int kq = 16 * s + (lane >> 5) * 8;
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(As + (wi + (lane & 31)) * LD + kq);
+                const bf16x8 b = *reinterpret_cast<const bf16x8*>(Bs + (wj + (lane & 31)) * LD + kq);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+            }
+        }
     }
     const int j = jb + wj + (lane & 31);
     if (j >= N) return;
@@ -111,7 +164,7 @@ __global__ __launch_bounds__(kMlpBlock) void k_gemm_bf16(
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int i = ib + wi + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            if (i < M) unsafeAtomicAdd(Cf + i * ldc + j, acc[r]);
+            if (i < M) unsafeAtomicAdd(Cf + (long long)i * ldc + j, acc[r]);
         }
         return;
     }
@@ -120,20 +173,17 @@ __global__ __launch_bounds__(kMlpBlock) void k_gemm_bf16(
     for (int r = 0; r < 16; ++r) {
         const int i = ib + wi + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         if (i >= M) continue;
-        const float z = acc[r] + bj;
-        Cf[i * ldc + j] = z;
-        if (act) Hb[i * ldc + j] = f32_to_bf16_rne(gelu(z));
+        const long long o = (long long)i * ldc + j;
+        if (act == 2) {
+            const float g = acc[r] * gelu_grad(Zpre[o]);
+            Cf[o] = g;
+            Hb[o] = f32_to_bf16_rne(g);
+        } else {
+            const float z = acc[r] + bj;
+            Cf[o] = z;
+            if (act) Hb[o] = f32_to_bf16_rne(gelu(z));
+        }
     }
-}
-
-// dZ = dH * GELU'(Z) (fp32 and bf16 copies), n elements
-__global__ void k_gelu_back(const float* __restrict__ dH, const float* __restrict__ Z,
-                            float* __restrict__ dZf, uint16_t* __restrict__ dZb, long long n) {
-    const long long i = (long long)blockIdx.x * kMlpBlock + threadIdx.x;
-    if (i >= n) return;
-    const float g = dH[i] * gelu_grad(Z[i]);
-    dZf[i] = g;
-    dZb[i] = f32_to_bf16_rne(g);
 }
 
 // out[j] += sum_i X[i * N + j] (out zeroed beforehand): workgroup

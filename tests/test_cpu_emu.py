@@ -344,11 +344,14 @@ def _bf16(a):
     return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("widths,batch", [([4, 40, 33, 70], 37), ([4, 40, 70], 300)])
+@pytest.mark.parametrize("widths,batch", [([4, 40, 33, 70], 37), ([4, 40, 70], 300), ([4, 64, 40, 520], 300)])
 def test_network_kernels_against_reference(widths, batch):
     """Ragged sizes (K = 4, widths not multiples of the 32x32 tiles, batch
     not a multiple of 64) through forward, gradients and one Adam step; the
-    batch of 300 splits the weight-gradient products over K."""
+    batch of 300 splits the weight-gradient products over K.  Widths that
+    are multiples of 8 take the 16-byte operand fetches; 520 outputs give
+    the input-side product of the last layer three K panels, the last one
+    partial."""
     from emu import run_mlp
     from oracle import mlp
     rng = np.random.default_rng(3)
