@@ -58,6 +58,7 @@ def _load():
     lib.orc_forces_3d.argtypes = [c_int, D, c_int, I, c_double, c_double, c_double,
                                   c_int, c_int, c_int, D, D]
     lib.orc_inside.argtypes = [c_int, c_int, c_int, c_int, I, c_int, D, c_int, I, D, I]
+    lib.orc_respace_2d.argtypes = [c_int, D, c_double, D]
     lib.orc_threads.argtypes = [c_int]
     lib.orc_threads.restype = c_int
     lib.orc_inside_cells.argtypes = [c_int, c_int, c_int, c_int, I, c_int, D, c_int, I, D,
@@ -66,7 +67,7 @@ def _load():
                                           c_double, c_int, c_int, c_int, D, D]
     lib.orc_run.argtypes = [c_int, c_int, c_int, c_int, I, c_double, c_double, D,
                             c_double, c_double, D, c_double, c_double, c_int, c_int, c_int,
-                            c_int, D, c_int, I, c_int,
+                            c_double, c_int, D, c_int, I, c_int,
                             D, D, D, D, D, D, D, D]
     lib.orc_run.restype = c_int
     _lib = lib
@@ -288,6 +289,22 @@ def inside_cells(params, q, cells, tris=None, ref=None):
 # time loop
 # --------------------------------------------------------------------------
 
+def respace_2d(q, beta):
+    """Tangential re-spacing displacement of the closed 2D outline q (N, 2):
+    node j moves by beta/2 (l_j+ - l_j-) along the unit chord of its two
+    neighbours (l_j-, l_j+: lengths of its two edges).  An addition to the
+    method for long runs, not part of the paper: a line tension has no
+    tangential stiffness, so nodes carried by the fluid drift along the
+    outline, and this keeps their spacing even."""
+    lib = _load()
+    q = np.asarray(q, dtype=np.float64)
+    N = q.shape[0]
+    qa = np.ascontiguousarray(q.T).copy()
+    dq = np.zeros((2, N))
+    lib.orc_respace_2d(N, _d(qa), float(beta), _d(dq))
+    return dq.T.copy()
+
+
 def run(params, q0, nsteps, tris=None, f0=None, F_fixed=None):
     """Run `nsteps` of the coupled method from post-collision populations f0
     (default: fluid at rest, density one) and nodes q0 (N, dim; N may be 0
@@ -296,8 +313,9 @@ def run(params, q0, nsteps, tris=None, f0=None, F_fixed=None):
     `params` is any object with attributes dim, nx, ny, nz, bc, tau, sigma,
     theta_eq_deg, xi, n_exp, m_exp, wetting, and optionally lam (viscosity
     ratio, default 1; the classification window is centred on the mean of
-    q0) and shear (surface shear modulus of an elastic interface, 3D,
-    default 0; the reference mesh is q0).  Returns a dict with the final f, q, and the last step's rho, U, F,
+    q0), shear (surface shear modulus of an elastic interface, 3D,
+    default 0; the reference mesh is q0) and respace (rate beta of the
+    tangential re-spacing of a 2D outline, respace_2d; default 0).  Returns a dict with the final f, q, and the last step's rho, U, F,
     phi, qdot, dropped, status."""
     p = params
     lib = _load()
@@ -327,6 +345,7 @@ def run(params, q0, nsteps, tris=None, f0=None, F_fixed=None):
     status = lib.orc_run(dim, p.nx, p.ny, nz, _i(_bc(p.bc)), float(p.tau), tau_in, _d(ref),
                          float(p.sigma), mu_s, _d(qref), math.radians(p.theta_eq_deg), float(p.xi),
                          int(p.n_exp), int(p.m_exp), int(bool(p.wetting)),
+                         float(getattr(p, "respace", 0.0)),
                          N, _d(qa), T.shape[0], _i(T), int(nsteps),
                          _d(f), _d(rho), _d(U), _d(F), _d(Ff), _d(phi), _d(qdot), _d(dropped))
     return dict(f=f, q=qa.T[:N].copy(), rho=rho, U=U, F=F, phi=phi.T[:N].copy(),

@@ -630,6 +630,29 @@ void orc_inside_cells(int dim, int nx, int ny, int nz, const int *bc, int N, con
     }
 }
 
+/* Tangential re-spacing of a closed 2D outline: an addition to the method,
+ * not part of the paper.  Node j moves along the chord of its neighbours,
+ *   dq_j = (beta / 2) (l_j+ - l_j-) (q_{j+1} - q_{j-1}) / |q_{j+1} - q_{j-1}|,
+ * with l_j- = |q_j - q_{j-1}| and l_j+ = |q_{j+1} - q_j| (ring indices).
+ * Uniformly spaced nodes do not move; along a straight run of nodes this is
+ * an explicit diffusion of the node positions along the line (stable for
+ * beta < 1) that keeps them on it, so the outline's shape changes only at
+ * second order where it is curved.  q, dq: [2][N]. */
+void orc_respace_2d(int N, const double *q, double beta, double *dq)
+{
+    for (int j = 0; j < N; ++j) {
+        const int a = j == 0 ? N - 1 : j - 1, b = j == N - 1 ? 0 : j + 1;
+        const double xa = q[a], ya = q[N + a], xj = q[j], yj = q[N + j], xb = q[b], yb = q[N + b];
+        const double lm = sqrt((xj - xa) * (xj - xa) + (yj - ya) * (yj - ya));
+        const double lp = sqrt((xb - xj) * (xb - xj) + (yb - yj) * (yb - yj));
+        const double cx = xb - xa, cy = yb - ya;
+        const double c = sqrt(cx * cx + cy * cy);
+        const double s = c > 0.0 ? 0.5 * beta * (lp - lm) / c : 0.0;
+        dq[j] = s * cx;
+        dq[N + j] = s * cy;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Time loop                                                                 */
 /* ------------------------------------------------------------------------ */
@@ -639,6 +662,8 @@ void orc_inside_cells(int dim, int nx, int ny, int nz, const int *bc, int N, con
  * half-force velocity alike) -> interpolate U(t) at q(t) -> q(t+1).
  * mu_s != 0 (3D) adds the shear part of the elastic interface measured from
  * the reference positions qref ([3][N]).
+ * respace > 0 (2D) adds orc_respace_2d's tangential re-spacing, computed
+ * from q(t), to the advected positions: q(t+1) = (q(t) + qdot) + dq.
  * With tau_in != tau the cells enclosed by the interface at q(t) relax with
  * tau_in in the LB step of step t and the others with tau (classification
  * window centred on ref[3]; see orc_inside).
@@ -651,7 +676,7 @@ void orc_inside_cells(int dim, int nx, int ny, int nz, const int *bc, int N, con
  * (may be NULL).  Returns 0, or -4 if a node reached h <= 0 (wetting on). */
 int orc_run(int dim, int nx, int ny, int nz, const int *bc, double tau, double tau_in,
             const double *ref, double sigma, double mu_s, const double *qref, double theta,
-            double xi, int n_exp, int m_exp, int wetting,
+            double xi, int n_exp, int m_exp, int wetting, double respace,
             int N, double *q, int T, const int *tri, int nsteps,
             double *f, double *rho, double *U, double *F, const double *F_fixed,
             double *phi, double *qdot, double *dropped)
@@ -663,6 +688,7 @@ int orc_run(int dim, int nx, int ny, int nz, const int *bc, double tau, double t
     const int two_tau = N > 0 && tau_in != tau;
     double *tau_cell = two_tau ? (double *)malloc(sizeof(double) * ncell) : NULL;
     int *inside = two_tau ? (int *)malloc(sizeof(int) * ncell) : NULL;
+    double *dq = (dim == 2 && N > 0 && respace > 0.0) ? (double *)malloc(sizeof(double) * 2 * N) : NULL;
     int status = 0;
     for (int t = 0; t < nsteps; ++t) {
         if (N > 0) {
@@ -689,10 +715,16 @@ int orc_run(int dim, int nx, int ny, int nz, const int *bc, double tau, double t
         memcpy(f, g, sizeof(double) * Q * ncell);
         if (N > 0) {
             orc_interp(dim, nx, ny, nz, bc, U, N, q, qdot);
-            for (long k = 0; k < (long)dim * N; ++k) q[k] += qdot[k];
+            if (dq) {
+                orc_respace_2d(N, q, respace, dq);
+                for (long k = 0; k < 2L * N; ++k) q[k] = (q[k] + qdot[k]) + dq[k];
+            } else {
+                for (long k = 0; k < (long)dim * N; ++k) q[k] += qdot[k];
+            }
         }
     }
     free(g);
+    free(dq);
     free(tau_cell);
     free(inside);
     return status;

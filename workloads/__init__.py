@@ -52,6 +52,10 @@ class Params:
     # surface shear modulus of an elastic interface (3D; the stress-free
     # reference is the mesh as first set); 0: a liquid droplet
     shear: float = 0.0
+    # rate beta of the tangential re-spacing of a 2D outline (nodes moved
+    # along the chord of their neighbours by beta/2 times the difference of
+    # their two edge lengths each step; an addition for long runs); 0: off
+    respace: float = 0.0
 
     def to_dict(self):
         return asdict(self)
