@@ -283,6 +283,22 @@ int iblb_set_viscosity_ratio(iblb_ctx *ctx, int droplet, double lambda);
  * an interface, or for a negative or non-finite mu_s.  Synchronises. */
 int iblb_set_membrane_shear(iblb_ctx *ctx, int droplet, double mu_s);
 
+/* Tangential re-spacing of droplet d's outline (2D), an addition to the
+ * method for long runs rather than a passage of the paper: the outline's
+ * nodes move with the interpolated fluid velocity only (eq.
+ * vel_interpolation), and a line tension has no tangential stiffness, so
+ * over 10^5 steps and more they drift along the outline and open gaps of
+ * many lattice units at the contact corners, through which the interface
+ * leaks.  With beta > 0, each step adds to node j's advected position
+ *   (beta / 2) (|q_{j+1} - q_j| - |q_j - q_{j-1}|) c / |c|,
+ * c = q_{j+1} - q_{j-1}, all at the positions before the advection: a move
+ * along the outline that leaves uniformly spaced nodes where they are and
+ * evens out uneven spacing.  q_dot (iblb_read_nodes, the rest criterion of
+ * iblb_run_to_rest) stays the fluid velocity.  0 <= beta < 1 (0: off, the
+ * default).  EINVAL in 3D, without an interface, or for beta outside that
+ * range.  Synchronises. */
+int iblb_set_node_respacing(iblb_ctx *ctx, int droplet, double beta);
+
 /* Inside/outside classification of droplet d's cells at its current node
  * positions (the rule of iblb_set_viscosity_ratio, for any lambda):
  * d_mask (device, uint8, ncell = nx*ny*nz, [z][y][x]) receives 1 for cells

@@ -242,6 +242,11 @@ class Solver:
         stress-free at its current node positions (3D; 0: liquid)."""
         self._chk(self.lib.iblb_set_membrane_shear(self.ctx, d, float(mu_s)))
 
+    def set_node_respacing(self, d, beta):
+        """Tangential re-spacing of droplet d's outline at rate beta (2D;
+        0: off)."""
+        self._chk(self.lib.iblb_set_node_respacing(self.ctx, d, float(beta)))
+
     def contact_radius(self, d, z_cut, flat_tol):
         """(protocol (i) radius at z_cut, protocol (ii) radius with flatness
         tolerance flat_tol, number of protocol (i) crossings) of droplet d."""

@@ -33,7 +33,7 @@ EXPORTED = (
     "iblb_read_nodes", "iblb_diagnostics", "iblb_set_lb_variant", "iblb_autotune",
     "iblb_set_graph_steps", "iblb_set_active", "iblb_set_timing", "iblb_last_timing", "iblb_time_lattice",
     "iblb_probe_copy", "iblb_run_to_rest", "iblb_set_viscosity_ratio", "iblb_inside_mask",
-    "iblb_contact_radius", "iblb_set_membrane_shear",
+    "iblb_contact_radius", "iblb_set_membrane_shear", "iblb_set_node_respacing",
     "iblb_mlp_workspace_bytes", "iblb_mlp_create", "iblb_mlp_destroy", "iblb_mlp_last_error",
     "iblb_mlp_param_count", "iblb_mlp_set_params", "iblb_mlp_get_params", "iblb_mlp_forward",
     "iblb_mlp_gradients", "iblb_mlp_adam_step", "iblb_mlp_forward_noalloc",
@@ -113,6 +113,7 @@ def load() -> ctypes.CDLL:
     lib.iblb_inside_mask.argtypes = [c_void_p, c_int, c_void_p]
     lib.iblb_contact_radius.argtypes = [c_void_p, c_int, c_double, c_double, P(c_double)]
     lib.iblb_set_membrane_shear.argtypes = [c_void_p, c_int, c_double]
+    lib.iblb_set_node_respacing.argtypes = [c_void_p, c_int, c_double]
     lib.iblb_set_timing.argtypes = [c_void_p, c_int]
     lib.iblb_last_timing.argtypes = [c_void_p, P(c_double), P(c_double)]
     lib.iblb_time_lattice.argtypes = [c_void_p, c_int, P(c_double)]

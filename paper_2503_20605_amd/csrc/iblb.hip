@@ -1444,6 +1444,15 @@ int iblb_set_membrane_shear(iblb_ctx* c, int d, double mu_s) {
     return upload_drops(c);
 }
 
+int iblb_set_node_respacing(iblb_ctx* c, int d, double beta) {
+    if (!check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
+    if (c->dim != 2) return fail(c, IBLB_EINVAL, "node re-spacing applies to a 2D outline");
+    if (!(beta >= 0.0 && beta < 1.0)) return fail(c, IBLB_EINVAL, "re-spacing rate must lie in [0, 1)");
+    if (c->n_nodes[d] == 0 || !c->iface_set[d]) return fail(c, IBLB_EINVAL, "droplet has no interface");
+    c->drops[d].respace = beta;
+    return upload_drops(c);
+}
+
 int iblb_inside_mask(iblb_ctx* c, int d, uint8_t* d_mask) {
     if (!check_droplet(c, d)) return fail(c, IBLB_EINVAL, "bad droplet index");
     if (!d_mask) return fail(c, IBLB_EINVAL, "NULL mask");

@@ -75,6 +75,7 @@ struct DropDev {
     double win[3];        // classification window [win, win + n) of each axis
     double img_base, img_r;  // x image of cell centre c: c + img_base (+ nx if c < img_r)
     double shear;         // surface shear modulus of an elastic interface (0: liquid)
+    double respace;       // rate beta of the tangential re-spacing of a 2D outline (0: off)
 };
 
 struct DiagDev {
@@ -449,6 +450,23 @@ __device__ __forceinline__ void ring_2d(const DropDev& D, int j, int& jm, int& j
     const int N = D.n_nodes, loc = j - D.node_off;
     jm = D.node_off + (loc == 0 ? N - 1 : loc - 1);
     jp = D.node_off + (loc == N - 1 ? 0 : loc + 1);
+}
+
+// Tangential re-spacing of a 2D outline, an addition to the method for long
+// runs (a line tension has no tangential stiffness, so nodes carried by the
+// fluid drift along the outline and open gaps): node m with ring neighbours
+// a and b moves by beta/2 (|q_b - q_m| - |q_m - q_a|) along the unit chord
+// q_b - q_a, computed from the positions before the advection and added to
+// the advected position.  Uniform spacing is left alone.
+__device__ __forceinline__ void respace_move(double beta, const double qa[3], const double qm[3],
+                                             const double qb[3], double dq[2]) {
+    const double lm = sqrt((qm[0] - qa[0]) * (qm[0] - qa[0]) + (qm[1] - qa[1]) * (qm[1] - qa[1]));
+    const double lp = sqrt((qb[0] - qm[0]) * (qb[0] - qm[0]) + (qb[1] - qm[1]) * (qb[1] - qm[1]));
+    const double cx = qb[0] - qa[0], cy = qb[1] - qa[1];
+    const double c = sqrt(cx * cx + cy * cy);
+    const double sc = c > 0.0 ? 0.5 * beta * (lp - lm) / c : 0.0;
+    dq[0] = sc * cx;
+    dq[1] = sc * cy;
 }
 
 __device__ __forceinline__ void node_geom_2d(const DropDev& D, const NodeArrays& A, int j,
@@ -1061,16 +1079,31 @@ __global__ __launch_bounds__(kNodeBlock) void k_interp_advect(const DropDev* __r
 #pragma unroll
     for (int a = 0; a < DIM; ++a) acc[a] = group_sum<G>(acc[a]);
     if (k != 0) return;
+    double dq[2] = {0.0, 0.0};
+    if (DIM == 2 && D.respace != 0.0) {
+        int jm, jp;
+        ring_2d(D, j, jm, jp);
+        const double qm[3] = {A.pos[jm], A.pos[st + jm], 0.0}, qp[3] = {A.pos[jp], A.pos[st + jp], 0.0};
+        if (!(coord_ok(qm[0]) && coord_ok(qm[1]) && coord_ok(qp[0]) && coord_ok(qp[1]))) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) hold_position<DIM>(A, j, a);
+            atomicOr(status + d, 4);
+            return;
+        }
+        respace_move(D.respace, qm, q, qp, dq);
+    }
     float sp = 0.f;
+    double qn[DIM];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
+        qn[a] = (q[a] + (double)acc[a]) + (a < 2 ? dq[a] : 0.0);
         A.qdot[a * st + j] = acc[a];
-        A.pos_w[a * st + j] = q[a] + (double)acc[a];
+        A.pos_w[a * st + j] = qn[a];
         sp += acc[a] * acc[a];
     }
     int bad = 0;
     if (!(sp <= 0.09f)) bad |= 2;  // |qdot| > 0.3 or not finite
-    if (D.wetting && !(q[DIM - 1] + (double)acc[DIM - 1] > 0.0)) bad |= 1;
+    if (D.wetting && !(qn[DIM - 1] > 0.0)) bad |= 1;
     if (bad) atomicOr(status + d, bad);
 }
 
@@ -1295,7 +1328,20 @@ __global__ __launch_bounds__(kNodeBlock) void k_ib_fused2(const DropDev* __restr
             q[m][1] = A.pos[st + id[m]];
         }
     }
-    bool ok = true;
+    // with re-spacing, the ring neighbours' moves need their own outer
+    // neighbours: qo[0] before jm, qo[1] after jp
+    const bool resp = D.respace != 0.0;
+    double qo[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    if (resp) {
+        int jmm, jpp, dummy;
+        ring_2d(D, jm, jmm, dummy);
+        ring_2d(D, jp, dummy, jpp);
+        qo[0][0] = A.pos[jmm];
+        qo[0][1] = A.pos[st + jmm];
+        qo[1][0] = A.pos[jpp];
+        qo[1][1] = A.pos[st + jpp];
+    }
+    bool ok = !resp || (coord_ok(qo[0][0]) && coord_ok(qo[0][1]) && coord_ok(qo[1][0]) && coord_ok(qo[1][1]));
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         q[m][2] = 0.0;
@@ -1342,6 +1388,18 @@ __global__ __launch_bounds__(kNodeBlock) void k_ib_fused2(const DropDev* __restr
         qn[m][0] = q[m][0] + (double)acc[m][0];
         qn[m][1] = q[m][1] + (double)acc[m][1];
         qn[m][2] = 0.0;
+    }
+    if (resp) {
+        double dq[2];
+        respace_move(D.respace, qo[0], q[0], q[1], dq);
+        qn[0][0] += dq[0];
+        qn[0][1] += dq[1];
+        respace_move(D.respace, q[0], q[1], q[2], dq);
+        qn[1][0] += dq[0];
+        qn[1][1] += dq[1];
+        respace_move(D.respace, q[1], q[2], qo[1], dq);
+        qn[2][0] += dq[0];
+        qn[2][1] += dq[1];
     }
     if (k == 0) {
         A.qdot[j] = acc[1][0];

@@ -132,6 +132,10 @@ def _solver(draws, storage):
     from . import Solver, params_from
     s = Solver([params_from(w.params) for w in draws], [w.nodes for w in draws], storage=storage)
     s.set_graph_steps(100)
+    for d, w in enumerate(draws):
+        beta = float(getattr(w.params, "respace", 0.0))
+        if beta:
+            s.set_node_respacing(d, beta)
     return s
 
 

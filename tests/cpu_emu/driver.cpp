@@ -173,6 +173,13 @@ int main(int argc, char** argv) {
         }
     }
     for (int d = 0; d < n; ++d) {
+        const std::string key = "respace_" + std::to_string(d);
+        if (cfg.count(key) && iblb_set_node_respacing(ctx, d, atof(cfg[key].c_str()))) {
+            fprintf(stderr, "node re-spacing: %s\n", iblb_last_error(ctx));
+            return 17;
+        }
+    }
+    for (int d = 0; d < n; ++d) {
         const std::string key = "lambda_" + std::to_string(d);
         if (cfg.count(key) && iblb_set_viscosity_ratio(ctx, d, atof(cfg[key].c_str()))) {
             fprintf(stderr, "viscosity ratio: %s\n", iblb_last_error(ctx));

@@ -71,6 +71,9 @@ def run_case(params_list, nodes_list=None, tris_list=None, steps=(1,), storage=0
             mu_s = float(getattr(params_list[k], "shear", 0.0))
             if mu_s != 0.0:
                 cfg.append(f"shear_{k} {mu_s!r}")
+            beta = float(getattr(params_list[k], "respace", 0.0))
+            if beta != 0.0:
+                cfg.append(f"respace_{k} {beta!r}")
             q = nodes_list[k]
             if q is not None:
                 q = np.asarray(q, dtype=np.float64)

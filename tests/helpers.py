@@ -24,6 +24,9 @@ def gpu_solver(params_list, nodes_list=None, tris_list=None, storage=0):
         mu_s = float(getattr(p, "shear", 0.0))
         if mu_s != 0.0:
             s.set_membrane_shear(d, mu_s)
+        beta = float(getattr(p, "respace", 0.0))
+        if beta != 0.0:
+            s.set_node_respacing(d, beta)
     return s
 
 

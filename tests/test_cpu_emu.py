@@ -152,6 +152,28 @@ def test_batch_with_fluid_only_member():
     assert np.array_equal(out[1]["q"], qs[1]) and np.all(out[1]["fdev"] == 0)
 
 
+def test_node_respacing_2d_single_and_batch():
+    """Tangential re-spacing of unevenly spaced outlines (every third node
+    removed along part of the arc), for a lone droplet and inside a batch
+    (the two ring lookups of the fused node kernel), through the first-step,
+    fused and last-step node kernels; the oracle's run with the same rate
+    must agree, and the re-spacing must move the nodes."""
+    import dataclasses
+    p1 = wl.Params(dim=2, nx=96, ny=40, tau=0.7, sigma=0.006, theta_eq_deg=40.0, xi=2.0, respace=0.4)
+    p2 = wl.Params(dim=2, nx=70, ny=33, tau=1.3, sigma=0.009, theta_eq_deg=140.0, xi=2.0, respace=0.25)
+    q1 = np.delete(wl.cap_polygon(12.0, 90.0, 2.0, 94, 48.0), list(range(10, 40, 3)), axis=0)
+    q2 = np.delete(wl.cap_polygon(9.0, 90.0, 2.0, 71, 35.0), list(range(5, 30, 3)), axis=0)
+    lone, batch = run_cases([dict(params_list=[p1], nodes_list=[q1], steps=(5, 4), graph_steps=2),
+                             dict(params_list=[p1, p2], nodes_list=[q1, q2], steps=(5, 4), graph_steps=2)])
+    r1 = o.run(p1, q1, 9)
+    r0 = o.run(dataclasses.replace(p1, respace=0.0), q1, 9)
+    assert np.max(np.abs(r1["q"] - r0["q"])) > 1e-2
+    for g, r, name in ((lone[0], r1, "lone"), (batch[0], r1, "batch0"), (batch[1], o.run(p2, q2, 9), "batch1")):
+        drho, du, dq = compare_fields(g, r, 2, f"emu respace {name}")
+        assert g["status"] == 0
+        assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
+
+
 def test_two_viscosities_2d_across_periodic_edge():
     """Viscosity ratio 10, ragged box, droplet across the periodic x edge:
     the classification at the initial and the final node positions equals
