@@ -315,6 +315,13 @@ def tte(a):
     log(f"network trained on {len(X)} equilibria in {t_train:.1f} s (loss {hist[-1][1]:.3e})")
     draws = wl.batch_draws(a.droplets, seed=6)
     res = ws.evaluate_arms(draws, m, scale, a.max_steps, log=log, rest=REST)
+    if a.dump:
+        # the trained network (parameters and output scaling), the learned
+        # start outlines, and which of them turned unstable
+        bad = [i for i, x in enumerate(res["f16_learned"]["steps"]) if x == -2]
+        np.savez(a.dump + ".net.npz", params=m.get_params(), mean=scale[0], std=scale[1],
+                 unstable=np.array(bad, dtype=np.int64),
+                 **{f"start_q_{i}": st[0] for i, st in enumerate(res["f16_learned"]["starts"])})
     m.close()
     summary = ws.summarize(draws, res, a.max_steps)
     cells = sum(w.params.nx * w.params.ny for w in draws)

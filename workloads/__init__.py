@@ -234,10 +234,11 @@ def batch_draws(n: int = 256, seed: int = 3):
     """Independent droplets of uneven box size and wettability: Nx in
     {128,...,512} and Ny in {64,...,256} (multiples of 32), circle radius
     R ~ U[15, 100] with round(2 pi R / 0.8) nodes, theta_eq ~ U[20, 160] deg,
-    tau ~ U[0.6, 1.5], sigma ~ U[0.002, 0.01], xi = 2.  A draw is rejected and
-    redrawn when the 90-degree start or the equal-area theta_eq cap would
-    not fit its box.  Returns a list of Workloads starting from the half
-    disk."""
+    tau ~ U[0.6, 1.5], sigma ~ U[0.002, 0.01], xi = 2, tangential node
+    re-spacing at rate 0.05 (these droplets are run for up to 10^6 steps).
+    A draw is rejected and redrawn when the 90-degree start or the
+    equal-area theta_eq cap would not fit its box.  Returns a list of
+    Workloads starting from the half disk."""
     rng = np.random.default_rng(seed)
     out = []
     while len(out) < n:
@@ -255,7 +256,7 @@ def batch_draws(n: int = 256, seed: int = 3):
         fits_eq = 2 * half_w <= nx - 32 and h + xi <= ny - 8
         if not (fits90 and fits_eq):
             continue
-        p = Params(dim=2, nx=nx, ny=ny, tau=tau, sigma=sigma, theta_eq_deg=th, xi=xi)
+        p = Params(dim=2, nx=nx, ny=ny, tau=tau, sigma=sigma, theta_eq_deg=th, xi=xi, respace=0.05)
         q = cap_polygon(R, 90.0, xi, nn, nx / 2.0)
         out.append(Workload(f"batch{len(out)}", p, q, meta={"R": R}))
     return out
