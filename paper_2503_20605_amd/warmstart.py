@@ -34,6 +34,7 @@ U_SCALE = 1e4             # velocity targets are O(1e-6 .. 1e-4) lattice units
 U_WEIGHT = 0.3            # weight of the (noise-dominated) velocity outputs in the loss
 U_MAX = 1e-3              # predicted velocities are clipped to this magnitude
 H_MIN = 0.85              # predicted nodes stay at least this many xi above the wall
+MAX_TURN_DEG = 175.0      # a predicted outline turning more sharply than this folds back
 PHI = 2.0 * math.pi * np.arange(K_RAYS) / K_RAYS
 
 
@@ -233,9 +234,23 @@ def fit(X, Y, steps=4000, lr=1e-3, seed=7, log=print):
     return m, (mu, sd), hist
 
 
+def max_turn_deg(q):
+    """Largest turning angle (degrees) between consecutive edges of the
+    closed outline q: 180 - theta at a contact corner of angle theta, 180
+    where the outline folds back on itself."""
+    e = np.roll(q, -1, axis=0) - q
+    a = np.arctan2(e[:, 1], e[:, 0])
+    turn = np.abs((np.roll(a, -1) - a + math.pi) % (2.0 * math.pi) - math.pi)
+    return float(np.degrees(turn.max()))
+
+
 def predict_starts(m, scale, draws):
     """Initial outlines and fluid velocity fields predicted by the network
-    (scale: the output mean and std of fit)."""
+    (scale: the output mean and std of fit).  Keeping the nodes above the
+    wall can fold the predicted outline of a flat droplet back on itself
+    near its contact line (a spike of zero width, which no solver step
+    survives); such a start is replaced by the analytic prior (cap_starts)
+    before anything runs.  Returns the starts and the indices replaced."""
     X = np.array([features(math.radians(w.params.theta_eq_deg), polygon_area(w.nodes),
                            w.params.tau, w.params.sigma) for w in draws])
     out = m.forward(X).cpu().numpy().astype(np.float64) * scale[1] + scale[0]
@@ -249,7 +264,12 @@ def predict_starts(m, scale, draws):
         q = outline_from_profile(ref, r, len(w.nodes), H_MIN * p.xi)
         Uc = np.clip(o[K_RAYS:].reshape(2, *GRID) / U_SCALE, -U_MAX, U_MAX)
         starts.append((q, fine_velocity(Uc, p.ny, p.nx), rc))
-    return starts
+    rejected = [i for i, st in enumerate(starts) if max_turn_deg(st[0]) > MAX_TURN_DEG]
+    if rejected:
+        prior = cap_starts([draws[i] for i in rejected])
+        for k, i in enumerate(rejected):
+            starts[i] = prior[k]
+    return starts, rejected
 
 
 def cap_starts(draws):
@@ -322,15 +342,19 @@ def shape_error(q_start, q_final, ref):
 def evaluate_arms(draws, m, scale, max_steps, log=print, rest=None):
     """Run the draws to rest four ways: plain fp32 from the 90-degree cap,
     fp16 from the 90-degree cap, fp16 from the analytic equal-area cap, fp16
-    from the network's start; plus the learned arm with every start that
+    from the network's start (predicted outlines that fold replaced by the
+    analytic cap beforehand); plus the learned arm with every start that
     turned unstable rerun from the analytic cap (its wall time charged to
     the learned arm)."""
     res = {}
     arms = [("plain_f32_90deg", 0, None), ("f16_90deg", 1, None),
-            ("f16_cap_prior", 1, cap_starts(draws)), ("f16_learned", 1, predict_starts(m, scale, draws))]
+            ("f16_cap_prior", 1, cap_starts(draws))]
+    learned, rejected = predict_starts(m, scale, draws)
+    arms.append(("f16_learned", 1, learned))
     for name, storage, starts in arms:
         wall, steps, ang, finals = run_from(draws, starts, storage, max_steps, log=log, rest=rest)
-        res[name] = dict(wall=wall, steps=steps, theta=ang, finals=finals, starts=starts)
+        res[name] = dict(wall=wall, steps=steps, theta=ang, finals=finals, starts=starts,
+                         rejected=rejected if name == "f16_learned" else [])
         log(f"[evaluate] {name}: {wall:.1f} s, at rest {sum(1 for x in steps if x > 0)}/"
             f"{len(steps)}")
     lr = res["f16_learned"]
@@ -362,6 +386,7 @@ def summarize(draws, res, max_steps):
             else np.zeros(0)
         e = {"wall_s": round(r["wall"], 2), "at_rest": len(conv),
              "fallback_reruns": r.get("fallback", 0),
+             "folded_starts_replaced_by_cap": len(r.get("rejected", [])),
              "unstable": sum(1 for x in r["steps"] if x == -2),
              "median_steps": float(np.median([r["steps"][i] for i in conv])) if conv else None,
              "theta_vs_plain_within_1deg": int((dth < 1.0).sum()),
