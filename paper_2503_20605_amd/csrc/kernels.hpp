@@ -1135,10 +1135,12 @@ __global__ __launch_bounds__(kBlock) void k_force3(const DropDev* __restrict__ d
 // chunk's taps, and each touched cell then takes one global atomic add per
 // component instead of one per contribution.  A chunk whose box exceeds
 // kBoxCells (vertices far apart) adds straight to global memory.
-// Chunks of 16 vertices, 256-lane workgroups and a 1024-cell box (13 KB of
-// LDS) measured fastest among chunks of 8-64 vertices and 128-1024 lanes
-// (3D steps of 256x256x128 and 240x240x130: 295 and 348 us against 312
-// and 374 us for 64 vertices on 1024 lanes).
+// Chunks of 16 vertices, 256-lane workgroups and a 1024-cell box measured
+// fastest among chunks of 8-64 vertices and 128-1024 lanes (3D steps of
+// 256x256x128 and 240x240x130: 295 and 348 us against 312 and 374 us for
+// 64 vertices on 1024 lanes), and again with the 64-bit fixed-point sums
+// (256x256x128 step 271 us against 273-278 us for chunks of 8-32 vertices,
+// 128-512 lanes and boxes of 512-2048 cells).
 #ifndef IBLB_SPREAD_CHUNK
 #define IBLB_SPREAD_CHUNK 16
 #endif

@@ -152,27 +152,27 @@ void launch_gemm(const iblb_mlp* c, dim3 grid, const Operand& A, const Operand& 
 }
 
 // C (M x N, leading dimension ldc) = A B.  With split_k, K is divided over
-// enough workgroups to give the device at least ~256 of them (at most 16
+// enough workgroups to give the device about 1024 of them (at most 16
 // pieces, each a multiple of the LDS panel); the pieces add into Cf, which
 // the caller has zeroed.  Only plain products (no bias, act 0) split.
-// Panels of 256 k (one fetch for the usual K = 256) unless K is short.
+// Panels of 128 k: against 256-k panels (one fetch for K = 256, half the
+// workgroups per compute unit) and splits aiming at 256 workgroups, the
+// training step of the 4-256-256-256-1280 network on 4096 samples took
+// 0.297 against 0.313 ms.
 void gemm(const iblb_mlp* c, const Operand& A, const Operand& B, float* Cf, uint16_t* Hb, long long ldc,
           const float* bias, const float* Zpre, int M, int N, int K, int act, bool split_k = false) {
-    const int KP = K > 128 ? 256 : 128;
+    constexpr int KP = 128;
     const long long tiles = mlp_cdiv(N, 64) * mlp_cdiv(M, 64);
     int splits = 1;
     if (split_k && !bias && act == 0) {
-        const long long want = mlp_cdiv(256, tiles);
+        const long long want = mlp_cdiv(1024, tiles);
         splits = (int)std::max(1LL, std::min({want, 16LL, mlp_cdiv(K, KP)}));
     }
     const int kc = (int)(mlp_cdiv(mlp_cdiv(K, splits), KP) * KP);
     splits = (int)mlp_cdiv(K, kc);
     const int avec = pieces_ok(A, A.t == 0 ? K : M), bvec = pieces_ok(B, B.t == 0 ? K : N);
     const dim3 grid((unsigned)mlp_cdiv(N, 64), (unsigned)mlp_cdiv(M, 64), (unsigned)splits);
-    if (KP == 256)
-        launch_gemm<256>(c, grid, A, B, Cf, Hb, ldc, bias, Zpre, M, N, K, act, kc, avec, bvec);
-    else
-        launch_gemm<128>(c, grid, A, B, Cf, Hb, ldc, bias, Zpre, M, N, K, act, kc, avec, bvec);
+    launch_gemm<KP>(c, grid, A, B, Cf, Hb, ldc, bias, Zpre, M, N, K, act, kc, avec, bvec);
 }
 
 // forward pass of `batch` rows from device fp32 input x

@@ -372,8 +372,8 @@ def test_network_kernels_against_reference(widths, batch):
     not a multiple of 64) through forward, gradients and one Adam step; the
     batch of 300 splits the weight-gradient products over K.  Widths that
     are multiples of 8 take the 16-byte operand fetches; 520 outputs give
-    the input-side product of the last layer three K panels, the last one
-    partial."""
+    the input-side product of the last layer five K panels of 128, the last
+    one partial."""
     from emu import run_mlp
     from oracle import mlp
     rng = np.random.default_rng(3)
