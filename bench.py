@@ -113,7 +113,8 @@ def parse():
                     help="--tte: write every droplet's steps and angles per arm to this JSON file")
     ap.add_argument("--train-draws", type=int, default=512,
                     help="seeded draws whose equilibria train the warm-start network (--tte)")
-    ap.add_argument("--max-steps", type=int, default=200000)
+    ap.add_argument("--max-steps", type=int, default=None,
+                    help="step cap: --tte 800000 (per arm), --tanner 150000")
     ap.add_argument("--workload", default="d3q19", choices=["d3q19", "d2q9", "d3q19_spreading"])
     ap.add_argument("--lam", type=float, default=None,
                     help="viscosity ratio mu_in / mu_out (default: the workload's own)")
@@ -214,7 +215,7 @@ def tanner(a):
     s = Solver([params_from(p)], [W.nodes], [W.tris])
     s.autotune(steps=16)
     zc = p.xi * 2.0 ** (1.0 / 3.0) + 1.0
-    n_total = a.max_steps if a.max_steps != 200000 else 150000
+    n_total = a.max_steps or 150000
     marks = sorted({int(round(10 ** e)) for e in np.arange(1.0, math.log10(n_total) + 1e-9, 0.05)})
     ts, ri, rii = [], [], []
     t0 = time.perf_counter()
@@ -307,6 +308,8 @@ def tte(a):
     import numpy as np
     import workloads as wl
     from paper_2503_20605_amd import warmstart as ws
+    if a.max_steps is None:
+        a.max_steps = 800000
     t0 = time.perf_counter()
     X, Y, S = ws.generate(wl.batch_draws(a.train_draws, seed=5), storage=1, max_steps=a.max_steps,
                           rest=REST, log=log)
