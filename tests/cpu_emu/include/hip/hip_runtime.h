@@ -6,7 +6,9 @@
 // access of every kernel is checked on the CPU before it runs on a GPU.
 //
 // Execution model: a launch runs its blocks one after another; the threads
-// of a block are fibers (ucontext) that run until they reach a point where
+// of a block are fibers (own stacks, switched by a few lines of x86-64
+// assembly: glibc's swapcontext makes a signal-mask system call on every
+// switch, which dominated the run time) that run until they reach a point where
 // lanes exchange data -- __syncthreads(), __shfl_xor() or
 // __builtin_amdgcn_readfirstlane() -- which act as barriers of the block or
 // of the 64-lane wavefront, exactly as lock-step execution would order
@@ -22,7 +24,6 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
-#include <ucontext.h>
 
 #include <functional>
 #include <vector>
@@ -87,7 +88,7 @@ struct Event { int id; };
 enum State { READY, AT_WAVE_FIRST, AT_WAVE_XOR, AT_WAVE_MFMA, AT_WAVE_BALLOT, AT_BLOCK, DONE };
 
 struct Fiber {
-    ucontext_t ctx;
+    void* sp = nullptr;   // saved stack pointer while switched out
     char* stack = nullptr;
     int tid = 0;
     State st = READY;
@@ -100,7 +101,7 @@ struct Fiber {
 struct Runtime {
     dim3 grid, block, bidx;
     std::vector<Fiber> fibers;
-    ucontext_t sched;
+    void* sched_sp = nullptr;
     Fiber* cur = nullptr;
     const std::function<void()>* body = nullptr;
     Stream* capturing = nullptr;
@@ -429,9 +430,25 @@ extern "C" void __sanitizer_finish_switch_fiber(void* fake_stack_save, const voi
                                                 size_t* size_old);
 #endif
 
+// Context switch (x86-64 System V): push the callee-saved registers on the
+// current stack, store its pointer in *save, load `load` as the stack
+// pointer, pop that stack's registers and return into it.  Weak, so that
+// every translation unit including this header may define it.
+extern "C" void hipemu_switch(void** save, void* load);
+__asm__(".text\n"
+        ".weak hipemu_switch\n"
+        ".type hipemu_switch,@function\n"
+        "hipemu_switch:\n"
+        "  pushq %rbp\n  pushq %rbx\n  pushq %r12\n  pushq %r13\n  pushq %r14\n  pushq %r15\n"
+        "  movq %rsp, (%rdi)\n"
+        "  movq %rsi, %rsp\n"
+        "  popq %r15\n  popq %r14\n  popq %r13\n  popq %r12\n  popq %rbx\n  popq %rbp\n"
+        "  ret\n"
+        ".size hipemu_switch, .-hipemu_switch\n");
+
 namespace hipemu {
 
-constexpr size_t kStack = 512 * 1024;
+constexpr size_t kStack = 128 * 1024;
 
 inline Runtime& rt() {
     static Runtime r;
@@ -451,7 +468,7 @@ inline void yield_to_sched(bool finished) {
 #ifdef HIPEMU_ASAN
     __sanitizer_start_switch_fiber(finished ? nullptr : &f->asan_fake, r.sched_bottom, r.sched_size);
 #endif
-    swapcontext(&f->ctx, &r.sched);
+    hipemu_switch(&f->sp, r.sched_sp);
 #ifdef HIPEMU_ASAN
     __sanitizer_finish_switch_fiber(f->asan_fake, nullptr, nullptr);
 #endif
@@ -505,11 +522,14 @@ inline void run_block(const std::function<void()>& fn) {
         f.tid = t;
         f.st = READY;
         f.asan_fake = nullptr;
-        getcontext(&f.ctx);
-        f.ctx.uc_stack.ss_sp = f.stack;
-        f.ctx.uc_stack.ss_size = kStack;
-        f.ctx.uc_link = nullptr;
-        makecontext(&f.ctx, fiber_entry, 0);
+        // a fresh stack that hipemu_switch "returns" into fiber_entry from:
+        // six zero register slots, then the entry address at a 16-byte
+        // boundary, so that the entry sees the stack of a function call
+        uintptr_t top = (reinterpret_cast<uintptr_t>(f.stack) + kStack) & ~(uintptr_t)15;
+        void** slot = reinterpret_cast<void**>(top - 16);
+        slot[0] = reinterpret_cast<void*>(&fiber_entry);
+        for (int k = 1; k <= 6; ++k) slot[-k] = nullptr;
+        f.sp = slot - 6;
     }
     const int nw = (n + 63) / 64;
     for (;;) {
@@ -523,7 +543,7 @@ inline void run_block(const std::function<void()>& fn) {
 #ifdef HIPEMU_ASAN
             __sanitizer_start_switch_fiber(&fake, f.stack, kStack);
 #endif
-            swapcontext(&r.sched, &f.ctx);
+            hipemu_switch(&r.sched_sp, f.sp);
 #ifdef HIPEMU_ASAN
             __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
 #endif
