@@ -290,12 +290,6 @@ def sweep(a):
                       "workload": "d2q9_1024x512_R120_N1024_run0-9", "runs": runs}), flush=True)
 
 
-# Rest criterion of the time-to-equilibrium runs: largest normal node speed
-# below 1e-5 lattice units per step for 10 checks 1000 steps apart, while the
-# angle from the half-height moved by less than 0.01 degrees over them.
-REST = dict(tol=1e-5, angle_tol_deg=0.01, check_every=1000, hold=10)
-
-
 def tte(a):
     """Time to equilibrium of held-out batch droplets: the plain solver (fp32
     storage, 90-degree cap, fluid at rest) against fp16 storage with the
@@ -308,6 +302,7 @@ def tte(a):
     import numpy as np
     import workloads as wl
     from paper_2503_20605_amd import warmstart as ws
+    REST = ws.REST
     if a.max_steps is None:
         a.max_steps = 800000
     t0 = time.perf_counter()

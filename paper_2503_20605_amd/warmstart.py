@@ -36,6 +36,10 @@ U_MAX = 1e-3              # predicted velocities are clipped to this magnitude
 H_MIN = 0.85              # predicted nodes stay at least this many xi above the wall
 MAX_TURN_DEG = 175.0      # a predicted outline turning more sharply than this folds back
 PHI = 2.0 * math.pi * np.arange(K_RAYS) / K_RAYS
+# rest criterion of the time-to-equilibrium runs (see Solver.run_to_rest):
+# normal node speed below 1e-5 and the angle from the half-height steady
+# within 0.01 deg over 10 checks 1000 steps apart
+REST = dict(tol=1e-5, angle_tol_deg=0.01, check_every=1000, hold=10)
 
 
 # ---------------------------------------------------------------------------
@@ -431,7 +435,8 @@ def main(argv):
         n_train = int(os.environ.get("IBLB_WARM_TRAIN", "4096"))
         draws = wl.batch_draws(n_train, seed=5)
         X, Y, S = generate(draws, storage=1,
-                           max_steps=int(os.environ.get("IBLB_WARM_GEN_STEPS", "100000")), log=log)
+                           max_steps=int(os.environ.get("IBLB_WARM_GEN_STEPS", "800000")), log=log,
+                           rest=REST)
         np.savez(os.path.join(out_dir, "train.npz"), X=X.astype(np.float32),
                  Y=Y.astype(np.float32), S=S)
         log(f"[generate] saved {len(X)} equilibria")
@@ -445,14 +450,14 @@ def main(argv):
                   open(os.path.join(out_dir, "train.json"), "w"))
     elif what == "evaluate":
         from . import MLP
-        max_steps = int(os.environ.get("IBLB_WARM_EVAL_STEPS", "200000"))
+        max_steps = int(os.environ.get("IBLB_WARM_EVAL_STEPS", "800000"))
         n_test = int(os.environ.get("IBLB_WARM_TEST", "512"))
         draws = wl.batch_draws(n_test, seed=6)
         m = MLP(WIDTHS, n_test)
         net = np.load(os.path.join(out_dir, "net.npz"))
         m.set_params(net["params"])
         scale = (net["mu"], net["sd"])
-        res = evaluate_arms(draws, m, scale, max_steps, log=log)
+        res = evaluate_arms(draws, m, scale, max_steps, log=log, rest=REST)
         summary = summarize(draws, res, max_steps)
         json.dump(summary, open(os.path.join(out_dir, "evaluate.json"), "w"), indent=1)
         log(json.dumps(summary))
