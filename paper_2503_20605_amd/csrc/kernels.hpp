@@ -193,8 +193,9 @@ __device__ __forceinline__ bool cell_inside(const DropDev& D, const int* __restr
 // ---------------------------------------------------------------------------
 // Lattice kernel
 // ---------------------------------------------------------------------------
-// NT = 1 writes the new populations with non-temporal stores: they are not
-// read again before the next launch, so they need not displace cached lines.
+// NT = 1 writes the new populations with non-temporal stores (fp32 ones
+// with sc1 as well, see nt_store_policy): they are not read again before
+// the next launch, so they need not displace cached lines.
 // NTL = 1 reads the populations with non-temporal loads: each is read once
 // per launch (neighbouring wavefronts share only the edges of the lines
 // that x-streamed populations straddle).
@@ -354,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         const float fn = M.relax(i, f[i], om, g, forced);
         const int lo = i == 0 ? 0 : ((i & 1) ? i : i - 1);
         const auto rd = buffer_of(fdst + (long long)lo * fst, (i == 0 ? 1 : 2) * fst * SB);
-        C::template store_buf<NT ? kBufNT : 0>(rd, (unsigned)((i - lo) * fst + cell) * SB, fn);
+        C::template store_buf<NT ? nt_store_policy<S>() : 0>(rd, (unsigned)((i - lo) * fst + cell) * SB, fn);
     }
 
     if (band && D.force_mode == 0) {
