@@ -79,3 +79,20 @@ def test_respacing_keeps_a_long_run_closed():
     assert worst_gap < 1.5
     assert worst_area < 0.02
     assert max(th[2:]) - min(th[2:]) < 0.5
+
+
+def test_respacing_arguments_are_checked():
+    from paper_2503_20605_amd import IblbError
+    W = wl.droplet_3d(theta_eq_deg=90.0, small=True)
+    s3 = gpu_solver([W.params], [W.nodes], [W.tris])
+    with pytest.raises(IblbError):
+        s3.set_node_respacing(0, 0.1)          # a 3D mesh has no outline to re-space
+    p = wl.Params(dim=2, nx=64, ny=32, tau=0.9, sigma=0.005, theta_eq_deg=90.0, xi=2.0)
+    s2 = gpu_solver([p], [wl.cap_polygon(8.0, 90.0, 2.0, 60, 32.0)])
+    for bad in (-0.1, 1.0, float("nan")):
+        with pytest.raises(IblbError):
+            s2.set_node_respacing(0, bad)
+    with pytest.raises(IblbError):
+        s2.set_node_respacing(1, 0.1)          # no such droplet
+    s2.set_node_respacing(0, 0.0)
+    s2.set_node_respacing(0, 0.999)
