@@ -519,8 +519,8 @@ void launch_spread(const iblb_ctx* c, hipStream_t s, int p, int want_dropped) {
                            want_dropped);
         return;
     }
-    hipLaunchKernelGGL(one ? k_force3<true> : k_force3<false>, dim3(ceil_div(c->L.ntot, kBlock)), dim3(kBlock), 0, s,
-                       D, A);
+    hipLaunchKernelGGL(one ? k_force3<true> : k_force3<false>, dim3(ceil_div(c->L.ntot * kForceLanes, kBlock)),
+                       dim3(kBlock), 0, s, D, A);
     if (c->nchunks == 0) return;
     hipLaunchKernelGGL(k_spread3, dim3(c->nchunks), dim3(kSpreadBlock), 0, s, D, A,
                        (const int4*)c->at<int4>(c->L.chunks), c->at<unsigned long long>(c->L.Fq),

@@ -1111,19 +1111,59 @@ __global__ __launch_bounds__(kNodeBlock) void k_interp_advect(const DropDev* __r
 // ---------------------------------------------------------------------------
 // 3D: nodal forces, then spreading aggregated in LDS (eq. force_spread)
 // ---------------------------------------------------------------------------
-// Forces of every vertex (membrane + wetting), one lane per vertex.
+template <int G>
+__device__ __forceinline__ double group_sum_d(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Forces of every vertex (membrane + wetting): a group of kForceLanes lanes
+// per vertex, each lane taking its own incident triangles (one for the
+// usual vertex), their contributions summed across the group; the group's
+// first lane adds the wetting term and writes the force.  Against one lane
+// per vertex that walks its triangles in turn (three batched rounds of
+// loads, then 5-6 FP64 triangle evaluations in sequence) the chain per lane
+// is one triangle long and the launch has eight times the wavefronts.
+constexpr int kForceLanes = 8;
 template <bool ONE>
 __global__ __launch_bounds__(kBlock) void k_force3(const DropDev* __restrict__ drops, NodeArrays A) {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= A.ntot) return;
+    const int gid = blockIdx.x * kBlock + threadIdx.x;
+    const int j = gid / kForceLanes, k = gid % kForceLanes;
+    if (j >= A.ntot) return;  // the whole group leaves together
     const DropDev& D = drops[node_droplet<ONE>(A, j)];
     if (!D.active || D.force_mode != 0) return;
-    double q[3], fs[3], n[3], chi;
-    node_geom_3d(D, A, j, q, fs, n, chi);
+    const int st = A.stride, ts = A.tstride;
+    const double q[3] = {A.pos[j], A.pos[st + j], A.pos[2 * st + j]};
+    const int beg = A.inc_beg[j], cnt = A.inc_end[j] - beg;
+    double fs[3] = {0.0, 0.0, 0.0}, ns[3] = {0.0, 0.0, 0.0}, chi = 0.0;
+    for (int i = k; i < cnt; i += kForceLanes) {
+        const int e = A.inc[beg + i];
+        const int t = e >> 2, s = e & 3;
+        const int sb = s == 2 ? 0 : s + 1, sc = s == 0 ? 2 : s - 1;
+        const int vb = A.tri[sb * ts + t], vc = A.tri[sc * ts + t];
+        // vertex slot s of triangle t is node j itself
+        double P[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            P[s][a] = q[a];
+            P[sb][a] = A.pos[a * st + vb];
+            P[sc][a] = A.pos[a * st + vc];
+        }
+        tri_contrib(D, A, t, s, P, fs, ns, chi);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        fs[a] = group_sum_d<kForceLanes>(fs[a]);
+        ns[a] = group_sum_d<kForceLanes>(ns[a]);
+    }
+    chi = group_sum_d<kForceLanes>(chi);
+    if (k != 0) return;
     if (D.wetting) {
+        const double nn = sqrt(ns[0] * ns[0] + ns[1] * ns[1] + ns[2] * ns[2]);
         const double P = wetting_pi(D, q[2]);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) fs[a] -= (chi / 3.0) * P * n[a];
+        for (int a = 0; a < 3; ++a) fs[a] -= (chi / 3.0) * P * (ns[a] / nn);
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) A.phi[a * A.stride + j] = (float)fs[a];
