@@ -40,7 +40,8 @@ struct MlpLayout {
     std::vector<long long> woff, boff;  // offsets in the packed parameter vector
     long long P = 0;
     size_t master, grad, m, v, wb, xb, partial, total;
-    size_t dZf[2], dZb[2];  // output-side gradients of two consecutive layers, used in turn
+    size_t dZf;     // the last layer's output-side gradient (fp32, for its bias gradient)
+    size_t dZb[2];  // output-side gradients (bf16) of two consecutive layers, used in turn
     std::vector<size_t> Z, H;  // Z[l]: layer l output (fp32); H[l]: layer l input (bf16)
 };
 
@@ -78,10 +79,8 @@ bool mlp_plan(int L, const int* widths, int B, MlpLayout& Y, std::string& err) {
         Y.H[l] = take(2ull * B * Y.w[l]);
     }
     Y.xb = Y.H[0];
-    for (int h = 0; h < 2; ++h) {
-        Y.dZf[h] = take(4ull * B * Y.maxw);
-        Y.dZb[h] = take(2ull * B * Y.maxw);
-    }
+    Y.dZf = take(4ull * B * Y.w[L]);
+    for (int h = 0; h < 2; ++h) Y.dZb[h] = take(2ull * B * Y.maxw);
     Y.partial = take(8ull * mlp_cdiv((long long)B * Y.w[L], kMlpBlock));
     Y.total = o;
     return true;
@@ -133,22 +132,23 @@ int pieces_ok(const Operand& X, int ext) {
 
 template <int KP>
 void launch_gemm(const iblb_mlp* c, dim3 grid, const Operand& A, const Operand& B, float* Cf, uint16_t* Hb,
-                 long long ldc, const float* bias, const float* Zpre, int M, int N, int K, int act, int kc,
+                 long long ldc, const float* bias, const float* Zpre, float* colsum, int M, int N, int K, int act,
+                 int kc,
                  int avec, int bvec) {
     const dim3 block(kMlpBlock);
     const int sel = 2 * A.t + B.t;
     if (sel == 0)
         hipLaunchKernelGGL((k_gemm_bf16<0, 0, KP>), grid, block, 0, c->stream, A.p, A.ld, B.p, B.ld, Cf, Hb,
-                           ldc, bias, Zpre, M, N, K, act, kc, avec, bvec);
+                           ldc, bias, Zpre, colsum, M, N, K, act, kc, avec, bvec);
     else if (sel == 1)
         hipLaunchKernelGGL((k_gemm_bf16<0, 1, KP>), grid, block, 0, c->stream, A.p, A.ld, B.p, B.ld, Cf, Hb,
-                           ldc, bias, Zpre, M, N, K, act, kc, avec, bvec);
+                           ldc, bias, Zpre, colsum, M, N, K, act, kc, avec, bvec);
     else if (sel == 2)
         hipLaunchKernelGGL((k_gemm_bf16<1, 0, KP>), grid, block, 0, c->stream, A.p, A.ld, B.p, B.ld, Cf, Hb,
-                           ldc, bias, Zpre, M, N, K, act, kc, avec, bvec);
+                           ldc, bias, Zpre, colsum, M, N, K, act, kc, avec, bvec);
     else
         hipLaunchKernelGGL((k_gemm_bf16<1, 1, KP>), grid, block, 0, c->stream, A.p, A.ld, B.p, B.ld, Cf, Hb,
-                           ldc, bias, Zpre, M, N, K, act, kc, avec, bvec);
+                           ldc, bias, Zpre, colsum, M, N, K, act, kc, avec, bvec);
 }
 
 // C (M x N, leading dimension ldc) = A B.  With split_k, K is divided over
@@ -160,7 +160,8 @@ void launch_gemm(const iblb_mlp* c, dim3 grid, const Operand& A, const Operand& 
 // training step of the 4-256-256-256-1280 network on 4096 samples took
 // 0.297 against 0.313 ms.
 void gemm(const iblb_mlp* c, const Operand& A, const Operand& B, float* Cf, uint16_t* Hb, long long ldc,
-          const float* bias, const float* Zpre, int M, int N, int K, int act, bool split_k = false) {
+          const float* bias, const float* Zpre, int M, int N, int K, int act, bool split_k = false,
+          float* colsum = nullptr) {
     constexpr int KP = 128;
     const long long tiles = mlp_cdiv(N, 64) * mlp_cdiv(M, 64);
     int splits = 1;
@@ -172,7 +173,7 @@ void gemm(const iblb_mlp* c, const Operand& A, const Operand& B, float* Cf, uint
     splits = (int)mlp_cdiv(K, kc);
     const int avec = pieces_ok(A, A.t == 0 ? K : M), bvec = pieces_ok(B, B.t == 0 ? K : N);
     const dim3 grid((unsigned)mlp_cdiv(N, 64), (unsigned)mlp_cdiv(M, 64), (unsigned)splits);
-    launch_gemm<KP>(c, grid, A, B, Cf, Hb, ldc, bias, Zpre, M, N, K, act, kc, avec, bvec);
+    launch_gemm<KP>(c, grid, A, B, Cf, Hb, ldc, bias, Zpre, colsum, M, N, K, act, kc, avec, bvec);
 }
 
 // forward pass of `batch` rows from device fp32 input x
@@ -378,21 +379,27 @@ int iblb_mlp_gradients(iblb_mlp* c, const float* d_x, const float* d_t, int batc
                        Y.P);
     // dZ of layer l lives in buffer pair (L - 1 - l) % 2
     hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(kMlpBlock), 0, c->stream, (const float*)c->at<float>(Y.Z[L - 1]),
-                       d_t, c->at<float>(Y.dZf[0]), c->at<uint16_t>(Y.dZb[0]), c->at<double>(Y.partial), ny);
+                       d_t, c->at<float>(Y.dZf), c->at<uint16_t>(Y.dZb[0]), c->at<double>(Y.partial), ny);
     for (int l = L - 1; l >= 0; --l) {
         const int in = Y.w[l], out = Y.w[l + 1];
         const int h = (L - 1 - l) & 1;
-        const float* dZf = c->at<float>(Y.dZf[h]);
         const uint16_t* dZb = c->at<uint16_t>(Y.dZb[h]);
-        // bias: column sums of dZ; weights: H^T dZ (K = batch, split over
-        // workgroups); input side: dZ W^T, times GELU'(Z) of the layer below
-        hipLaunchKernelGGL(k_colsum, dim3((unsigned)mlp_cdiv(out, 64), (unsigned)mlp_cdiv(batch, kColsumRows)),
-                           dim3(kColsumBlock), 0, c->stream, dZf, grad + Y.boff[l], batch, out);
+        // bias: column sums of dZ (the last layer's here; the others' in the
+        // epilogue of the product that forms their dZ); weights: H^T dZ
+        // (K = batch, split over workgroups); input side: dZ W^T, times
+        // GELU'(Z) of the layer below
+        if (l == L - 1)
+            hipLaunchKernelGGL(k_colsum, dim3((unsigned)mlp_cdiv(out, 64), (unsigned)mlp_cdiv(batch, kColsumRows)),
+                               dim3(kColsumBlock), 0, c->stream, (const float*)c->at<float>(Y.dZf), grad + Y.boff[l],
+                               batch, out);
         gemm(c, {c->at<uint16_t>(Y.H[l]), in, 1}, {dZb, out, 1}, grad + Y.woff[l], nullptr, out, nullptr, nullptr,
              in, out, batch, 0, true);
         if (l > 0)
-            gemm(c, {dZb, out, 0}, {c->at<uint16_t>(Y.wb) + Y.woff[l], out, 0}, c->at<float>(Y.dZf[h ^ 1]),
-                 c->at<uint16_t>(Y.dZb[h ^ 1]), in, nullptr, c->at<float>(Y.Z[l - 1]), batch, in, out, 2);
+            // (dZ of the layer below is needed in bf16 only: its column sums
+            // are formed here)
+            gemm(c, {dZb, out, 0}, {c->at<uint16_t>(Y.wb) + Y.woff[l], out, 0}, nullptr,
+                 c->at<uint16_t>(Y.dZb[h ^ 1]), in, nullptr, c->at<float>(Y.Z[l - 1]), batch, in, out, 2, false,
+                 grad + Y.boff[l - 1]);
     }
     MLPCHK(c, hipGetLastError());
     c->last_batch = batch;

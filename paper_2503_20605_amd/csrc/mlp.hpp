@@ -55,7 +55,9 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // outside M x N x [kbeg, kend) read as zero.
 // Epilogue (act): 0: Cf = C + bias; 1: Cf = Z = C + bias, Hb = bf16(GELU(Z));
 // 2: Cf = C * GELU'(Zpre), Hb = its bf16 copy (the backward of a GELU layer,
-// Zpre its pre-activation, same layout as Cf).  With gridDim.z = S > 1 the
+// Zpre its pre-activation, same layout as Hb; Cf may be null), and, when
+// colsum is given, colsum[j] += the sum of column j over the rows (added
+// atomically).  With gridDim.z = S > 1 the
 // workgroups of z take k in [z kc, (z + 1) kc) and add their partial
 // products to Cf atomically (Cf zeroed beforehand; no bias, act = 0).
 //
@@ -114,7 +116,8 @@ template <int AT, int BT, int KP>
 __global__ __launch_bounds__(kMlpBlock) void k_gemm_bf16(
     const uint16_t* __restrict__ A, long long lda, const uint16_t* __restrict__ B, long long ldb,
     float* __restrict__ Cf, uint16_t* __restrict__ Hb, long long ldc, const float* __restrict__ bias,
-    const float* __restrict__ Zpre, int M, int N, int K, int act, int kc, int avec, int bvec) {
+    const float* __restrict__ Zpre, float* __restrict__ colsum, int M, int N, int K, int act, int kc,
+    int avec, int bvec) {
     constexpr int LD = KP + 8, NV = KP / 32;
     __shared__ __attribute__((aligned(16))) uint16_t As[64 * LD];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * LD];
@@ -169,6 +172,7 @@ __global__ __launch_bounds__(kMlpBlock) void k_gemm_bf16(
         return;
     }
     const float bj = bias ? bias[j] : 0.f;
+    float cs = 0.f;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int i = ib + wi + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -176,13 +180,20 @@ __global__ __launch_bounds__(kMlpBlock) void k_gemm_bf16(
         const long long o = (long long)i * ldc + j;
         if (act == 2) {
             const float g = acc[r] * gelu_grad(Zpre[o]);
-            Cf[o] = g;
+            if (Cf) Cf[o] = g;
             Hb[o] = f32_to_bf16_rne(g);
+            cs += g;
         } else {
             const float z = acc[r] + bj;
             Cf[o] = z;
             if (act) Hb[o] = f32_to_bf16_rne(gelu(z));
         }
+    }
+    if (act == 2 && colsum) {
+        // the column sums of dZ (the bias gradient of the layer below):
+        // lanes l and l ^ 32 hold the two halves of column j's 32 rows
+        cs += __shfl_xor(cs, 32, 64);
+        if (lane < 32) unsafeAtomicAdd(colsum + j, cs);
     }
 }
 
