@@ -40,7 +40,6 @@ struct MlpLayout {
     std::vector<long long> woff, boff;  // offsets in the packed parameter vector
     long long P = 0;
     size_t master, grad, m, v, wb, xb, partial, total;
-    size_t dZf;     // the last layer's output-side gradient (fp32, for its bias gradient)
     size_t dZb[2];  // output-side gradients (bf16) of two consecutive layers, used in turn
     std::vector<size_t> Z, H;  // Z[l]: layer l output (fp32); H[l]: layer l input (bf16)
 };
@@ -79,9 +78,8 @@ bool mlp_plan(int L, const int* widths, int B, MlpLayout& Y, std::string& err) {
         Y.H[l] = take(2ull * B * Y.w[l]);
     }
     Y.xb = Y.H[0];
-    Y.dZf = take(4ull * B * Y.w[L]);
     for (int h = 0; h < 2; ++h) Y.dZb[h] = take(2ull * B * Y.maxw);
-    Y.partial = take(8ull * mlp_cdiv((long long)B * Y.w[L], kMlpBlock));
+    Y.partial = take(8ull * mlp_cdiv(Y.w[L], 64) * mlp_cdiv(B, kColsumRows));
     Y.total = o;
     return true;
 }
@@ -372,26 +370,25 @@ int iblb_mlp_gradients(iblb_mlp* c, const float* d_x, const float* d_t, int batc
     const MlpLayout& Y = c->Y;
     const int L = Y.L;
     const long long ny = (long long)batch * Y.w[L];
-    const int nblk = (int)mlp_cdiv(ny, kMlpBlock);
+    const dim3 lgrid((unsigned)mlp_cdiv(Y.w[L], 64), (unsigned)mlp_cdiv(batch, kColsumRows));
+    const int nblk = (int)(lgrid.x * lgrid.y);
     float* grad = c->at<float>(Y.grad);
     // the gradients of every layer are accumulated atomically: zeroed first
     hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)mlp_cdiv(Y.P, kMlpBlock)), dim3(kMlpBlock), 0, c->stream, grad,
                        Y.P);
-    // dZ of layer l lives in buffer pair (L - 1 - l) % 2
-    hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(kMlpBlock), 0, c->stream, (const float*)c->at<float>(Y.Z[L - 1]),
-                       d_t, c->at<float>(Y.dZf), c->at<uint16_t>(Y.dZb[0]), c->at<double>(Y.partial), ny);
+    // dZ of layer l lives in buffer (L - 1 - l) % 2; the loss gradient also
+    // gives the last layer's bias gradient
+    hipLaunchKernelGGL(k_mse_colsum, lgrid, dim3(kColsumBlock), 0, c->stream,
+                       (const float*)c->at<float>(Y.Z[L - 1]), d_t, c->at<uint16_t>(Y.dZb[0]),
+                       grad + Y.boff[L - 1], c->at<double>(Y.partial), batch, Y.w[L]);
     for (int l = L - 1; l >= 0; --l) {
         const int in = Y.w[l], out = Y.w[l + 1];
         const int h = (L - 1 - l) & 1;
         const uint16_t* dZb = c->at<uint16_t>(Y.dZb[h]);
-        // bias: column sums of dZ (the last layer's here; the others' in the
-        // epilogue of the product that forms their dZ); weights: H^T dZ
+        // bias: the column sums of dZ, formed with dZ itself (k_mse_colsum,
+        // or the epilogue of the product that forms it); weights: H^T dZ
         // (K = batch, split over workgroups); input side: dZ W^T, times
         // GELU'(Z) of the layer below
-        if (l == L - 1)
-            hipLaunchKernelGGL(k_colsum, dim3((unsigned)mlp_cdiv(out, 64), (unsigned)mlp_cdiv(batch, kColsumRows)),
-                               dim3(kColsumBlock), 0, c->stream, (const float*)c->at<float>(Y.dZf), grad + Y.boff[l],
-                               batch, out);
         gemm(c, {c->at<uint16_t>(Y.H[l]), in, 1}, {dZb, out, 1}, grad + Y.woff[l], nullptr, out, nullptr, nullptr,
              in, out, batch, 0, true);
         if (l > 0)

@@ -12,10 +12,9 @@
 //                   accumulation); epilogue: + bias, optional GELU (keeps
 //                   the fp32 pre-activation and writes the bf16
 //                   activation), or the GELU backward dZ = C * GELU'(Z)
-//   k_colsum        bias gradient (column sums of dZ): 64 columns x 256
-//                   rows per workgroup, reduced in LDS, then added
-//                   atomically
-//   k_mse           loss and dY = 2 (Y - T) / (B n)
+//   k_mse_colsum    loss, dY = 2 (Y - T) / (B n) and the last layer's bias
+//                   gradient (column sums of dY): 64 columns x 256 rows
+//                   per workgroup, reduced in LDS, then added atomically
 //   k_adam          Adam update of the fp32 master weights + bf16 copy
 #pragma once
 
@@ -197,27 +196,56 @@ __global__ __launch_bounds__(kMlpBlock) void k_gemm_bf16(
     }
 }
 
-// out[j] += sum_i X[i * N + j] (out zeroed beforehand): workgroup
-// (bx, by) takes 64 columns and rows [by kColsumRows, (by + 1) kColsumRows);
-// its 16 lane groups sum every 16th row, the 16 partial sums are added in
-// LDS and the result atomically to out.
+// The loss gradient of the last layer and its column sums: dY = 2 (Y - T) /
+// (M N) for Y, T of M rows and N columns (row-major), written in bf16 for
+// the products; colsum[j] += sum_i dY(i, j) (zeroed beforehand; the bias
+// gradient); partial[block] = sum of (Y - T)^2 over the block's elements in
+// fp64 (the loss, summed on the host in block order).  Workgroup (bx, by)
+// takes 64 columns and rows [by kColsumRows, (by + 1) kColsumRows); its 16
+// lane groups take every 16th row; the partial sums meet in LDS and each
+// column's goes out with one atomic.
 constexpr int kColsumBlock = 1024;
 constexpr int kColsumRows = 256;
-__global__ __launch_bounds__(kColsumBlock) void k_colsum(const float* __restrict__ X,
-                                                          float* __restrict__ out, int M, int N) {
+__global__ __launch_bounds__(kColsumBlock) void k_mse_colsum(const float* __restrict__ Y,
+                                                              const float* __restrict__ T,
+                                                              uint16_t* __restrict__ dYb,
+                                                              float* __restrict__ colsum,
+                                                              double* __restrict__ partial, int M, int N) {
     __shared__ float part[16][64];
+    __shared__ double sq[16][64];
     const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int j = blockIdx.x * 64 + c;
     const int i0 = blockIdx.y * kColsumRows, i1 = i0 + kColsumRows < M ? i0 + kColsumRows : M;
+    const float scale = 2.f / (float)((long long)M * N);
     float s = 0.f;
+    double e2 = 0.0;
     if (j < N)
-        for (int i = i0 + g; i < i1; i += 16) s += X[(long long)i * N + j];
+        for (int i = i0 + g; i < i1; i += 16) {
+            const long long o = (long long)i * N + j;
+            const float e = Y[o] - T[o];
+            const float d = scale * e;
+            dYb[o] = f32_to_bf16_rne(d);
+            s += d;
+            e2 += (double)e * e;
+        }
     part[g][c] = s;
+    sq[g][c] = e2;
     __syncthreads();
-    if (g == 0 && j < N) {
+    if (g == 0) {
         float t = 0.f;
-        for (int k = 0; k < 16; ++k) t += part[k][c];
-        unsafeAtomicAdd(out + j, t);
+        double q = 0.0;
+        for (int k = 0; k < 16; ++k) {
+            t += part[k][c];
+            q += sq[k][c];
+        }
+        if (j < N) unsafeAtomicAdd(colsum + j, t);
+        sq[0][c] = q;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double q = 0.0;
+        for (int k = 0; k < 64; ++k) q += sq[0][k];
+        partial[blockIdx.y * gridDim.x + blockIdx.x] = q;
     }
 }
 
@@ -225,29 +253,6 @@ __global__ __launch_bounds__(kColsumBlock) void k_colsum(const float* __restrict
 __global__ void k_zero_f32(float* __restrict__ x, long long n) {
     const long long i = (long long)blockIdx.x * kMlpBlock + threadIdx.x;
     if (i < n) x[i] = 0.f;
-}
-
-// dY = 2 (Y - T) / n (fp32 and bf16), per-block partial sums of (Y - T)^2
-__global__ void k_mse(const float* __restrict__ Y, const float* __restrict__ T,
-                      float* __restrict__ dYf, uint16_t* __restrict__ dYb,
-                      double* __restrict__ partial, long long n) {
-    __shared__ double sh[kMlpBlock];
-    const long long i = (long long)blockIdx.x * kMlpBlock + threadIdx.x;
-    double e2 = 0.0;
-    if (i < n) {
-        const float e = Y[i] - T[i];
-        const float g = 2.f * e / (float)n;
-        dYf[i] = g;
-        dYb[i] = f32_to_bf16_rne(g);
-        e2 = (double)e * e;
-    }
-    sh[threadIdx.x] = e2;
-    __syncthreads();
-    for (int o = kMlpBlock / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
 // Adam (Kingma & Ba) on the fp32 master copy; bc1 = 1 - beta1^t,
