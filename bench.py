@@ -32,17 +32,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-# lattice-kernel variants: block width along x (0: flat runs of 256 cells),
-# non-temporal stores, non-temporal loads
+# lattice-kernel forms (variant % 16): block width along x (0: flat runs of
+# 256 cells), non-temporal stores, non-temporal loads; variant // 16 is the
+# block order (0: one contiguous run of tiles per XCD, 1: storage order)
 LB_BX = (256, 128, 64) * 4 + (0,) * 4
 LB_NT = (0, 0, 0, 1, 1, 1) * 2 + (0, 1, 0, 1)
 LB_NTL = (0,) * 6 + (1,) * 6 + (0, 0, 1, 1)
+LB_ORDER = ("xcd-runs", "storage")
 
 
 def lb_kernel_name(dim, storage, variant, vis=0, one=1):
     """Name of the lattice kernel instance as the kernel trace prints it; one:
     the form for a handle of a single droplet (used unless vis)."""
-    return (f"k_lb<{dim}, {storage}, {LB_BX[variant]}, {LB_NT[variant]}, {LB_NTL[variant]}, "
+    k = variant % 16
+    return (f"k_lb<{dim}, {storage}, {LB_BX[k]}, {LB_NT[k]}, {LB_NTL[k]}, "
             f"{vis}, {0 if vis else one}>")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lb_traffic.md")
 
@@ -53,33 +56,40 @@ def code_only(src):
     return re.sub(rb"\s+", b" ", re.sub(rb"//[^\n]*", b"", src)).strip()
 
 
-def lb_source_hash(lattice_src=None, kernels_src=None):
-    """Hash of the lattice kernel's code (lattice.hpp and the part of
-    kernels.hpp up to the end of the lattice kernel, comments and layout
-    left out), to tell whether stored counter readings still describe the
-    kernel as built."""
+def lb_source_hash(lattice_src=None, kernels_src=None, host_src=None):
+    """Hash of the lattice kernel's code (lattice.hpp, the part of
+    kernels.hpp up to the end of the lattice kernel, and the population
+    layout and tile order of iblb.hip; comments and layout left out), to tell
+    whether stored counter readings still describe the kernel as built."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2503_20605_amd", "csrc")
     lat = lattice_src if lattice_src is not None else open(os.path.join(csrc, "lattice.hpp"), "rb").read()
     k = kernels_src if kernels_src is not None else open(os.path.join(csrc, "kernels.hpp"), "rb").read()
+    hs = host_src if host_src is not None else open(os.path.join(csrc, "iblb.hip"), "rb").read()
     h = hashlib.sha256()
     h.update(code_only(lat))
     h.update(code_only(k[:k.index(b"// Nodes whose coordinates are not finite")]))
+    lo = hs.index(b"// Lattice-kernel variants (autotuner candidates)")
+    h.update(code_only(hs[lo:hs.index(b"int tiles_of(", lo)]))
+    lo = hs.index(b"// Tiles of droplet d in the given shape")
+    h.update(code_only(hs[lo:hs.index(b"// ---- kernel dispatch", lo)]))
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
-    """HBM-side bytes per launch of `kernel` on `workload` from the stored
-    FETCH_SIZE / WRITE_SIZE counter runs (each scaled by what the counter
-    reads for a copy of known size), or None when there is no reading for
-    this kernel and workload or the kernel's source changed since."""
+def measured_traffic(kernel, workload, order):
+    """HBM-side bytes per launch of `kernel` in block order `order` on
+    `workload` from the stored FETCH_SIZE / WRITE_SIZE counter runs (each
+    scaled by what the counter reads for a copy of known size), or None when
+    there is no reading for this kernel, order and workload or the kernel's
+    source changed since."""
     try:
         text = open(TRAFFIC_FILE).read()
         rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, ValueError, IndexError):
         return None
     for r in rec.get("readings", []):
-        if r["kernel"] == kernel and r["workload"] == workload and r["source_hash"] == lb_source_hash():
+        if (r["kernel"] == kernel and r["workload"] == workload and r.get("block_order") == order
+                and r["source_hash"] == lb_source_hash()):
             return round(r["fetch_bytes"] + r["write_bytes"])
     return None
 
@@ -98,7 +108,7 @@ def parse():
     ap.add_argument("--run", type=int, default=1, help="sweep point 0..9 of the 1024x512 set")
     ap.add_argument("--graph-steps", type=int, default=64)
     ap.add_argument("--variant", type=int, default=-1,
-                    help="lattice-kernel variant 0..15; -1 autotunes")
+                    help="lattice-kernel variant 0..31; -1 autotunes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the secondary lines (1024x512 D2Q9 step, lattice kernel alone on "
@@ -405,14 +415,15 @@ def lb_only_rate(dim, nx, ny, nz, storage, steps):
     gbs = bytes_per_cell(dim, storage) * cells / (lb_ms * 1e-3) / 1e9
     s.close()
     return {"lattice": f"{'D2Q9' if dim == 2 else 'D3Q19'} {nx}x{ny}" + (f"x{nz}" if dim == 3 else ""),
-            "storage": ["f32", "f16", "bf16"][storage], "variant": v,
+            "storage": ["f32", "f16", "bf16"][storage], "variant": v, "block_order": LB_ORDER[v // 16],
             "working_set_MB": round(bytes_per_cell(dim, storage) * cells / 1e6, 1),
             "lb_us": round(lb_ms * 1e3, 2),
             "MLUPS": round(cells / (lb_ms * 1e-3) / 1e6, 1),
             "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(lb_kernel_name(dim, storage, v),
                                         f"d{dim}q{9 if dim == 2 else 19}_{nx}x{ny}"
-                                        + (f"x{nz}" if dim == 3 else "") + "_lattice_only")}
+                                        + (f"x{nz}" if dim == 3 else "") + "_lattice_only",
+                                        LB_ORDER[v // 16])}
 
 
 def log(msg):
@@ -523,7 +534,7 @@ def main():
     # then the warm-up steps
     if a.variant < 0:
         variant, tune_ms = s.autotune(steps=2 * a.graph_steps + 2)
-        tune_steps = 16 * 2 * (2 * a.graph_steps + 2)
+        tune_steps = len(tune_ms) * 2 * (2 * a.graph_steps + 2)
     else:
         variant, tune_ms, tune_steps = s.set_lb_variant(a.variant), None, 0
     s.step(warm)
@@ -558,7 +569,7 @@ def main():
     bpc = bytes_per_cell(dim, storage)
     achieved = bpc * cells / (lb_ms * 1e-3) / 1e9
     lb_name = lb_kernel_name(dim, storage, variant, vis=int(lam != 1.0))
-    traffic = measured_traffic(lb_name, W.name)
+    traffic = measured_traffic(lb_name, W.name, LB_ORDER[variant // 16])
 
     out = {
         "metric": "MLUPS (coupled IB-LB step) + HBM GB/s fraction of the lattice kernel",
@@ -580,7 +591,7 @@ def main():
                    "triangles": None if W.tris is None else len(W.tris),
                    "viscosity_ratio": lam,
                    "tau": p.tau, "theta_eq_deg": p.theta_eq_deg, "sigma": p.sigma, "xi": p.xi,
-                   "storage": a.storage, "lb_variant": variant},
+                   "storage": a.storage, "lb_variant": variant, "block_order": LB_ORDER[variant // 16]},
         "roofline": {"kernel": lb_name + " (fused pull-stream + BGK + Guo)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

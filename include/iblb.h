@@ -228,8 +228,11 @@ int iblb_run_to_rest(iblb_ctx *ctx, double tol, double angle_tol, int check_ever
  *   12-15: 256 consecutive cells per block in storage order (no idle lanes
  *          when nx is not a multiple of 64): plain, non-temporal stores,
  *          non-temporal loads, both
+ *   16-31: as variant - 16 with the blocks in storage order of their tiles
+ *          (0-15 give each of the device's eight XCDs one contiguous run of
+ *          tiles)
  * variant = -1 keeps the current one; *variant_out (may be NULL) receives
- * the variant in use. */
+ * the variant in use; other values: IBLB_EINVAL. */
 int iblb_set_lb_variant(iblb_ctx *ctx, int variant, int *variant_out);
 
 /* Time every lattice-kernel variant on the handle's own coupled steps and
@@ -241,7 +244,7 @@ int iblb_set_lb_variant(iblb_ctx *ctx, int variant, int *variant_out);
  * steps advance the simulation.  With cache_path non-NULL the winner is
  * looked up in / appended to that text file, keyed by device, lattice,
  * storage and size bucket; a cache hit runs no step.  chosen (may be NULL)
- * receives the variant; ms (may be NULL, 16 entries) the measured
+ * receives the variant; ms (may be NULL, 32 entries) the measured
  * milliseconds per coupled step of each variant (-1 on a cache hit). */
 int iblb_autotune(iblb_ctx *ctx, int steps, const char *cache_path, int *chosen, double *ms);
 

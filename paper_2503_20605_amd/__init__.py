@@ -26,6 +26,8 @@ __all__ = ["Solver", "MLP", "make_params", "IblbError", "IBLB_F32", "IBLB_F16", 
            "IBLB_PERIODIC", "IBLB_WALL", "STORAGE", "probe_copy_bandwidth"]
 
 STORAGE = {"f32": IBLB_F32, "f16": IBLB_F16, "bf16": IBLB_BF16}
+# lattice-kernel variants: 16 kernel forms, each in two block orders
+LB_VARIANTS = 32
 
 
 def make_params(dim=2, nx=128, ny=64, nz=1, bc=None, tau=1.0, sigma=0.01, theta_eq_deg=90.0,
@@ -197,13 +199,13 @@ class Solver:
         return out.value
 
     def autotune(self, steps=130, cache_path=None):
-        """Time the sixteen lattice-kernel variants on the handle's own coupled
+        """Time the 32 lattice-kernel variants on the handle's own coupled
         steps and keep the fastest; returns (variant, per-variant ms per
         coupled step, or -1 on a cache hit).  The default runs the step graph
         (64 steps unless set otherwise) twice per timing; every step taken
         here advances the simulation."""
         out = ctypes.c_int()
-        ms = (ctypes.c_double * 16)()
+        ms = (ctypes.c_double * LB_VARIANTS)()
         cp = None if cache_path is None else str(cache_path).encode()
         self._chk(self.lib.iblb_autotune(self.ctx, int(steps), cp, ctypes.byref(out), ms))
         return out.value, list(ms)

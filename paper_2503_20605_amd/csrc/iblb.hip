@@ -30,16 +30,31 @@ using namespace iblb;
 
 namespace {
 
-// Lattice-kernel variants (autotuner candidates): tiles of 256x1, 128x2 or
-// 64x4 cells per block (shape v % 3), ordinary or non-temporal stores
-// ((v / 3) % 2), ordinary or non-temporal loads (v / 6) for v < 12; then
-// the flat form (256 consecutive cells per block, shape 3) with the four
-// load/store kinds (v = 12 + stores + 2 loads).
+// Lattice-kernel variants (autotuner candidates).  The kernel form k = v %
+// 16: tiles of 256x1, 128x2 or 64x4 cells per block (shape k % 3),
+// ordinary or non-temporal stores ((k / 3) % 2), ordinary or non-temporal
+// loads (k / 6) for k < 12; then the flat form (256 consecutive cells per
+// block, shape 3) with the four load/store kinds (k = 12 + stores + 2
+// loads).  The block order v / 16: 0 deals each XCD one contiguous run of
+// tiles, 1 keeps the tiles in storage order (blocks go round-robin to the
+// XCDs, so neighbouring tiles run on different XCDs at the same time).
 constexpr int kShapes = 4;
-constexpr int kVariants = 16;
+constexpr int kForms = 16;
+constexpr int kVariants = 2 * kForms;
 constexpr int kShapeBX[kShapes] = {256, 128, 64, 0};
 constexpr int kShapeBY[kShapes] = {1, 2, 4, 0};
-int shape_of(int variant) { return variant < 12 ? variant % 3 : 3; }
+int form_of(int variant) { return variant % kForms; }
+int order_of(int variant) { return variant / kForms; }
+int shape_of(int variant) { return form_of(variant) < 12 ? form_of(variant) % 3 : 3; }
+
+// Blocks are dealt round-robin to the eight XCDs (block b to XCD b % 8).
+// Position of the tile that block b takes when each XCD is to work through
+// one contiguous run of the nb tiles (x-neighbouring strips and
+// y-neighbouring rows then meet in the same L2).
+int xcd_run_tile(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7, l = b >> 3;
+    return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
 constexpr size_t kAlign = 256;
 constexpr int kMaxGraphSteps = 1024;
 constexpr int kTimedChunk = 256;  // timed lattice launches between two reads of their events
@@ -77,6 +92,16 @@ constexpr int kPopPad = IBLB_POP_PAD;
 #define IBLB_POP_ROUND 64
 #endif
 constexpr long long kPopRound = IBLB_POP_ROUND;
+// Element stride between the z-planes of a 3D population array: nx ny plus
+// kPlanePad.  With power-of-two planes the streams of the populations that
+// move along z sit a power of two bytes away from those that do not; a pad
+// of 32-64 elements made the D3Q19 update 3.5% faster on a 256x256x128 box
+// (1024 elements: no gain, 512: 7% slower).  Field arrays (rho, U, F) keep
+// the compact [z][y][x] layout.
+#ifndef IBLB_PLANE_PAD
+#define IBLB_PLANE_PAD 64
+#endif
+constexpr int kPlanePad = IBLB_PLANE_PAD;
 
 // Cell budget of a 3D spreading chunk's tap box when the host cuts chunks
 // (see morton_order); the kernel's own limit is kBoxCells.
@@ -90,6 +115,11 @@ int strips_of(int nx) { return (ceil_div(nx, kStrip) + 3) / 4 * 4; }
 
 long long pop_stride(long long cells) {
     return (cells + kPopRound - 1) / kPopRound * kPopRound + kPopPad;
+}
+
+// Elements per z-plane of a population array (2D: the whole box).
+long long plane_pitch(const iblb_params& p, int dim) {
+    return (long long)p.nx * p.ny + (dim == 3 ? kPlanePad : 0);
 }
 
 int tiles_of(const iblb_params& p, int shape) {
@@ -134,7 +164,8 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
             return false;
         }
         const long long cells = (long long)p.nx * p.ny * nz;
-        if ((long long)Q * pop_stride(cells) >= (1LL << 31)) {
+        const long long pcells = plane_pitch(p, dim) * nz;
+        if ((long long)Q * pop_stride(pcells) >= (1LL << 31)) {
             snprintf(buf, sizeof buf, "droplet %d: Q * cells must stay below 2^31", d);
             err = buf;
             return false;
@@ -168,7 +199,7 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
         }
         L.c_off[d] = L.cells;
         L.cells += cells;
-        L.fst[d] = pop_stride(cells);
+        L.fst[d] = pop_stride(pcells);
         L.f_off[d] = L.pop_elems;
         L.pop_elems += (long long)Q * L.fst[d];
         if (L.pop_elems >= (1LL << 40)) { err = "population arrays too large"; return false; }
@@ -409,6 +440,13 @@ int rebuild_tiles(iblb_ctx* c) {
         c->drops[d].n_tiles = (int)all.size() - c->drops[d].tile_off;
         if (c->drops[d].active) push_tiles(c, d, shape_of(c->variant), lb);
     }
+    if (order_of(c->variant) == 0) {
+        // block b takes tile xcd_run_tile(b): the list is laid out in
+        // block order, so the kernel reads entry blockIdx.x
+        std::vector<int4> runs(lb.size());
+        for (size_t b = 0; b < lb.size(); ++b) runs[b] = lb[xcd_run_tile((int)b, (int)lb.size())];
+        lb.swap(runs);
+    }
     c->ntiles_all = (int)all.size();
     c->ntiles_lb = (int)lb.size();
     HIPCHK(c, hipMemcpyAsync(c->at<int4>(c->L.tiles_all), all.data(), sizeof(int4) * all.size(),
@@ -450,7 +488,7 @@ void launch_lb_v(const iblb_ctx* c, hipStream_t s, int src, int full, const hipE
             },
             args);
     };
-    switch (c->variant) {
+    switch (form_of(c->variant)) {
         case 0: go(k_lb<DIM, S, 256, 0, 0, VIS, ONE>); break;
         case 1: go(k_lb<DIM, S, 128, 0, 0, VIS, ONE>); break;
         case 2: go(k_lb<DIM, S, 64, 0, 0, VIS, ONE>); break;
@@ -621,10 +659,10 @@ void launch_pop_io(iblb_ctx* c, int d, const double* in, double* out) {
     const long long n = (long long)c->Q * D.ncell;
     if (in)
         hipLaunchKernelGGL(k_pop_write<S>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, c->stream, f,
-                           D.ncell, D.fst, n, in);
+                           D.ncell, D.fst, D.nx * D.ny, D.ppl, n, in);
     else
         hipLaunchKernelGGL(k_pop_read<S>, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, c->stream,
-                           (const T*)f, D.ncell, D.fst, n, out);
+                           (const T*)f, D.ncell, D.fst, D.nx * D.ny, D.ppl, n, out);
 }
 
 int pop_io(iblb_ctx* c, int d, const double* in, double* out) {
@@ -778,6 +816,7 @@ int iblb_create(int n, const iblb_params* P, const int* nn, const int* nt, int s
         D.ncell = p.nx * p.ny * D.nz;
         D.f_off = L.f_off[d];
         D.fst = L.fst[d];
+        D.ppl = (int)plane_pitch(p, c->dim);
         D.c_off = L.c_off[d];
         D.flag_off = L.flag_off[d];
         D.omega = (float)(1.0 / p.tau);
@@ -1052,9 +1091,11 @@ void launch_init_eq(iblb_ctx* c, int d, const float* rho, const float* u) {
     T* f = c->at<T>(c->cur ? c->L.f1 : c->L.f0) + D.f_off;
     const dim3 grid(ceil_div(D.ncell, kBlock)), block(kBlock);
     if (c->dim == 2)
-        hipLaunchKernelGGL((k_init_eq<2, S>), grid, block, 0, c->stream, f, D.ncell, D.fst, rho, u);
+        hipLaunchKernelGGL((k_init_eq<2, S>), grid, block, 0, c->stream, f, D.ncell, D.fst, D.nx * D.ny, D.ppl,
+                           rho, u);
     else
-        hipLaunchKernelGGL((k_init_eq<3, S>), grid, block, 0, c->stream, f, D.ncell, D.fst, rho, u);
+        hipLaunchKernelGGL((k_init_eq<3, S>), grid, block, 0, c->stream, f, D.ncell, D.fst, D.nx * D.ny, D.ppl,
+                           rho, u);
 }
 
 }  // namespace
@@ -1376,7 +1417,7 @@ int iblb_run_to_rest(iblb_ctx* c, double tol, double angle_tol, int check_every,
 int iblb_set_lb_variant(iblb_ctx* c, int variant, int* variant_out) {
     if (!c) return IBLB_EINVAL;
     if (variant >= kVariants || variant < -1)
-        return fail(c, IBLB_EINVAL, "lattice-kernel variant must be -1 or 0..15");
+        return fail(c, IBLB_EINVAL, "lattice-kernel variant must be -1 or 0..31");
     if (variant >= 0 && variant != c->variant) {
         c->variant = variant;
         c->tiles_dirty = true;

@@ -65,7 +65,9 @@ struct DropDev {
     int tri_off, n_tris;
     int tile_off, n_tiles;  // this droplet's run in the list of all tiles
     int wetting, n_exp, m_exp;
-    int fst;              // element stride between population arrays (>= ncell)
+    int fst;              // element stride between population arrays (>= ppl nz)
+    int ppl;              // elements per z-plane of a population array (>= nx ny):
+                          // cell (x, y, z) sits at z ppl + y nx + x
     double sigma, A, xi, zcut;
     // two viscosities (viscosity ratio != 1): cells enclosed by the
     // interface relax with omega_in / guo_in
@@ -92,14 +94,6 @@ struct DiagDev {
     double cross_r;             // 3D: mean distance of crossings to their centre
     double cross_n;
 };
-
-// Blocks are dealt round-robin to the eight XCDs.  Remap the block index so
-// that each XCD works through one contiguous run of tiles: x-neighbouring
-// strips and y-neighbouring rows then meet in the same L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-    const int q = nb >> 3, r = nb & 7, x = b & 7, l = b >> 3;
-    return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
-}
 
 // Fixed-point accumulation of the spread force density (eq. force_spread):
 // every contribution phi_j Delta is rounded to an integer number of 2^-40
@@ -228,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
     constexpr int Q = L::Q;
     constexpr bool FLAT = BX == 0;
     constexpr int BY = FLAT ? 1 : kBlock / (FLAT ? 1 : BX);
-    const int4 tile = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const int4 tile = tiles[blockIdx.x];  // the host lays the list out in block order
     const DropDev& D = drops[ONE ? 0 : tile.x];
     const int nx = D.nx, ny = D.ny, nz = D.nz;
     int x, y, z;
@@ -245,8 +239,9 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         z = tile.w;
         if (x >= nx || y >= ny) return;
     }
-    const int ncell = D.ncell, fst = D.fst;
-    const int cell = (z * ny + y) * nx + x;
+    const int ncell = D.ncell, fst = D.fst, ppl = D.ppl;
+    const int cell = (z * ny + y) * nx + x;  // field arrays
+    const int pc = z * ppl + y * nx + x;      // population arrays
     const typename C::T* __restrict__ fsrc = fsrc_all + D.f_off;
     typename C::T* __restrict__ fdst = fdst_all + D.f_off;
 
@@ -296,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         const bool wall = (sx | sy | sz) < 0;
         const int lo = i == 0 ? 0 : ((i & 1) ? i : i - 1);
         const auto rs = buffer_of(fsrc + (long long)lo * fst, (i == 0 ? 1 : 2) * fst * SB);
-        const int rel = wall ? (opp(i) - lo) * fst + cell : (i - lo) * fst + (sz * ny + sy) * nx + sx;
+        const int rel = wall ? (opp(i) - lo) * fst + pc : (i - lo) * fst + sz * ppl + sy * nx + sx;
         f[i] = C::template load_buf<NTL ? kBufNT : 0>(rs, (unsigned)rel * SB);
     }
 
@@ -355,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         const float fn = M.relax(i, f[i], om, g, forced);
         const int lo = i == 0 ? 0 : ((i & 1) ? i : i - 1);
         const auto rd = buffer_of(fdst + (long long)lo * fst, (i == 0 ? 1 : 2) * fst * SB);
-        C::template store_buf<NT ? nt_store_policy<S>() : 0>(rd, (unsigned)((i - lo) * fst + cell) * SB, fn);
+        C::template store_buf<NT ? nt_store_policy<S>() : 0>(rd, (unsigned)((i - lo) * fst + pc) * SB, fn);
     }
 
     if (band && D.force_mode == 0) {
@@ -1484,12 +1479,17 @@ __global__ __launch_bounds__(kNodeBlock) void k_ib_fused2(const DropDev* __restr
 // Equilibrium populations (eq. f^eq, deviation form f_eq - w =
 // w (rho - 1) + w rho (3 c.u + 4.5 (c.u)^2 - 1.5 u^2)) from a density field
 // (null: 1) and a velocity field [dim][ncell] (null: 0), one lane per cell.
+// nxy cells per plane of the fields, ppl elements per plane of the
+// population arrays.
+__device__ __forceinline__ int pop_cell(int cell, int nxy, int ppl) { return cell + cell / nxy * (ppl - nxy); }
+
 template <int DIM, int S>
-__global__ void k_init_eq(typename Codec<S>::T* __restrict__ f, int ncell, int fst,
+__global__ void k_init_eq(typename Codec<S>::T* __restrict__ f, int ncell, int fst, int nxy, int ppl,
                           const float* __restrict__ rho_in, const float* __restrict__ u_in) {
     using L = Lattice<DIM>;
     const int cell = blockIdx.x * kBlock + threadIdx.x;
     if (cell >= ncell) return;
+    const int pc = pop_cell(cell, nxy, ppl);
     const float rho = rho_in ? rho_in[cell] : 1.f;
     float u[3] = {0.f, 0.f, 0.f};
     if (u_in)
@@ -1500,24 +1500,24 @@ __global__ void k_init_eq(typename Codec<S>::T* __restrict__ f, int ncell, int f
     for (int i = 0; i < L::Q; ++i) {
         const float cu = L::c[i][0] * u[0] + L::c[i][1] * u[1] + (DIM == 3 ? L::c[i][2] * u[2] : 0.f);
         const float v = L::w[i] * ((rho - 1.f) + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * usq));
-        Codec<S>::store(f, i * fst + cell, v);
+        Codec<S>::store(f, i * fst + pc, v);
     }
 }
 
 // Dense [Q][ncell] doubles on the caller's side, population arrays fst
-// elements apart in the workspace.
+// elements apart in the workspace, their planes ppl elements apart.
 template <int S>
-__global__ void k_pop_write(typename Codec<S>::T* __restrict__ f, int ncell, int fst, long long n,
-                            const double* __restrict__ src) {
+__global__ void k_pop_write(typename Codec<S>::T* __restrict__ f, int ncell, int fst, int nxy, int ppl,
+                            long long n, const double* __restrict__ src) {
     const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) f[(i / ncell) * fst + i % ncell] = Codec<S>::from_double(src[i]);
+    if (i < n) f[(i / ncell) * fst + pop_cell((int)(i % ncell), nxy, ppl)] = Codec<S>::from_double(src[i]);
 }
 
 template <int S>
-__global__ void k_pop_read(const typename Codec<S>::T* __restrict__ f, int ncell, int fst, long long n,
-                           double* __restrict__ dst) {
+__global__ void k_pop_read(const typename Codec<S>::T* __restrict__ f, int ncell, int fst, int nxy, int ppl,
+                           long long n, double* __restrict__ dst) {
     const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) dst[i] = Codec<S>::to_double(f[(i / ncell) * fst + i % ncell]);
+    if (i < n) dst[i] = Codec<S>::to_double(f[(i / ncell) * fst + pop_cell((int)(i % ncell), nxy, ppl)]);
 }
 
 // Streaming copy used to measure the attainable HBM bandwidth of the device:
@@ -1609,7 +1609,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_sums(const DropDev* __restrict_
         const int cell = (z * D.ny + y) * D.nx + x;
         const typename Codec<S>::T* f = f_all + D.f_off;
         double s = 0.0;
-        for (int i = 0; i < L::Q; ++i) s += (double)Codec<S>::load(f, i * D.fst + cell);
+        const int pc = z * D.ppl + y * D.nx + x;
+        for (int i = 0; i < L::Q; ++i) s += (double)Codec<S>::load(f, i * D.fst + pc);
         v[0] = s;
         const double rho = rho_all[D.c_off + cell];
         const float* U = U_all + (long long)DIM * D.c_off;

@@ -87,6 +87,9 @@ def _background_jobs():
                        masks=True),
         "rest": dict(params_list=ps, nodes_list=qs, steps=(0,), rest=(2e-3, 4, 2, 60), graph_steps=2),
         "tiny3d": dict(params_list=[p3], nodes_list=[V3], tris_list=[T3], steps=(3,), graph_steps=2),
+        # blocks in the storage order of their tiles, flat form
+        "tiny3d_storage_order": dict(params_list=[p3], nodes_list=[V3], tris_list=[T3], steps=(3,),
+                                     graph_steps=2, shape=31),
         "coarse3d": dict(params_list=[pc], nodes_list=[Vc], tris_list=[Tc], steps=(2,), graph_steps=2),
         "coarse3d_direct": dict(params_list=[pc], nodes_list=[Vc], tris_list=[Tc], steps=(2,),
                                 graph_steps=2, direct_chunks=True),
@@ -284,11 +287,12 @@ def test_two_viscosities_3d(background):
 
 def test_droplet_3d_tiny(background):
     p, V, T = _tiny3d_case()
-    g = background["tiny3d"].result()[0]
     r = o.run(p, V, 3, tris=T)
-    drho, du, dq = compare_fields(g, r, 3, "emu 3d")
-    assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
-    assert abs(g["diag"]["volume"] - o.volume_3d(r["q"], T)) < 1e-9 * abs(g["diag"]["volume"])
+    for key in ("tiny3d", "tiny3d_storage_order"):
+        g = background[key].result()[0]
+        drho, du, dq = compare_fields(g, r, 3, f"emu 3d {key}")
+        assert drho <= 1e-6 and du <= 1e-5 and dq <= 1e-7
+        assert abs(g["diag"]["volume"] - o.volume_3d(r["q"], T)) < 1e-9 * abs(g["diag"]["volume"])
 
 
 def test_droplet_3d_coarse_mesh_across_periodic_edge(background):
@@ -313,12 +317,14 @@ def test_streaming_bit_exact_all_storages(storage):
         w = weights(dim)
         dev = wl.tagged_deviation(Q, nx * ny * nz, 5).reshape(Q, nz, ny, nx)
         p = wl.Params(dim=dim, nx=nx, ny=ny, nz=nz, bc=bc, tau=math.inf, wetting=False)
-        g = run_case([p], steps=(3,), storage=storage, f0dev=[dev], graph_steps=2)[0]
         f = w[:, None, None, None] + dev
         for _ in range(3):
             f, _, _ = o.lb_step(dim, nx, ny, nz, bc, math.inf, f, None)
         k = np.rint((f - w[:, None, None, None]) * 1024.0)
-        assert np.array_equal(g["fdev"], k / 1024.0)
+        # default variant (tiles in runs per XCD) and a tiled one in storage order
+        for shape in (None, 17):
+            g = run_case([p], steps=(3,), storage=storage, f0dev=[dev], graph_steps=2, shape=shape)[0]
+            assert np.array_equal(g["fdev"], k / 1024.0), (dim, shape)
 
 
 def test_prescribed_force_field():

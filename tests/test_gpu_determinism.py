@@ -30,6 +30,18 @@ def test_3d_runs_repeat_bit_for_bit():
     _same(a, b, 3)
 
 
+@pytest.mark.parametrize("form", [9, 13])
+def test_3d_block_orders_agree_bit_for_bit(form):
+    """A lattice-kernel form with its blocks in runs per XCD (variant form)
+    and in the storage order of their tiles (form + 16): the order in which
+    blocks run changes no cell's update."""
+    W = wl.droplet_3d(theta_eq_deg=45.0, small=True)
+    print(f"[det] 3D 64x64x32, 80 steps, variants {form} and {form + 16}", flush=True)
+    a = gpu_run(W.params, W.nodes, 80, tris=W.tris, graph_steps=16, shape=form)
+    b = gpu_run(W.params, W.nodes, 80, tris=W.tris, graph_steps=16, shape=form + 16)
+    _same(a, b, 3)
+
+
 def test_3d_coarse_mesh_direct_path_repeats_bit_for_bit():
     """Coarse cap across the periodic edge: some chunks overflow their LDS
     box and add their taps straight to global memory."""

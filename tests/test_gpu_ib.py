@@ -30,7 +30,7 @@ def test_droplet_on_wall_1000_steps():
     assert np.max(np.abs(g["F"] - r["F"][:2])) <= 1e-5 * np.max(np.abs(r["F"]))
 
 
-@pytest.mark.parametrize("tile", list(range(16)))
+@pytest.mark.parametrize("tile", list(range(32)))
 def test_first_step_node_arrays(tile):
     """One step: nodal forces, spread field and interpolated velocities."""
     W = wl.droplet_2d_small()

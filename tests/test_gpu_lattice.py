@@ -26,7 +26,7 @@ STREAM_CASES = [
 
 @pytest.mark.parametrize("storage", [0, 1, 2], ids=["f32", "f16", "bf16"])
 @pytest.mark.parametrize("dim,shape,bc", STREAM_CASES)
-@pytest.mark.parametrize("tile", [0, 2, 3, 4, 6, 8, 10, 11, 12, 13, 14, 15])
+@pytest.mark.parametrize("tile", [0, 2, 3, 4, 6, 8, 10, 11, 12, 13, 14, 15, 16, 25, 31])
 def test_pure_streaming_bit_exact(dim, shape, bc, storage, tile):
     nx, ny, nz = shape
     Q = 9 if dim == 2 else 19
