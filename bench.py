@@ -87,9 +87,10 @@ def measured_traffic(kernel, workload, order):
         rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, ValueError, IndexError):
         return None
+    if rec.get("source_hash") != lb_source_hash():
+        return None
     for r in rec.get("readings", []):
-        if (r["kernel"] == kernel and r["workload"] == workload and r.get("block_order") == order
-                and r["source_hash"] == lb_source_hash()):
+        if r["kernel"] == kernel and r["workload"] == workload and r["block_order"] == order:
             return round(r["fetch_bytes"] + r["write_bytes"])
     return None
 
