@@ -509,7 +509,8 @@ def main():
         return
     if a.hbm_probe:
         from paper_2503_20605_amd import probe_copy_bandwidth
-        res = {"lb_hbm": lb_hbm_boxes(20), "copy_1GiB_GBs": round(probe_copy_bandwidth(1 << 30, 5), 1)}
+        res = {"lb_hbm": lb_hbm_boxes(20), "batch256_d2q9_f16": batch_rate(20),
+               "copy_1GiB_GBs": round(probe_copy_bandwidth(1 << 30, 5), 1)}
         print(json.dumps(res), flush=True)
         return
     storage = STORAGE[a.storage]
@@ -674,7 +675,48 @@ def extra_workloads(a):
           "MLUPS_graph_replay": round(cells * 2000 / wall_g / 1e6, 1),
           "lb_us": round(lb_ms * 1e3, 3),
           "effective_GBs": round(72 * cells / (lb_ms * 1e-3) / 1e9, 1)}
-    return {"d2q9_1024x512_coupled": d2, "lb_hbm": lb_hbm_boxes(100)}
+    return {"d2q9_1024x512_coupled": d2, "batch256_d2q9_f16": batch_rate(500),
+            "lb_hbm": lb_hbm_boxes(100)}
+
+
+def batch_rate(steps):
+    """The 256-droplet batch of uneven 2D boxes (the time-to-equilibrium
+    draws, seed 3) in one handle, fp16 storage: coupled steps per second and
+    the lattice kernel's per-launch duration from the events its dispatch
+    marks.  Its two population copies (about 470 MB) exceed the 256 MB
+    last-level cache, so the GB/s is an HBM figure."""
+    import torch
+    import workloads as wl
+    from paper_2503_20605_amd import STORAGE, Solver, params_from
+    draws = wl.batch_draws(256, seed=3)
+    s = Solver([params_from(w.params) for w in draws], [w.nodes for w in draws], storage=STORAGE["f16"])
+    for d, w in enumerate(draws):
+        s.set_node_respacing(d, w.params.respace)
+    v, _ = s.autotune(steps=16)
+    s.set_graph_steps(64)
+    s.step(130)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    wall_g = time.perf_counter() - t0
+    s.set_timing(True)
+    s.step(steps + 1)
+    lb_ms, step_ms = s.last_timing()
+    s.set_timing(False)
+    status = max(s.diagnostics(d)["status"] for d in range(len(draws)))
+    s.close()
+    cells = sum(w.params.nx * w.params.ny for w in draws)
+    bpc = bytes_per_cell(2, 1)
+    gbs = bpc * cells / (lb_ms * 1e-3) / 1e9
+    name = lb_kernel_name(2, 1, v, one=0)
+    return {"workload": "batch256_seed3_d2q9_f16", "droplets": len(draws), "cells": cells,
+            "working_set_MB": round(bpc * cells / 1e6, 1), "lb_variant": v, "block_order": LB_ORDER[v // 16],
+            "MLUPS_graph_replay": round(cells * steps / wall_g / 1e6, 1),
+            "step_us_events": round(step_ms * 1e3, 2), "lb_us": round(lb_ms * 1e3, 2),
+            "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(name, "batch256_seed3_d2q9_f16", LB_ORDER[v // 16]),
+            "status": status}
 
 
 def lb_hbm_boxes(steps):
