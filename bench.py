@@ -623,7 +623,8 @@ def main():
             out["extra"] = extra_workloads(a)
     if not a.no_cpu and not a.profile_only:
         log("CPU oracle baseline")
-        n1, nn = (1, 4) if dim == 3 else (20, 200)
+        # about 10 s of oracle work on one thread and 10 s on all of them
+        n1, nn = (4, 40) if dim == 3 else (200, 2000)
         out["cpu_baseline"] = cpu_baseline(W, n1, nn)
     print(json.dumps(out), flush=True)
 
