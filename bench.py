@@ -142,6 +142,9 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="the ten-run 1024x512 sweep (tau 0.6/1.0 x theta_eq 30-150 deg), 50000 steps "
                          "each: measured angle and contact radius at the end of every run")
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="only the FP64 oracle on the host: the oracle-sized 2D and 3D cases, one thread "
+                         "and all threads")
     ap.add_argument("--hbm-probe", action="store_true",
                     help="only the lattice kernel alone on the boxes far above the last-level "
                          "cache and the copy probe (short; used for hardware-counter runs)")
@@ -482,8 +485,25 @@ def cpu_baseline(W, steps_one, steps_all):
         "nproc": os.cpu_count(), "cpus_available": affinity, "cpu_model": cpu_model()}
 
 
+def cpu_configs(a):
+    """The FP64 oracle alone, on the host, on one thread and on all: the
+    128x64 D2Q9 droplet run in full (2000 steps), the 1024x512 D2Q9 sweep
+    point over its first 500 steps, and the 64x64x32 D3Q19 copy of the 3D
+    workload over 1000 steps.  No GPU work."""
+    import workloads as wl
+    out = {}
+    for W, n in ((wl.droplet_2d_small(), 2000), (wl.droplet_2d_large(run=a.run), 500),
+                 (wl.droplet_3d(theta_eq_deg=90.0, small=True), 1000)):
+        log(f"oracle {W.name}, {n} steps")
+        out[W.name] = cpu_baseline(W, n, n)
+    print(json.dumps({"metric": "FP64 oracle MLUPS on the host", "configs": out}), flush=True)
+
+
 def main():
     a = parse()
+    if a.cpu_configs:
+        cpu_configs(a)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the droplet batch "
                                    "and the single-box path are not sharded across GPUs"}))
