@@ -328,15 +328,16 @@ int iblb_inside_mask(iblb_ctx *ctx, int droplet, uint8_t *d_mask);
  * z_cut or a negative flat_tol.  Synchronises the stream. */
 int iblb_contact_radius(iblb_ctx *ctx, int droplet, double z_cut, double flat_tol, double *out);
 
-/* With timing on, iblb_step() launches every step directly (no graph
- * replay) and launches each lattice kernel with a pair of HIP events that
- * its own dispatch marks at the kernel's start and end (the interval a
- * kernel-trace profiler reports for that dispatch); the stream is
- * synchronised every 256 steps to read them.  iblb_last_timing() gives the
- * average of those intervals and the average time of a whole step
- * (milliseconds, events around the call) over the last such call; the
- * call's final, field-storing step is left out of the kernel average.
- * Either output pointer may be NULL. */
+/* With timing on (on = n > 0), iblb_step() launches every step directly
+ * (no graph replay) and launches every n-th lattice kernel of a call, the
+ * first included, with a pair of HIP events that its own dispatch marks at
+ * the kernel's start and end (the interval a kernel-trace profiler reports
+ * for that dispatch); the stream is synchronised every 256 timed launches
+ * to read them.  on = 0 turns timing off; a negative on is EINVAL.
+ * iblb_last_timing() gives the average of those intervals and the average
+ * time of a whole step (milliseconds, events around the call) over the last
+ * such call; the call's final, field-storing step is left out of the kernel
+ * average.  Either output pointer may be NULL. */
 int iblb_set_timing(iblb_ctx *ctx, int on);
 int iblb_last_timing(const iblb_ctx *ctx, double *lb_ms_per_step, double *step_ms_per_step);
 

@@ -257,7 +257,9 @@ class Solver:
         return out[0], out[1], int(out[2])
 
     def set_timing(self, on):
-        self._chk(self.lib.iblb_set_timing(self.ctx, int(bool(on))))
+        """False / 0: off; True / 1: time every lattice launch; n > 1: every
+        n-th one (see iblb_set_timing)."""
+        self._chk(self.lib.iblb_set_timing(self.ctx, int(on)))
 
     def last_timing(self):
         """(lattice-kernel duration from events marked by its dispatch, whole

@@ -276,7 +276,7 @@ struct iblb_ctx {
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipGraphExec_t lexec = nullptr;                // lattice-only launches (time_lattice)
     int lexec_n = 0, lexec_p = 0;                  // its launch count and start parity
-    bool timing = false;
+    int timing = 0;  // 0: off; n: every n-th lattice launch of a call carries timing events
     double t_lb = 0.0, t_step = 0.0;
     std::vector<hipEvent_t> events;  // [0, 2): around a whole call; then pairs per timed lattice launch
     long long step = 0;
@@ -1171,15 +1171,18 @@ int iblb_step(iblb_ctx* c, int n_steps) {
         int pending = 0;
         HIPCHK(c, hipEventRecord(ev[0], c->stream));
         launch_spread(c, c->stream, c->cur, n_steps == 1);
-        for (int rem = n_steps; rem > 1; --rem) {
-            if (pending == kTimedChunk) {
+        for (int rem = n_steps, k = 0; rem > 1; --rem, ++k) {
+            // with a stride above one only every timing-th launch carries
+            // the events, so that they perturb the run less
+            const bool timed = k % c->timing == 0;
+            if (timed && pending == kTimedChunk) {
                 if ((rc = read_lb_events(c, pending, ms))) return rc;
                 lb += ms;
                 nlb += pending;
                 pending = 0;
             }
-            launch_step(c, c->stream, c->cur, false, 0, rem == 2, ev + 2 + 2 * pending);
-            ++pending;
+            launch_step(c, c->stream, c->cur, false, 0, rem == 2, timed ? ev + 2 + 2 * pending : nullptr);
+            if (timed) ++pending;
             c->cur ^= 1;
             c->step++;
         }
@@ -1543,7 +1546,8 @@ int iblb_contact_radius(iblb_ctx* c, int d, double z_cut, double flat_tol, doubl
 
 int iblb_set_timing(iblb_ctx* c, int on) {
     if (!c) return IBLB_EINVAL;
-    c->timing = on != 0;
+    if (on < 0) return fail(c, IBLB_EINVAL, "timing: the stride must be >= 0");
+    c->timing = on;
     return IBLB_OK;
 }
 
@@ -1649,8 +1653,8 @@ int iblb_autotune(iblb_ctx* c, int steps, const char* cache_path, int* chosen, d
     int rc = ensure_events(c, 2);
     if (rc) return rc;
     hipEvent_t* ev = c->events.data();
-    const bool was_timing = c->timing;
-    c->timing = false;
+    const int was_timing = c->timing;
+    c->timing = 0;
     double ms[kVariants];
     double best_ms = 1e300;
     for (int v = 0; v < kVariants; ++v) {

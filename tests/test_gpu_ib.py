@@ -174,24 +174,33 @@ def test_full_size_large_droplet_in_graph_configuration():
 
 
 def test_steps_split_over_calls_and_timing_mode():
-    """The step count split over calls of 1, 2, 3, 66 and 300 steps (graph
-    replays of 16 steps, direct launches, the forces of each call's first
-    step computed at its start), with the timed schedule on for the last
-    two calls (the last one reads its events in two chunks), reaches the
-    oracle's state after the same 372 steps; the lattice kernel's timed
-    duration is positive and shorter than a step."""
+    """The step count split over calls of 1, 2, 3, 66, 300 and 600 steps
+    (graph replays of 16 steps, direct launches, the forces of each call's
+    first step computed at its start), with the timed schedule on for the
+    last three calls (the 300-step call times every lattice launch and reads
+    its events in two chunks, the 600-step call every seventh), reaches the
+    oracle's state after the same 972 steps; the lattice kernel's timed
+    duration is positive and shorter than a step, and the sampled average
+    agrees with the full one."""
+    from paper_2503_20605_amd import IblbError
     W = wl.droplet_2d_small()
     s = gpu_solver([W.params], [W.nodes])
     s.set_graph_steps(16)
-    print("[ib] split calls 1+2+3+66+300", flush=True)
-    for k, n in enumerate((1, 2, 3, 66, 300)):
-        s.set_timing(k >= 3)
+    print("[ib] split calls 1+2+3+66+300+600", flush=True)
+    full = None
+    for k, n in enumerate((1, 2, 3, 66, 300, 600)):
+        s.set_timing({3: True, 4: 1, 5: 7}.get(k, False))
         s.step(n)
+        if k == 4:
+            full = s.last_timing()
     span, step = s.last_timing()
-    assert 0.0 < span < step
+    assert 0.0 < span < step and 0.0 < full[0] < full[1]
+    assert 0.5 * full[0] < span < 2.0 * full[0]
+    with pytest.raises(IblbError):
+        s.set_timing(-1)
     s.set_timing(False)
     g = collect(s, 0, 2)
-    r = o.run(W.params, W.nodes, 372)
+    r = o.run(W.params, W.nodes, 972)
     drho, du, dq = compare_fields(g, r, 2, "split-calls")
     assert drho <= 1e-5 and du <= 1e-5 and dq <= 1e-5
     assert np.max(np.abs(g["phi"] - r["phi"])) <= 1e-6 * max(1.0, np.max(np.abs(r["phi"])))
