@@ -684,7 +684,7 @@ def extra_workloads(a):
     s = Solver([params_from(p)], [W.nodes])
     v, _ = s.autotune(steps=130)
     s.step(200)
-    s.set_timing(True)
+    s.set_timing(TIMING_STRIDE)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.step(2000)
@@ -731,7 +731,7 @@ def batch_rate(steps):
     s.step(steps)
     torch.cuda.synchronize()
     wall_g = time.perf_counter() - t0
-    s.set_timing(True)
+    s.set_timing(TIMING_STRIDE)
     s.step(steps + 1)
     lb_ms, step_ms = s.last_timing()
     s.set_timing(False)
