@@ -1202,25 +1202,28 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restr
     __shared__ int sok[kChunk];
     __shared__ int lo[3], hi[3];
     const int4 ch = chunks[blockIdx.x];  // (droplet, first index into perm, count, -)
+    const int t = threadIdx.x, st = A.stride, count = ch.z;
+    // the chunk's vertices (positions and forces together) are fetched
+    // before the droplet's parameters are checked, not after them
+    double q[3] = {0.0, 0.0, 0.0};
+    float ph[3] = {0.f, 0.f, 0.f};
+    if (t < count) {
+        const int j = A.perm[ch.y + t];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            q[a] = A.pos[a * st + j];
+            ph[a] = A.phi[a * st + j];
+        }
+    }
     const DropDev& D = drops[ch.x];
     if (!D.active || D.force_mode != 0) return;
-    const int t = threadIdx.x, st = A.stride, count = ch.z;
     if (t < 3) {
         lo[t] = INT_MAX;
         hi[t] = INT_MIN;
     }
     __syncthreads();
     if (t < count) {
-        const int j = A.perm[ch.y + t];
         bool ok = true;
-        double q[3];
-        float ph[3];
-        // the force is fetched with the position, not after its check
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            q[a] = A.pos[a * st + j];
-            ph[a] = A.phi[a * st + j];
-        }
 #pragma unroll
         for (int a = 0; a < 3; ++a) ok = ok && coord_ok(q[a]);
         sok[t] = ok;
