@@ -408,7 +408,8 @@ def mlp_rate(a):
 def lb_only_rate(dim, nx, ny, nz, storage, steps):
     """Lattice kernel on a big box with no interface (every cell is a plain
     collide + stream), autotuned; its per-launch duration from the events its
-    dispatch marks, over `steps` timed steps."""
+    dispatch marks, over `steps` timed steps, and from graph replays of
+    back-to-back launches without events."""
     from paper_2503_20605_amd import Solver, make_params
     p = make_params(dim=dim, nx=nx, ny=ny, nz=nz, tau=0.8, wetting=False)
     s = Solver([p], None, storage=storage)
@@ -417,6 +418,9 @@ def lb_only_rate(dim, nx, ny, nz, storage, steps):
     s.step(steps + 1)
     lb_ms, _ = s.last_timing()
     s.set_timing(False)
+    # the same kernel replayed back to back from a graph of 64 launches, no
+    # events on any of them (median of three replays)
+    graph_ms = sorted(s.time_lattice(64) for _ in range(3))[1]
     cells = nx * ny * nz
     gbs = bytes_per_cell(dim, storage) * cells / (lb_ms * 1e-3) / 1e9
     s.close()
@@ -426,6 +430,8 @@ def lb_only_rate(dim, nx, ny, nz, storage, steps):
             "lb_us": round(lb_ms * 1e3, 2),
             "MLUPS": round(cells / (lb_ms * 1e-3) / 1e6, 1),
             "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "lb_us_graph": round(graph_ms * 1e3, 2),
+            "frac_graph": round(bytes_per_cell(dim, storage) * cells / (graph_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(lb_kernel_name(dim, storage, v),
                                         f"d{dim}q{9 if dim == 2 else 19}_{nx}x{ny}"
                                         + (f"x{nz}" if dim == 3 else "") + "_lattice_only",
