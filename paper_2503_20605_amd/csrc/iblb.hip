@@ -109,9 +109,13 @@ constexpr int kPlanePad = IBLB_PLANE_PAD;
 #define IBLB_CHUNK_BUDGET 640
 #endif
 
-// Band flags per lattice row: one byte per 16-cell strip, padded to a
-// multiple of four so that a row's flags start on a 32-bit boundary.
-int strips_of(int nx) { return (ceil_div(nx, kStrip) + 3) / 4 * 4; }
+// Band flags per lattice row: one byte per strip of Strip<dim>::n cells,
+// padded to a multiple of the strips of 64 cells so that a row's flags start
+// on a word boundary.
+int strips_of(int nx, int dim) {
+    const int n = dim == 2 ? Strip<2>::n : Strip<3>::n, w = dim == 2 ? Strip<2>::per64 : Strip<3>::per64;
+    return (ceil_div(nx, n) + w - 1) / w * w;
+}
 
 long long pop_stride(long long cells) {
     return (cells + kPopRound - 1) / kPopRound * kPopRound + kPopPad;
@@ -204,7 +208,7 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
         L.pop_elems += (long long)Q * L.fst[d];
         if (L.pop_elems >= (1LL << 40)) { err = "population arrays too large"; return false; }
         L.flag_off[d] = L.flag_bytes;
-        L.flag_bytes += (long long)nz * p.ny * strips_of(p.nx);
+        L.flag_bytes += (long long)nz * p.ny * strips_of(p.nx, dim);
         L.node_off[d] = L.ntot;
         L.ntot += nn[d];
         if (dim == 3) L.nchunks += nn[d];  // capacity: at worst one vertex per chunk
@@ -689,7 +693,7 @@ int reset_droplet(iblb_ctx* c, int d) {
     HIPCHK(c, hipMemsetAsync(c->ws + c->L.U + vo, 0, vb, c->stream));
     HIPCHK(c, hipMemsetAsync(c->ws + c->L.Fout + vo, 0, vb, c->stream));
     const iblb_params& p = c->params[d];
-    const size_t fb = (size_t)(c->dim == 3 ? p.nz : 1) * p.ny * strips_of(p.nx);
+    const size_t fb = (size_t)(c->dim == 3 ? p.nz : 1) * p.ny * strips_of(p.nx, c->dim);
     HIPCHK(c, hipMemsetAsync(band_flags(c, 0) + D.flag_off, 0, fb, c->stream));
     HIPCHK(c, hipMemsetAsync(band_flags(c, 1) + D.flag_off, 0, fb, c->stream));
     hipLaunchKernelGGL(k_fill_f32, dim3(ceil_div(D.ncell, kBlock)), dim3(kBlock), 0, c->stream,
@@ -809,7 +813,7 @@ int iblb_create(int n, const iblb_params* P, const int* nn, const int* nt, int s
         D.nx = p.nx;
         D.ny = p.ny;
         D.nz = c->dim == 3 ? p.nz : 1;
-        D.nstrip = strips_of(p.nx);
+        D.nstrip = strips_of(p.nx, c->dim);
         D.bcx = p.bc[0];
         D.bcy = p.bc[1];
         D.bcz = c->dim == 3 ? p.bc[2] : 0;

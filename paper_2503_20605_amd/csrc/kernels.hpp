@@ -30,8 +30,8 @@
 //
 // The force density F and the velocity U are dense per-cell arrays, but the
 // lattice kernel touches them only inside the interface band: the spreading
-// kernel raises a one-byte flag for every 16-cell x strip that receives a
-// tap, and only the cells of flagged strips read F, write U for the
+// kernel raises a one-byte flag for every x strip (8 cells in 2D, 16 in 3D,
+// see Strip) that receives a tap, and only the cells of flagged strips read F, write U for the
 // interpolation and clear F (where it is not zero already).  The spread F is accumulated in fixed point (64-bit integers of
 // 2^-40 force units, see fq_of), so its value does not depend on the order
 // in which the nodes' contributions arrive; a prescribed force field is kept
@@ -44,13 +44,27 @@
 #include <limits.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lattice.hpp"
 
 namespace iblb {
 
 constexpr int kBlock = 256;   // threads per block of every kernel
-constexpr int kStrip = 16;    // cells per band flag (a quarter of a wavefront)
-constexpr int kStripShift = 4;
+// Cells per band flag: 8 in 2D (an eighth of a wavefront), 16 in 3D (a
+// quarter).  The 16-bit 256-droplet 2D batch's lattice kernel took 121.8
+// against 128.2 us per launch with 8-cell strips, the 3D benchmark step
+// 255.9 against 255.0 us: 3D keeps 16.  A row's flags are padded to a
+// multiple of the strips of 64 cells, so that a tiled wavefront (64 cells of
+// one row, starting at a multiple of 64) finds its strips' flags in one
+// aligned word: Strip<2>::Word is 64 bits, Strip<3>::Word 32 bits.
+template <int DIM>
+struct Strip {
+    static constexpr int shift = DIM == 2 ? 3 : 4;
+    static constexpr int n = 1 << shift;
+    static constexpr int per64 = 64 >> shift;  // strips of 64 cells (bytes of a word)
+    using Word = typename std::conditional<per64 == 8, uint64_t, uint32_t>::type;
+};
 
 struct DropDev {
     int nx, ny, nz, nstrip;
@@ -260,17 +274,16 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
     // populations: loads return in order, so waiting for the flag then does
     // not wait for the populations, and a band wavefront's F loads overlap
     // them instead of following them
-    // A row's flags are padded to a multiple of four bytes, so a tiled
-    // wavefront (64 cells of one row, starting at a multiple of 64) finds
-    // its four strips' flags in one aligned 32-bit word.
-    const long long fi = D.flag_off + (long long)(z * ny + y) * D.nstrip + (x >> kStripShift);
+    // A tiled wavefront reads its strips' flags as one aligned word.
+    using SW = typename Strip<DIM>::Word;
+    constexpr int SPW = Strip<DIM>::per64;
+    const long long fi = D.flag_off + (long long)(z * ny + y) * D.nstrip + (x >> Strip<DIM>::shift);
     int flag;
     if constexpr (FLAT) {
         flag = D.force_mode == 1 ? 1 : (int)flags_all[fi];
     } else {
-        const uint32_t w = D.force_mode == 1 ? 0xffffffffu
-                                             : *reinterpret_cast<const uint32_t*>(flags_all + (fi & ~3LL));
-        flag = (int)((w >> (8 * (int)(fi & 3))) & 0xffu);
+        const SW w = D.force_mode == 1 ? ~SW(0) : *reinterpret_cast<const SW*>(flags_all + (fi & ~(long long)(SPW - 1)));
+        flag = (int)((w >> (8 * (int)(fi & (SPW - 1)))) & 0xffu);
     }
     // Populations move through buffer instructions (32-bit lane offsets,
     // base in scalar registers): one descriptor per opposite pair (i,
@@ -312,9 +325,9 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         band = flag != 0;
         forced = __builtin_amdgcn_ballot_w64(band) != 0;
         if constexpr (FLAT) {
-            if (flags_clr && (x & (kStrip - 1)) == 0) flags_clr[fi] = 0;
+            if (flags_clr && (x & (Strip<DIM>::n - 1)) == 0) flags_clr[fi] = 0;
         } else {
-            if (flags_clr && (x & 63) == 0) *reinterpret_cast<uint32_t*>(flags_clr + fi) = 0u;
+            if (flags_clr && (x & 63) == 0) *reinterpret_cast<SW*>(flags_clr + fi) = SW(0);
         }
     }
     if (band) {
@@ -740,7 +753,7 @@ __device__ __forceinline__ void spread_lane(const DropDev& D, const NodeArrays& 
                 fine = false;
         }
         if (!fine) atomicOr(status_d, 2);
-        flags_all[D.flag_off + row * D.nstrip + (ix >> kStripShift)] = 1;
+        flags_all[D.flag_off + row * D.nstrip + (ix >> Strip<DIM>::shift)] = 1;
     }
     if (want_dropped) {
 #pragma unroll
@@ -1288,7 +1301,7 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restr
                 else
                     fine = false;
             }
-            flags_all[D.flag_off + row * D.nstrip + (gx >> kStripShift)] = 1;
+            flags_all[D.flag_off + row * D.nstrip + (gx >> Strip<3>::shift)] = 1;
         }
         if (want_dropped) {
 #pragma unroll
@@ -1315,7 +1328,7 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restr
             const unsigned long long v = box[a * kBoxCells + c];
             if (v != 0) atomicAdd(Fq + a * D.ncell + cell, v);
         }
-        flags_all[D.flag_off + row * D.nstrip + (gx >> kStripShift)] = 1;
+        flags_all[D.flag_off + row * D.nstrip + (gx >> Strip<3>::shift)] = 1;
     }
 }
 
