@@ -109,12 +109,16 @@ constexpr int kPlanePad = IBLB_PLANE_PAD;
 #define IBLB_CHUNK_BUDGET 640
 #endif
 
-// Band flags per lattice row: one byte per strip of Strip<dim>::n cells,
-// padded to a multiple of the strips of 64 cells so that a row's flags start
-// on a word boundary.
-int strips_of(int nx, int dim) {
-    const int n = dim == 2 ? Strip<2>::n : Strip<3>::n, w = dim == 2 ? Strip<2>::per64 : Strip<3>::per64;
-    return (ceil_div(nx, n) + w - 1) / w * w;
+// Band flags per lattice row: one byte per strip of Strip<dim, storage>::n
+// cells, padded to a multiple of the strips of 64 cells so that a row's
+// flags start on a word boundary.
+int strip_shift(int dim, int storage) {
+    if (dim == 2) return storage == ST_F32 ? Strip<2, ST_F32>::shift : Strip<2, ST_F16>::shift;
+    return Strip<3, ST_F32>::shift;
+}
+int strips_of(int nx, int dim, int storage) {
+    const int sh = strip_shift(dim, storage), w = 64 >> sh;
+    return (ceil_div(nx, 1 << sh) + w - 1) / w * w;
 }
 
 long long pop_stride(long long cells) {
@@ -208,7 +212,7 @@ bool plan(int n, const iblb_params* P, const int* nn, const int* nt, int storage
         L.pop_elems += (long long)Q * L.fst[d];
         if (L.pop_elems >= (1LL << 40)) { err = "population arrays too large"; return false; }
         L.flag_off[d] = L.flag_bytes;
-        L.flag_bytes += (long long)nz * p.ny * strips_of(p.nx, dim);
+        L.flag_bytes += (long long)nz * p.ny * strips_of(p.nx, dim, storage);
         L.node_off[d] = L.ntot;
         L.ntot += nn[d];
         if (dim == 3) L.nchunks += nn[d];  // capacity: at worst one vertex per chunk
@@ -693,7 +697,7 @@ int reset_droplet(iblb_ctx* c, int d) {
     HIPCHK(c, hipMemsetAsync(c->ws + c->L.U + vo, 0, vb, c->stream));
     HIPCHK(c, hipMemsetAsync(c->ws + c->L.Fout + vo, 0, vb, c->stream));
     const iblb_params& p = c->params[d];
-    const size_t fb = (size_t)(c->dim == 3 ? p.nz : 1) * p.ny * strips_of(p.nx, c->dim);
+    const size_t fb = (size_t)(c->dim == 3 ? p.nz : 1) * p.ny * strips_of(p.nx, c->dim, c->storage);
     HIPCHK(c, hipMemsetAsync(band_flags(c, 0) + D.flag_off, 0, fb, c->stream));
     HIPCHK(c, hipMemsetAsync(band_flags(c, 1) + D.flag_off, 0, fb, c->stream));
     hipLaunchKernelGGL(k_fill_f32, dim3(ceil_div(D.ncell, kBlock)), dim3(kBlock), 0, c->stream,
@@ -813,7 +817,8 @@ int iblb_create(int n, const iblb_params* P, const int* nn, const int* nt, int s
         D.nx = p.nx;
         D.ny = p.ny;
         D.nz = c->dim == 3 ? p.nz : 1;
-        D.nstrip = strips_of(p.nx, c->dim);
+        D.nstrip = strips_of(p.nx, c->dim, c->storage);
+        D.sshift = strip_shift(c->dim, c->storage);
         D.bcx = p.bc[0];
         D.bcy = p.bc[1];
         D.bcz = c->dim == 3 ? p.bc[2] : 0;

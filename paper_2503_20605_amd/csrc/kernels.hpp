@@ -30,8 +30,8 @@
 //
 // The force density F and the velocity U are dense per-cell arrays, but the
 // lattice kernel touches them only inside the interface band: the spreading
-// kernel raises a one-byte flag for every x strip (8 cells in 2D, 16 in 3D,
-// see Strip) that receives a tap, and only the cells of flagged strips read F, write U for the
+// kernel raises a one-byte flag for every x strip (8 or 16 cells, see
+// Strip) that receives a tap, and only the cells of flagged strips read F, write U for the
 // interpolation and clear F (where it is not zero already).  The spread F is accumulated in fixed point (64-bit integers of
 // 2^-40 force units, see fq_of), so its value does not depend on the order
 // in which the nodes' contributions arrive; a prescribed force field is kept
@@ -51,16 +51,18 @@
 namespace iblb {
 
 constexpr int kBlock = 256;   // threads per block of every kernel
-// Cells per band flag: 8 in 2D (an eighth of a wavefront), 16 in 3D (a
-// quarter).  The 16-bit 256-droplet 2D batch's lattice kernel took 121.8
-// against 128.2 us per launch with 8-cell strips, the 3D benchmark step
-// 255.9 against 255.0 us: 3D keeps 16.  A row's flags are padded to a
-// multiple of the strips of 64 cells, so that a tiled wavefront (64 cells of
-// one row, starting at a multiple of 64) finds its strips' flags in one
-// aligned word: Strip<2>::Word is 64 bits, Strip<3>::Word 32 bits.
-template <int DIM>
+// Cells per band flag: 8 (an eighth of a wavefront) for 2D lattices in
+// 16-bit storage, 16 (a quarter) otherwise.  With 8-cell strips the fp16
+// 256-droplet 2D batch's lattice kernel took 121.8 against 128.2 us per
+// launch, while the fp32 1024x512 D2Q9 step took 13.68 against 13.48 us and
+// the 3D benchmark step 255.9 against 255.0 us.  A row's flags are padded to
+// a multiple of the strips of 64 cells, so that a tiled wavefront (64 cells
+// of one row, starting at a multiple of 64) finds its strips' flags in one
+// aligned word (64 bits for 8-cell strips, 32 for 16-cell ones).  The node
+// kernels take the width from the droplet record (DropDev::sshift).
+template <int DIM, int S>
 struct Strip {
-    static constexpr int shift = DIM == 2 ? 3 : 4;
+    static constexpr int shift = (DIM == 2 && S != ST_F32) ? 3 : 4;
     static constexpr int n = 1 << shift;
     static constexpr int per64 = 64 >> shift;  // strips of 64 cells (bytes of a word)
     using Word = typename std::conditional<per64 == 8, uint64_t, uint32_t>::type;
@@ -68,6 +70,7 @@ struct Strip {
 
 struct DropDev {
     int nx, ny, nz, nstrip;
+    int sshift;           // log2 of the cells per band flag (see Strip)
     int bcx, bcy, bcz, ncell;
     long long f_off;      // element offset of the populations (Q arrays, fst apart)
     long long c_off;      // cell offset; vector arrays start at dim * c_off
@@ -275,9 +278,9 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
     // not wait for the populations, and a band wavefront's F loads overlap
     // them instead of following them
     // A tiled wavefront reads its strips' flags as one aligned word.
-    using SW = typename Strip<DIM>::Word;
-    constexpr int SPW = Strip<DIM>::per64;
-    const long long fi = D.flag_off + (long long)(z * ny + y) * D.nstrip + (x >> Strip<DIM>::shift);
+    using SW = typename Strip<DIM, S>::Word;
+    constexpr int SPW = Strip<DIM, S>::per64;
+    const long long fi = D.flag_off + (long long)(z * ny + y) * D.nstrip + (x >> Strip<DIM, S>::shift);
     int flag;
     if constexpr (FLAT) {
         flag = D.force_mode == 1 ? 1 : (int)flags_all[fi];
@@ -325,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(const DropDev* __restrict__ drops
         band = flag != 0;
         forced = __builtin_amdgcn_ballot_w64(band) != 0;
         if constexpr (FLAT) {
-            if (flags_clr && (x & (Strip<DIM>::n - 1)) == 0) flags_clr[fi] = 0;
+            if (flags_clr && (x & (Strip<DIM, S>::n - 1)) == 0) flags_clr[fi] = 0;
         } else {
             if (flags_clr && (x & 63) == 0) *reinterpret_cast<SW*>(flags_clr + fi) = SW(0);
         }
@@ -753,7 +756,7 @@ __device__ __forceinline__ void spread_lane(const DropDev& D, const NodeArrays& 
                 fine = false;
         }
         if (!fine) atomicOr(status_d, 2);
-        flags_all[D.flag_off + row * D.nstrip + (ix >> Strip<DIM>::shift)] = 1;
+        flags_all[D.flag_off + row * D.nstrip + (ix >> D.sshift)] = 1;
     }
     if (want_dropped) {
 #pragma unroll
@@ -1301,7 +1304,7 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restr
                 else
                     fine = false;
             }
-            flags_all[D.flag_off + row * D.nstrip + (gx >> Strip<3>::shift)] = 1;
+            flags_all[D.flag_off + row * D.nstrip + (gx >> D.sshift)] = 1;
         }
         if (want_dropped) {
 #pragma unroll
@@ -1328,7 +1331,7 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread3(const DropDev* __restr
             const unsigned long long v = box[a * kBoxCells + c];
             if (v != 0) atomicAdd(Fq + a * D.ncell + cell, v);
         }
-        flags_all[D.flag_off + row * D.nstrip + (gx >> Strip<3>::shift)] = 1;
+        flags_all[D.flag_off + row * D.nstrip + (gx >> D.sshift)] = 1;
     }
 }
 
